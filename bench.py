@@ -1,0 +1,231 @@
+"""Benchmark: one Levenberg-Marquardt linear solve of multigrid bundle adjustment
+on one MI355X.
+
+A step is one pass of the whole hot path on a fixed synthetic street-view
+scene (city grid, 2,000 cameras, 600,000 points, ~3.48M observations):
+residual and Jacobian, normal blocks, multigrid setup (near-nullspace QR,
+explicit level-0 Schur complement, Galerkin products, Lanczos, coarse
+factorization), PCG on the implicitly applied Schur complement to rtol 1e-6,
+and back-substitution. Inputs are resident in HBM before timing starts; the
+integer plan (layout, covisibility, aggregation) is built once beforehand, as
+in an LM loop over a fixed visibility graph, and timed separately.
+
+Prints ONE JSON line (the driver's contract); see the design doc for the fields.
+"""
+import argparse
+import hashlib
+import json
+import os
+import resource
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RCS solve s to rtol 1e-6 (MG vs block-Jacobi, FP32 vs FP64); matvec GB/s"
+HBM_PEAK_GBPS = 8000.0
+PROFILE_PMC = os.path.join(ROOT, "profiles", "k_schur_tiles_city2k_traffic.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def schur_bytes(n_obs, n_pt, n_cam, s):
+    """Algorithmic bytes of one implicit Schur product y = A x - F^T E C^-1 E^T F x:
+    F_o, E_o (24 s) + a 4-byte index per observation; C_p^-1 (6 s) + a 4-byte
+    offset per point; x, A (45 packed), y per camera (63 s)."""
+    return n_obs * (24 * s + 4) + n_pt * (6 * s + 4) + n_cam * 63 * s
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("step_kernels.hip", "common.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2007_01941_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    vals = {}
+    for line in open(PROFILE_PMC):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--scene", default="city2k")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2007_01941_amd as bamg
+    from scenes import make_scene
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    sc = make_scene(args.scene)
+    log(f"[bench] scene {sc.summary()} generated in {time.time() - t0:.1f}s")
+    T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    cams, pts, uv = T(sc.cams), T(sc.pts), T(sc.uv)
+    oc, op = T(sc.obs_cam, torch.int32), T(sc.obs_pt, torch.int32)
+    torch.cuda.synchronize()
+
+    base = dict(rtol=1e-6, max_iter=5000)
+    t0 = time.time()
+    plan = bamg.Plan(sc.n_cam, sc.n_pt, oc, op, bamg.Options(precond="mg", **base))
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    log(f"[bench] plan built in {plan_s:.2f}s, levels {plan.mg_levels()}, "
+        f"device bytes {plan.device_bytes / 2**30:.2f} GiB")
+
+    def run(opts, steps, warmup):
+        for _ in range(warmup):
+            plan.lm_step(cams, pts, uv, opts=opts)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stats = []
+        t_wall = time.time()
+        ev0.record()
+        for _ in range(steps):
+            dc, dp, st = plan.lm_step(cams, pts, uv, opts=opts)
+            stats.append(st)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.time() - t_wall
+        ms = ev0.elapsed_time(ev1) / steps
+        return ms, wall, stats, dc, dp
+
+    # ---- headline: MG, FP64
+    mg64 = bamg.Options(precond="mg", precision="fp64", **base)
+    ms, wall, stats, dc, dp = run(mg64, args.steps, args.warmup)
+    st = stats[-1]
+    log(f"[bench] MG FP64: {ms:.2f} ms/step (iters {st.iters}, rel_res {st.rel_res:.2e}, "
+        f"jac {st.t_jacobian_ms:.2f} setup {st.t_setup_ms:.2f} solve {st.t_solve_ms:.2f} ms)")
+    result = {
+        "metric": METRIC, "value": ms / 1e3, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{sc.name}: city-grid street-view scene, {sc.n_cam} cameras, "
+                               f"{sc.n_pt} points, {sc.n_obs} observations (seeded)",
+                   "precond": "multigrid", "precision": "fp64", "rtol": 1e-6, "lambda": 1e-4,
+                   "parallelism": "single GPU"},
+        "phases_ms": {"jacobian_and_blocks": st.t_jacobian_ms, "mg_setup": st.t_setup_ms,
+                      "pcg_and_backsub": st.t_solve_ms},
+        "pcg_iters": st.iters, "rel_res": st.rel_res, "levels": st.nodes,
+        "plan_s": plan_s,
+    }
+
+    # ---- dominant kernel: implicit Schur product, timed on the library's stream
+    stream = torch.cuda.current_stream()
+    x = torch.randn(sc.n_cam, 9, dtype=torch.float64, device=dev)
+    mat = {}
+    for prec, s in (("fp64", 8), ("fp32", 4)):
+        opts = bamg.Options(precond="bj", precision="fp64" if prec == "fp64" else "mixed", **base)
+        plan.prepare(cams, pts, uv, opts=opts)
+        for _ in range(3):
+            plan.schur_apply(x, "fp64" if prec == "fp64" else "mixed")
+        reps = 50
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            plan.schur_apply(x, "fp64" if prec == "fp64" else "mixed")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) / reps / 1e3
+        B = schur_bytes(sc.n_obs, sc.n_pt, sc.n_cam, s)
+        mat[prec] = {"s_per_apply": t, "algorithmic_bytes": B, "GBps": B / t / 1e9}
+        log(f"[bench] Schur product {prec}: {t * 1e6:.1f} us/apply, {B / t / 1e9:.0f} GB/s")
+    result["matvec"] = mat
+    traffic = read_traffic()
+    a = mat["fp64"]["GBps"]
+    result["roofline"] = {"kernel": "k_schur_tiles<double> (+ k_apply_A): implicit Schur product",
+                          "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                          "frac": a / HBM_PEAK_GBPS, "traffic": traffic}
+
+    # ---- comparison variants
+    if not args.no_variants:
+        var = {}
+        for name, opts in (("bj_fp64", bamg.Options(precond="bj", precision="fp64", **base)),
+                           ("mg_mixed", bamg.Options(precond="mg", precision="mixed", **base)),
+                           ("bj_mixed", bamg.Options(precond="bj", precision="mixed", **base))):
+            vms, _, vst, vdc, _ = run(opts, max(2, args.steps // 2), 1)
+            s2 = vst[-1]
+            var[name] = {"s_per_step": vms / 1e3, "pcg_iters": s2.iters, "refine_steps": s2.refine_steps,
+                         "rel_res": s2.rel_res, "phases_ms": {"jacobian_and_blocks": s2.t_jacobian_ms,
+                                                              "setup": s2.t_setup_ms,
+                                                              "solve": s2.t_solve_ms},
+                         "rel_diff_vs_mg_fp64": float(torch.linalg.norm(vdc - dc) / torch.linalg.norm(dc))}
+            log(f"[bench] {name}: {vms:.2f} ms/step, iters {s2.iters}, rel_res {s2.rel_res:.2e}")
+        result["variants"] = var
+
+    # ---- CPU baseline: the oracle on a bounded sample of the same workload
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(sc, st.iters, dc)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(sc, gpu_iters, dc_gpu):
+    """Time the oracle's phases on the host: full residual/Jacobian/normal
+    blocks on the whole scene, the multigrid hierarchy setup, and a few PCG
+    iterations; the solve time is extrapolated to the GPU's iteration count."""
+    import numpy as np
+
+    from oracle import multigrid as omg
+    from oracle import step as ostep
+
+    log("[bench] oracle CPU baseline ...")
+    r0 = resource.getrusage(resource.RUSAGE_SELF)
+    w0 = time.time()
+    t = time.time()
+    nrm = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    b = nrm.rhs()
+    t_jac = time.time() - t
+    t = time.time()
+    levels = ostep.hierarchy_for(nrm, sc.cams, sc.obs_cam, sc.obs_pt, omg.MGOptions())
+    t_setup = time.time() - t
+    sample_iters = 3
+    t = time.time()
+    res = omg.pcg(nrm.S_apply, lambda r: omg.vcycle(levels, r), b, 1e-30, max_iter=sample_iters)
+    t_iter = (time.time() - t) / sample_iters
+    # the oracle's FP64 residual of the GPU step (parity at full size)
+    gpu_res = float(np.linalg.norm(b - nrm.S_apply(dc_gpu.cpu().numpy().ravel())) / np.linalg.norm(b))
+    wall = time.time() - w0
+    r1 = resource.getrusage(resource.RUSAGE_SELF)
+    cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
+    est = t_jac + t_setup + gpu_iters * t_iter
+    log(f"[bench] oracle: jac {t_jac:.1f}s setup {t_setup:.1f}s {t_iter:.2f}s/iter -> "
+        f"{est:.1f}s per step at {gpu_iters} iterations; GPU step residual (oracle) {gpu_res:.2e}")
+    return {"value": est, "unit": "s", "cores": round(cpu / wall, 2), "kind": "oracle",
+            "sample": (f"oracle (numpy/scipy FP64) on the full {sc.name} scene: residual, Jacobian and "
+                       f"normal blocks ({t_jac:.1f}s), multigrid hierarchy setup ({t_setup:.1f}s), and "
+                       f"{sample_iters} MG-PCG iterations ({t_iter:.2f}s each), extrapolated to the "
+                       f"GPU's {gpu_iters} iterations"),
+            "host_cpus": os.cpu_count(), "gpu_step_rel_res_by_oracle": gpu_res}
+
+
+if __name__ == "__main__":
+    main()

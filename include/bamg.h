@@ -1,0 +1,219 @@
+/*
+ * bamg.h -- one Levenberg-Marquardt linear solve of bundle adjustment on an
+ * AMD Instinct MI355X (gfx950), with the unsmoothed-aggregation multigrid
+ * preconditioner of Konolige and Brown, "Multigrid for Bundle Adjustment".
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE memory (hipMalloc / torch CUDA tensors) unless
+ *     the comment says (host). Arrays are dense, row-major, FP64 unless noted.
+ *   - The caller owns every input and output buffer; the library never frees
+ *     caller memory. A plan owns the device memory it allocates for itself
+ *     (layout, per-step buffers, hierarchy) until ba_plan_destroy.
+ *   - `stream` is a hipStream_t passed as void*; all device work is enqueued on
+ *     it. Calls that return step results block until those results are ready
+ *     (the solver reads its convergence test back to the host).
+ *   - A negative status means nothing was written to the outputs; a message is
+ *     available from ba_last_error() on the calling thread. BA_NOT_CONVERGED
+ *     means the outputs hold the last iterate and the statistics are valid.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ *
+ * Camera parameters (9 per camera, the 9-parameter camera the paper uses,
+ * Sections 2.1 and 6; model as in the Bundle Adjustment in the Large data the
+ * paper cites in Section 4):  [w0 w1 w2 | t0 t1 t2 | f | k1 k2],
+ *   x_cam = R(w) X + t, p = -(x_cam.x, x_cam.y) / x_cam.z,
+ *   pixel = f (1 + k1 |p|^2 + k2 |p|^4) p,  residual f_o = pixel - u_o.
+ * Points: 3 world coordinates each. Observations: (camera, point, u in R^2).
+ */
+#ifndef BAMG_H
+#define BAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ba_plan ba_plan;
+
+typedef enum {
+  BA_OK = 0,
+  BA_NOT_CONVERGED = 1,   /* iteration limit reached: outputs = last iterate */
+  BA_ERR_ARG = -1,        /* bad argument (null pointer, size, option value) */
+  BA_ERR_INDEX = -2,      /* an observation index is out of range */
+  BA_ERR_STRUCTURE = -3,  /* point with < 2 views, camera with no view, duplicate (camera, point) */
+  BA_ERR_GEOMETRY = -4,   /* non-finite input, or a point at/behind an observing camera (x_cam.z >= 0) */
+  BA_ERR_NOT_SPD = -5,    /* a 3x3 point block, a 9x9/16x16 smoother block or the coarse matrix
+                             is not positive definite, or PCG broke down (p'Sp <= 0, r'z <= 0) */
+  BA_ERR_HIP = -7,        /* a HIP runtime call failed */
+  BA_ERR_LIMIT = -8       /* a documented size limit was exceeded */
+} ba_status;
+
+enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_MULTIGRID = 1 };
+enum { BA_FP64 = 0, BA_MIXED = 1 };
+enum { BA_OP_AUTO = 0, BA_OP_IMPLICIT = 1, BA_OP_EXPLICIT = 2 };
+
+typedef struct {
+  int32_t precond;          /* BA_PC_BLOCK_JACOBI (point block Jacobi, Section 2.2) or BA_PC_MULTIGRID */
+  int32_t precision;        /* BA_FP64, or BA_MIXED: FP32 Schur product and preconditioner inside
+                               FP64 iterative refinement; C^-1, coarse solve and outer residual FP64 */
+  double lambda;            /* D = lambda * diag(J^T J) (Marquardt damping), default 1e-4 */
+  double rtol;              /* stop when ||b - S dc||_2 <= rtol ||b||_2, default 1e-6 */
+  int32_t max_iter;         /* PCG iteration limit (per refinement step in BA_MIXED), default 2000 */
+  int32_t max_refine;       /* BA_MIXED: refinement steps, default 10 */
+  double inner_rtol;        /* BA_MIXED: relative tolerance of each FP32 inner solve, default 1e-3 */
+  int32_t agg_cap;          /* aggregate size cap, default 20 (Section 3.2) */
+  int32_t cheb_degree;      /* Chebyshev steps per pre/post smoothing, default 2 (Section 3.4) */
+  int32_t lanczos_steps;    /* operator applications for lambda_max, default 5 (Section 3.4) */
+  int32_t coarse_max_nodes; /* stop coarsening at this many nodes, default 128 */
+  int32_t max_levels;       /* default 12 */
+  double cheb_lo, cheb_hi;  /* Chebyshev interval as fractions of lambda_max: 0.3, 1.1 (Section 3.4) */
+  double min_coarsen_ratio; /* stop when a level keeps more than this fraction of nodes, 0.9 */
+  int32_t level0_op;        /* operator for level-0 smoothing and Lanczos (Section 3.6): BA_OP_AUTO
+                               picks the cheaper of the implicit product and the explicit S by
+                               bytes moved per application; PCG itself always uses the implicit form */
+  int32_t freeze_damping_in_grad; /* backward: 1 = treat D as a constant, 0 = differentiate D(x) */
+  int32_t check_every;      /* PCG: read the convergence flag back every N iterations, default 4 */
+  int32_t reserved[8];
+} ba_opts;
+
+typedef struct {            /* (host) */
+  int32_t iters;            /* PCG iterations (summed over refinement steps) */
+  int32_t refine_steps;     /* BA_MIXED: outer refinement steps */
+  int32_t levels;           /* multigrid levels (1 = direct solve on level 0) */
+  int32_t nodes[16];        /* nodes per level */
+  double rel_res;           /* final ||b - S dc|| / ||b|| (recursive residual; FP64 outer in MIXED) */
+  double t_jacobian_ms;     /* residual + Jacobian + normal blocks */
+  double t_setup_ms;        /* preconditioner numeric setup */
+  double t_solve_ms;        /* PCG (and refinement) + back-substitution */
+} ba_stats;
+
+/* Defaults listed above. (host) o. */
+ba_status ba_opts_default(ba_opts* o);
+
+/* Build the integer structure reused by every LM step on the same visibility:
+ * observation order, point tiles, the covisibility counts W = V V^T
+ * (Section 3.2), greedy aggregation (Algorithm 2) on every level and the
+ * block patterns of the coarse operators. Depends only on which camera sees
+ * which point, never on parameter values.
+ *   obs_cam, obs_pt: [n_obs] int32 device arrays, any order.
+ *   Errors: BA_ERR_INDEX, BA_ERR_STRUCTURE, BA_ERR_LIMIT (n_obs >= 2^31, a
+ *   point seen by more than 65535 cameras), BA_ERR_HIP.
+ *   *out (host) receives the plan. */
+ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32_t* obs_cam,
+                         const int32_t* obs_pt, const ba_opts* o, void* stream, ba_plan** out);
+
+void ba_plan_destroy(ba_plan* p);
+
+/* Device bytes held by the plan (host). */
+size_t ba_plan_bytes(const ba_plan* p);
+
+/* One LM step (Section 2.1): solve (J^T J + D) delta = -J^T f for
+ * delta = [delta_cam; delta_pt] by PCG on the Schur complement
+ * S = A - F^T E C^-1 E^T F applied implicitly (Section 3.6), preconditioned by
+ * block Jacobi or the multigrid V-cycle (Algorithm 1), then back-substitution
+ * delta_pt = -C^-1 (g_p + E^T F delta_cam).
+ *   cams [n_cam][9], pts [n_pt][3], uv [n_obs][2] (observation order as given
+ *   to ba_plan_create); D: optional explicit damping diagonal [9 n_cam + 3 n_pt]
+ *   (camera entries first), NULL for D = lambda diag(J^T J).
+ *   Outputs delta_cam [n_cam][9], delta_pt [n_pt][3]; st (host) may be NULL. */
+ba_status ba_lm_step(ba_plan* p, const ba_opts* o, const double* cams, const double* pts,
+                     const double* uv, const double* D, double* delta_cam, double* delta_pt,
+                     ba_stats* st, void* stream);
+
+/* Gradient of a scalar loss L(delta) of one LM step with respect to the step's
+ * inputs, given gd_cam = dL/d delta_cam [n_cam][9] and gd_pt = dL/d delta_pt
+ * [n_pt][3]. With mu = H^-1 [gd_cam; gd_pt] (H = J^T J + D, solved with the same
+ * Schur system and preconditioner as the forward step, residual and Jacobian
+ * recomputed):  dL/du_o = J_o mu_o and
+ * dL/dx = -J^T J mu - sum_o sum_r Hess(pi_{o,r}) w_{o,r} (the second-order terms
+ * of the reprojection; with freeze_damping_in_grad = 0 the damping's own
+ * dependence on x is included). delta_cam/delta_pt are the forward outputs.
+ * Outputs g_cams [n_cam][9], g_pts [n_pt][3], g_uv [n_obs][2]. */
+ba_status ba_lm_step_backward(ba_plan* p, const ba_opts* o, const double* cams,
+                              const double* pts, const double* uv, const double* delta_cam,
+                              const double* delta_pt, const double* gd_cam, const double* gd_pt,
+                              double* g_cams, double* g_pts, double* g_uv, ba_stats* st,
+                              void* stream);
+
+/* ------------------------------------------------------------------------
+ * Stage-level entry points. ba_lm_step = ba_step_prepare + ba_step_solve.
+ * They expose each stage of the step so that it can be checked on its own.
+ * ---------------------------------------------------------------------- */
+
+/* Residual and Jacobian blocks per observation (Section 2.1):
+ * f [n_obs][2], F [n_obs][2][9] = d pi/d camera, E [n_obs][2][3] = d pi/d point,
+ * in the caller's observation order. Any output may be NULL. */
+ba_status ba_eval_jacobian(ba_plan* p, const double* cams, const double* pts, const double* uv,
+                           double* f, double* F, double* E, void* stream);
+
+/* Evaluate J, the damped normal blocks (Section 2.1), C^-1, the reduced
+ * right-hand side b = -g_c + W C^-1 g_p, the block-Jacobi blocks and, for
+ * BA_PC_MULTIGRID, the numeric multigrid setup (near-nullspace QR,
+ * Galerkin operators, smoothers, coarse factorization), keeping them in the
+ * plan for ba_step_solve / ba_schur_apply / ba_precond_apply. */
+ba_status ba_step_prepare(ba_plan* p, const ba_opts* o, const double* cams, const double* pts,
+                          const double* uv, const double* D, ba_stats* st, void* stream);
+
+/* PCG on S dc = b and back-substitution using the prepared step. */
+ba_status ba_step_solve(ba_plan* p, const ba_opts* o, double* delta_cam, double* delta_pt,
+                        ba_stats* st, void* stream);
+
+/* y = S x with the implicit product A x - F^T (E (C^-1 (E^T (F x))))
+ * (Section 3.6) of the prepared step. precision BA_FP64 or BA_MIXED (FP32
+ * operands and accumulation; x, y are still FP64 at this boundary).
+ * x, y: [n_cam][9]. */
+ba_status ba_schur_apply(ba_plan* p, int32_t precision, const double* x, double* y,
+                         void* stream);
+
+/* z = M r: one preconditioner application of the prepared step (block Jacobi,
+ * or one V-cycle of Algorithm 1 from a zero initial guess). [n_cam][9]. */
+ba_status ba_precond_apply(ba_plan* p, const ba_opts* o, int32_t precision, const double* r,
+                           double* z, void* stream);
+
+/* Reduced right-hand side b [n_cam][9], point blocks C^-1 [n_pt][3][3] and
+ * block-Jacobi blocks S_cc [n_cam][9][9] (before inversion) of the prepared
+ * step. Any output may be NULL. */
+ba_status ba_step_blocks(ba_plan* p, double* b, double* Cinv, double* Scc, void* stream);
+
+/* ---- multigrid hierarchy inspection (after ba_plan_create; numeric parts
+ * after ba_step_prepare with BA_PC_MULTIGRID). Sizes are (host) outputs. ---- */
+
+/* Number of levels and nodes per level (nodes: (host) array of >= 16). */
+ba_status ba_mg_levels(const ba_plan* p, int32_t* n_levels, int32_t* nodes);
+
+/* Aggregate id of every node of `level` (Algorithm 2; ids in creation order):
+ * agg [nodes(level)] int32 (device). Not defined on the coarsest level. */
+ba_status ba_mg_aggregates(const ba_plan* p, int32_t level, int32_t* agg);
+
+/* Covisibility counts W of `level` (Section 3.2; coarse levels
+ * W_{l+1} = Ahat^T W_l Ahat) in CSR with sorted columns, diagonal included:
+ * call with row_ptr == NULL to get *nnz (host); then row_ptr [nodes+1] int64,
+ * col [nnz] int32, val [nnz] int64 (device). */
+ba_status ba_mg_covisibility(const ba_plan* p, int32_t level, int64_t* nnz, int64_t* row_ptr,
+                             int32_t* col, int64_t* val);
+
+/* Numeric hierarchy of the prepared step, FP64:
+ *   what = 0: operator of `level` as dense [n][n] (n = nodes*bs; level 0 gives
+ *             the explicit S), only for n <= 16384;
+ *   what = 1: tentative prolongator blocks P [nodes][bs][16] of `level`;
+ *   what = 2: near-nullspace rows K [nodes][bs][16] of `level`;
+ *   what = 3: inverse smoother blocks D^-1 [nodes][bs][bs];
+ *   what = 4: lambda_max estimate of D^-1 S (1 value);
+ *   what = 5: coarsest level only: inverse of its operator, dense [n][n]. */
+ba_status ba_mg_level_data(const ba_plan* p, int32_t level, int32_t what, double* out,
+                           void* stream);
+
+/* Self-test of the FP64 matrix-core tile products the coarse factorization is
+ * built from: C += X Y^T (mode 0), C += X^T Y (mode 1), C += X Y (mode 2), with
+ * X, Y, C 16 x 16 row-major device arrays. Lets a test confirm the operand
+ * layout of the MFMA 16x16x4 FP64 instruction on the running GPU. */
+ba_status ba_selftest_tile_mma(const double* X, const double* Y, double* C, int32_t mode, void* stream);
+
+const char* ba_status_str(ba_status e);
+const char* ba_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BAMG_H */

@@ -1,0 +1,147 @@
+"""ctypes binding of libbamg.so (argument marshalling only).
+
+Every array argument is a torch tensor on the GPU; the library receives raw
+device pointers and the current HIP stream. Nothing here computes any part of
+the solve: if the shared library is missing, importing this module fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbamg.so")
+
+BA_OK, BA_NOT_CONVERGED = 0, 1
+PC_BLOCK_JACOBI, PC_MULTIGRID = 0, 1
+FP64, MIXED = 0, 1
+OP_AUTO, OP_IMPLICIT, OP_EXPLICIT = 0, 1, 2
+
+
+class BAError(RuntimeError):
+    def __init__(self, status, name, detail):
+        super().__init__(f"{name}: {detail}")
+        self.status = status
+        self.name = name
+
+
+class NotConverged(RuntimeWarning):
+    pass
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("precond", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("lam", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("max_refine", ctypes.c_int32),
+                ("inner_rtol", ctypes.c_double),
+                ("agg_cap", ctypes.c_int32), ("cheb_degree", ctypes.c_int32),
+                ("lanczos_steps", ctypes.c_int32), ("coarse_max_nodes", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32),
+                ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
+                ("min_coarsen_ratio", ctypes.c_double),
+                ("level0_op", ctypes.c_int32), ("freeze_damping_in_grad", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("levels", ctypes.c_int32), ("nodes", ctypes.c_int32 * 16),
+                ("rel_res", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
+                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class Options:
+    """Mirror of ba_opts (defaults as in ba_opts_default)."""
+    precond: str = "mg"              # "mg" | "bj"
+    precision: str = "fp64"          # "fp64" | "mixed"
+    lam: float = 1e-4
+    rtol: float = 1e-6
+    max_iter: int = 2000
+    max_refine: int = 10
+    inner_rtol: float = 1e-3
+    agg_cap: int = 20
+    cheb_degree: int = 2
+    lanczos_steps: int = 5
+    coarse_max_nodes: int = 128
+    max_levels: int = 12
+    cheb_lo: float = 0.3
+    cheb_hi: float = 1.1
+    min_coarsen_ratio: float = 0.9
+    level0_op: str = "auto"          # "auto" | "implicit" | "explicit"
+    freeze_damping_in_grad: bool = False
+    check_every: int = 4
+
+    def to_c(self) -> _Opts:
+        o = _Opts()
+        o.precond = {"bj": PC_BLOCK_JACOBI, "mg": PC_MULTIGRID}[self.precond]
+        o.precision = {"fp64": FP64, "mixed": MIXED}[self.precision]
+        o.lam, o.rtol, o.max_iter = self.lam, self.rtol, self.max_iter
+        o.max_refine, o.inner_rtol = self.max_refine, self.inner_rtol
+        o.agg_cap, o.cheb_degree, o.lanczos_steps = self.agg_cap, self.cheb_degree, self.lanczos_steps
+        o.coarse_max_nodes, o.max_levels = self.coarse_max_nodes, self.max_levels
+        o.cheb_lo, o.cheb_hi, o.min_coarsen_ratio = self.cheb_lo, self.cheb_hi, self.min_coarsen_ratio
+        o.level0_op = {"auto": OP_AUTO, "implicit": OP_IMPLICIT, "explicit": OP_EXPLICIT}[self.level0_op]
+        o.freeze_damping_in_grad = int(self.freeze_damping_in_grad)
+        o.check_every = self.check_every
+        return o
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(or python paper_2007_01941_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "ba_opts_default": [P],
+        "ba_plan_create": [I32, I32, I64, P, P, P, P, P],
+        "ba_plan_destroy": [P],
+        "ba_plan_bytes": [P],
+        "ba_lm_step": [P, P, P, P, P, P, P, P, P, P],
+        "ba_lm_step_backward": [P, P, P, P, P, P, P, P, P, P, P, P, P, P],
+        "ba_eval_jacobian": [P, P, P, P, P, P, P, P],
+        "ba_step_prepare": [P, P, P, P, P, P, P, P],
+        "ba_step_solve": [P, P, P, P, P, P],
+        "ba_schur_apply": [P, I32, P, P, P],
+        "ba_precond_apply": [P, P, I32, P, P, P],
+        "ba_step_blocks": [P, P, P, P, P],
+        "ba_mg_levels": [P, P, P],
+        "ba_mg_aggregates": [P, I32, P],
+        "ba_mg_covisibility": [P, I32, P, P, P, P],
+        "ba_mg_level_data": [P, I32, I32, P, P],
+        "ba_selftest_tile_mma": [P, P, P, I32, P],
+        "ba_status_str": [I32],
+        "ba_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int32
+    lib.ba_plan_destroy.restype = None
+    lib.ba_plan_bytes.restype = ctypes.c_size_t
+    lib.ba_status_str.restype = ctypes.c_char_p
+    lib.ba_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+LIB = _load()
+
+# The C ABI's exported symbols, as declared in include/bamg.h.
+EXPORTED = ["ba_opts_default", "ba_plan_create", "ba_plan_destroy", "ba_plan_bytes", "ba_lm_step",
+            "ba_lm_step_backward", "ba_eval_jacobian", "ba_step_prepare", "ba_step_solve",
+            "ba_schur_apply", "ba_precond_apply", "ba_step_blocks", "ba_mg_levels",
+            "ba_mg_aggregates", "ba_mg_covisibility", "ba_mg_level_data", "ba_selftest_tile_mma",
+            "ba_status_str", "ba_last_error"]
+
+
+def check(status: int, allow_not_converged=True):
+    if status == BA_OK:
+        return status
+    if status == BA_NOT_CONVERGED and allow_not_converged:
+        return status
+    name = LIB.ba_status_str(status).decode()
+    detail = LIB.ba_last_error().decode()
+    raise BAError(status, name, detail)

@@ -1,0 +1,379 @@
+// C ABI of the bamg library: plan lifetime, the LM step and its stages.
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+
+#include "kernels.hpp"
+
+namespace bamg {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+// PCG and refinement workspace of a plan.
+struct Scratch {
+  int n = 0;  // 9 * n_cam
+  DBuf<double> x, r, z, p, q, t, bref;
+  DBuf<float> fx, fr, fz, fp, fq, fb;
+  DBuf<double> partial;
+  DBuf<PcgScal> scal;
+  DBuf<double> dots;     // plain dot results
+  DBuf<double> pt_a, pt_b;
+  PcgScal* h_scal = nullptr;
+  void init(int ncam, int npt) {
+    n = 9 * ncam;
+    for (DBuf<double>* b : {&x, &r, &z, &p, &q, &t, &bref}) b->alloc(n);
+    for (DBuf<float>* b : {&fx, &fr, &fz, &fp, &fq, &fb}) b->alloc(n);
+    partial.alloc(RED_BLOCKS);
+    scal.alloc(2);
+    dots.alloc(8);
+    pt_a.alloc((size_t)3 * npt);
+    pt_b.alloc((size_t)3 * npt);
+    BA_HIP(hipMemset(scal.p, 0, 2 * sizeof(PcgScal)));
+    BA_HIP(hipHostMalloc((void**)&h_scal, 2 * sizeof(PcgScal), hipHostMallocDefault));
+  }
+  ~Scratch() {
+    if (h_scal) (void)hipHostFree(h_scal);
+  }
+};
+
+static int red_grid(int n) { return std::max(1, std::min(RED_BLOCKS, ceil_div(n, 256))); }
+
+static void check_errflag(ba_plan* P, hipStream_t s, const char* stage = "") {
+  uint32_t e = 0;
+  BA_HIP(hipMemcpyAsync(&e, P->errflag.p, sizeof(e), hipMemcpyDeviceToHost, s));
+  BA_HIP(hipStreamSynchronize(s));
+  if (e) BA_HIP(hipMemsetAsync(P->errflag.p, 0, sizeof(uint32_t), s));
+  BA_CHECK(!(e & ERRF_NONFINITE), BA_ERR_GEOMETRY, "non-finite camera, point, observation or residual");
+  BA_CHECK(!(e & ERRF_GEOMETRY), BA_ERR_GEOMETRY,
+           "a point lies at or behind an observing camera (x_cam.z >= 0)");
+  BA_CHECK(!(e & ERRF_NOT_SPD), BA_ERR_NOT_SPD, "%s: a block is not positive definite", stage);
+  BA_CHECK(!(e & ERRF_LIMIT), BA_ERR_LIMIT, "%s: a kernel capacity was exceeded", stage);
+}
+
+struct Timer {
+  hipEvent_t a, b;
+  hipStream_t s;
+  explicit Timer(hipStream_t st) : s(st) {
+    BA_HIP(hipEventCreate(&a));
+    BA_HIP(hipEventCreate(&b));
+    BA_HIP(hipEventRecord(a, s));
+  }
+  double ms() {
+    float t = 0;
+    BA_HIP(hipEventRecord(b, s));
+    BA_HIP(hipEventSynchronize(b));
+    BA_HIP(hipEventElapsedTime(&t, a, b));
+    return t;
+  }
+  ~Timer() {
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+  }
+};
+
+// ---------------------------------------------------------------- implicit S
+
+template <class T>
+static void schur_apply_dev(ba_plan* P, const T* x, T* y, const int* done, hipStream_t s);
+
+template <>
+void schur_apply_dev<double>(ba_plan* P, const double* x, double* y, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_A<double>, dim3(ceil_div(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam, P->A.p, x, y);
+  hipLaunchKernelGGL(k_schur_tiles<double>, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
+                     P->tile_coff.p, P->tile_cams.p, P->obs_slot.p, P->F.p, P->E.p, P->n_obs_pad, P->Cinv.p,
+                     x, y, done);
+}
+
+template <>
+void schur_apply_dev<float>(ba_plan* P, const float* x, float* y, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_A<float>, dim3(ceil_div(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam, P->A32.p, x, y);
+  hipLaunchKernelGGL(k_schur_tiles<float>, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
+                     P->tile_coff.p, P->tile_cams.p, P->obs_slot.p, P->F32.p, P->E32.p, P->n_obs_pad,
+                     P->Cinv32.p, x, y, done);
+}
+
+}  // namespace bamg
+
+#include "solver.cpp"
+
+using namespace bamg;
+
+#define BA_API_BEGIN try {
+#define BA_API_END                                                 \
+  }                                                                \
+  catch (const Fail& f) {                                          \
+    return f.st;                                                   \
+  }                                                                \
+  catch (const std::bad_alloc&) {                                  \
+    set_error("host out of memory");                               \
+    return BA_ERR_HIP;                                             \
+  }                                                                \
+  return BA_OK;
+
+extern "C" {
+
+ba_status ba_opts_default(ba_opts* o) {
+  if (!o) return BA_ERR_ARG;
+  std::memset(o, 0, sizeof(*o));
+  o->precond = BA_PC_MULTIGRID;
+  o->precision = BA_FP64;
+  o->lambda = 1e-4;
+  o->rtol = 1e-6;
+  o->max_iter = 2000;
+  o->max_refine = 10;
+  o->inner_rtol = 1e-3;
+  o->agg_cap = 20;
+  o->cheb_degree = 2;
+  o->lanczos_steps = 5;
+  o->coarse_max_nodes = 128;
+  o->max_levels = 12;
+  o->cheb_lo = 0.3;
+  o->cheb_hi = 1.1;
+  o->min_coarsen_ratio = 0.9;
+  o->level0_op = BA_OP_AUTO;
+  o->freeze_damping_in_grad = 0;
+  o->check_every = 4;
+  return BA_OK;
+}
+
+static void validate_opts(const ba_opts* o) {
+  BA_CHECK(o, BA_ERR_ARG, "opts is NULL");
+  BA_CHECK(o->precond == BA_PC_BLOCK_JACOBI || o->precond == BA_PC_MULTIGRID, BA_ERR_ARG, "bad precond");
+  BA_CHECK(o->precision == BA_FP64 || o->precision == BA_MIXED, BA_ERR_ARG, "bad precision");
+  BA_CHECK(o->lambda >= 0.0, BA_ERR_ARG, "lambda must be >= 0");
+  BA_CHECK(o->rtol > 0.0 && o->rtol < 1.0, BA_ERR_ARG, "rtol must be in (0, 1)");
+  BA_CHECK(o->max_iter >= 1, BA_ERR_ARG, "max_iter must be >= 1");
+  BA_CHECK(o->agg_cap >= 2, BA_ERR_ARG, "agg_cap must be >= 2");
+  BA_CHECK(o->cheb_degree >= 1 && o->cheb_degree <= 16, BA_ERR_ARG, "cheb_degree must be in [1, 16]");
+  BA_CHECK(o->lanczos_steps >= 1 && o->lanczos_steps <= 32, BA_ERR_ARG, "lanczos_steps must be in [1, 32]");
+  BA_CHECK(o->coarse_max_nodes >= 1, BA_ERR_ARG, "coarse_max_nodes must be >= 1");
+  BA_CHECK(o->max_levels >= 1 && o->max_levels <= 16, BA_ERR_ARG, "max_levels must be in [1, 16]");
+  BA_CHECK(o->cheb_hi > o->cheb_lo && o->cheb_lo > 0.0, BA_ERR_ARG, "bad Chebyshev interval");
+  BA_CHECK(o->check_every >= 1, BA_ERR_ARG, "check_every must be >= 1");
+  BA_CHECK(o->precision != BA_MIXED || (o->max_refine >= 1 && o->inner_rtol > 0.0 && o->inner_rtol < 1.0),
+           BA_ERR_ARG, "bad refinement options");
+}
+
+ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32_t* obs_cam,
+                         const int32_t* obs_pt, const ba_opts* o, void* stream, ba_plan** out) {
+  BA_API_BEGIN
+  BA_CHECK(out, BA_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  validate_opts(o);
+  BA_CHECK(n_cam >= 2 && n_pt >= 1 && n_obs >= 2, BA_ERR_ARG, "need n_cam >= 2, n_pt >= 1, n_obs >= 2");
+  BA_CHECK(n_obs < (int64_t)INT32_MAX - 1024, BA_ERR_LIMIT, "n_obs must be below 2^31");
+  BA_CHECK(obs_cam && obs_pt, BA_ERR_ARG, "observation index arrays are NULL");
+  hipStream_t s = (hipStream_t)stream;
+  ba_plan* P = new ba_plan();
+  try {
+    P->n_cam = n_cam;
+    P->n_pt = n_pt;
+    P->n_obs = n_obs;
+    P->n_obs_pad = (n_obs + 63) / 64 * 64;
+    P->errflag.alloc(1);
+    BA_HIP(hipMemsetAsync(P->errflag.p, 0, sizeof(uint32_t), s));
+    std::vector<int32_t> oc(n_obs), op(n_obs);
+    BA_HIP(hipMemcpyAsync(oc.data(), obs_cam, n_obs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BA_HIP(hipMemcpyAsync(op.data(), obs_pt, n_obs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BA_HIP(hipStreamSynchronize(s));
+    build_observation_layout(P, oc, op, s);
+    build_hierarchy(P, o, s);
+    allocate_step(P);
+    *out = P;
+  } catch (...) {
+    delete P;
+    throw;
+  }
+  BA_API_END
+}
+
+void ba_plan_destroy(ba_plan* p) {
+  if (!p) return;
+  delete p->scratch;
+  delete p;
+}
+
+size_t ba_plan_bytes(const ba_plan* P) {
+  if (!P) return 0;
+  return plan_bytes(P);
+}
+
+ba_status ba_eval_jacobian(ba_plan* P, const double* cams, const double* pts, const double* uv,
+                           double* f, double* F, double* E, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && cams && pts && uv, BA_ERR_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  eval_jacobian(P, cams, pts, uv, false, s);
+  hipLaunchKernelGGL(k_scatter_jacobian, dim3(ceil_div(P->n_obs, 256)), dim3(256), 0, s, (int)P->n_obs,
+                     P->obs_orig.p, P->n_obs_pad, P->F.p, P->E.p, P->fres.p, f, F, E);
+  BA_LAUNCH_CHECK();
+  BA_HIP(hipStreamSynchronize(s));
+  BA_API_END
+}
+
+ba_status ba_step_prepare(ba_plan* P, const ba_opts* o, const double* cams, const double* pts,
+                          const double* uv, const double* D, ba_stats* st, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && cams && pts && uv, BA_ERR_ARG, "null argument");
+  validate_opts(o);
+  prepare(P, o, cams, pts, uv, D, st, (hipStream_t)stream);
+  BA_API_END
+}
+
+ba_status ba_step_solve(ba_plan* P, const ba_opts* o, double* delta_cam, double* delta_pt,
+                        ba_stats* st, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && delta_cam && delta_pt, BA_ERR_ARG, "null argument");
+  validate_opts(o);
+  BA_CHECK(P->prepared, BA_ERR_ARG, "ba_step_prepare has not been called");
+  return solve(P, o, delta_cam, delta_pt, st, (hipStream_t)stream);
+  BA_API_END
+}
+
+ba_status ba_lm_step(ba_plan* P, const ba_opts* o, const double* cams, const double* pts,
+                     const double* uv, const double* D, double* delta_cam, double* delta_pt,
+                     ba_stats* st, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && cams && pts && uv && delta_cam && delta_pt, BA_ERR_ARG, "null argument");
+  validate_opts(o);
+  hipStream_t s = (hipStream_t)stream;
+  if (st) std::memset(st, 0, sizeof(*st));
+  prepare(P, o, cams, pts, uv, D, st, s);
+  return solve(P, o, delta_cam, delta_pt, st, s);
+  BA_API_END
+}
+
+ba_status ba_schur_apply(ba_plan* P, int32_t precision, const double* x, double* y, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && x && y, BA_ERR_ARG, "null argument");
+  BA_CHECK(P->prepared, BA_ERR_ARG, "ba_step_prepare has not been called");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = 9 * P->n_cam;
+  if (precision == BA_MIXED) {
+    BA_CHECK(P->have_mixed, BA_ERR_ARG, "step was prepared without BA_MIXED");
+    Scratch& W = *P->scratch;
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, n, x, W.fx.p);
+    schur_apply_dev<float>(P, W.fx.p, W.fq.p, nullptr, s);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, n, W.fq.p, y);
+  } else {
+    schur_apply_dev<double>(P, x, y, nullptr, s);
+  }
+  BA_LAUNCH_CHECK();
+  BA_HIP(hipStreamSynchronize(s));
+  BA_API_END
+}
+
+ba_status ba_precond_apply(ba_plan* P, const ba_opts* o, int32_t precision, const double* r,
+                           double* z, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && r && z, BA_ERR_ARG, "null argument");
+  validate_opts(o);
+  BA_CHECK(P->prepared, BA_ERR_ARG, "ba_step_prepare has not been called");
+  precond_apply_fp64boundary(P, o, precision, r, z, (hipStream_t)stream);
+  BA_HIP(hipStreamSynchronize((hipStream_t)stream));
+  BA_API_END
+}
+
+ba_status ba_step_blocks(ba_plan* P, double* b, double* Cinv, double* Scc, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P, BA_ERR_ARG, "null plan");
+  BA_CHECK(P->prepared, BA_ERR_ARG, "ba_step_prepare has not been called");
+  hipStream_t s = (hipStream_t)stream;
+  if (b) BA_HIP(hipMemcpyAsync(b, P->b.p, P->b.bytes(), hipMemcpyDeviceToDevice, s));
+  if (Scc) BA_HIP(hipMemcpyAsync(Scc, P->Scc.p, P->Scc.bytes(), hipMemcpyDeviceToDevice, s));
+  if (Cinv)
+    hipLaunchKernelGGL(k_unpack_cinv, dim3(ceil_div(P->n_pt, 256)), dim3(256), 0, s, P->n_pt, P->pt_orig.p,
+                       P->Cinv.p, Cinv);
+  BA_LAUNCH_CHECK();
+  BA_HIP(hipStreamSynchronize(s));
+  BA_API_END
+}
+
+ba_status ba_mg_levels(const ba_plan* P, int32_t* n_levels, int32_t* nodes) {
+  BA_API_BEGIN
+  BA_CHECK(P && n_levels, BA_ERR_ARG, "null argument");
+  *n_levels = (int32_t)P->levels.size();
+  if (nodes)
+    for (size_t l = 0; l < P->levels.size() && l < 16; ++l) nodes[l] = P->levels[l].n;
+  BA_API_END
+}
+
+ba_status ba_mg_aggregates(const ba_plan* P, int32_t level, int32_t* agg) {
+  BA_API_BEGIN
+  BA_CHECK(P && agg, BA_ERR_ARG, "null argument");
+  BA_CHECK(level >= 0 && level + 1 < (int)P->levels.size(), BA_ERR_ARG, "level has no aggregates");
+  const Level& L = P->levels[level];
+  BA_HIP(hipMemcpy(agg, L.agg.p, L.n * sizeof(int32_t), hipMemcpyDeviceToDevice));
+  BA_API_END
+}
+
+ba_status ba_mg_covisibility(const ba_plan* P, int32_t level, int64_t* nnz, int64_t* row_ptr,
+                             int32_t* col, int64_t* val) {
+  BA_API_BEGIN
+  BA_CHECK(P && nnz, BA_ERR_ARG, "null argument");
+  BA_CHECK(level >= 0 && level < (int)P->levels.size(), BA_ERR_ARG, "bad level");
+  const Level& L = P->levels[level];
+  *nnz = L.nnz;
+  if (row_ptr) BA_HIP(hipMemcpy(row_ptr, L.rowptr.p, (L.n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice));
+  if (col) BA_HIP(hipMemcpy(col, L.col.p, L.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice));
+  if (val) BA_HIP(hipMemcpy(val, L.wval.p, L.nnz * sizeof(int64_t), hipMemcpyDeviceToDevice));
+  BA_API_END
+}
+
+ba_status ba_mg_level_data(const ba_plan* P, int32_t level, int32_t what, double* out, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && out, BA_ERR_ARG, "null argument");
+  BA_CHECK(level >= 0 && level < (int)P->levels.size(), BA_ERR_ARG, "bad level");
+  BA_CHECK(P->inspectable_mg, BA_ERR_ARG, "no multigrid step has been prepared");
+  level_data(P, level, what, out, (hipStream_t)stream);
+  BA_API_END
+}
+
+ba_status ba_lm_step_backward(ba_plan* P, const ba_opts* o, const double* cams, const double* pts,
+                              const double* uv, const double* delta_cam, const double* delta_pt,
+                              const double* gd_cam, const double* gd_pt, double* g_cams, double* g_pts,
+                              double* g_uv, ba_stats* st, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && cams && pts && uv && delta_cam && delta_pt && gd_cam && gd_pt && g_cams && g_pts && g_uv,
+           BA_ERR_ARG, "null argument");
+  validate_opts(o);
+  return backward(P, o, cams, pts, uv, delta_cam, delta_pt, gd_cam, gd_pt, g_cams, g_pts, g_uv, st,
+                  (hipStream_t)stream);
+  BA_API_END
+}
+
+ba_status ba_selftest_tile_mma(const double* X, const double* Y, double* C, int32_t mode, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(X && Y && C && mode >= 0 && mode <= 2, BA_ERR_ARG, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, s, X, Y, C, mode);
+  BA_LAUNCH_CHECK();
+  BA_HIP(hipStreamSynchronize(s));
+  BA_API_END
+}
+
+const char* ba_status_str(ba_status e) {
+  switch (e) {
+    case BA_OK: return "BA_OK";
+    case BA_NOT_CONVERGED: return "BA_NOT_CONVERGED";
+    case BA_ERR_ARG: return "BA_ERR_ARG";
+    case BA_ERR_INDEX: return "BA_ERR_INDEX";
+    case BA_ERR_STRUCTURE: return "BA_ERR_STRUCTURE";
+    case BA_ERR_GEOMETRY: return "BA_ERR_GEOMETRY";
+    case BA_ERR_NOT_SPD: return "BA_ERR_NOT_SPD";
+    case BA_ERR_HIP: return "BA_ERR_HIP";
+    case BA_ERR_LIMIT: return "BA_ERR_LIMIT";
+  }
+  return "unknown status";
+}
+
+const char* ba_last_error(void) { return g_err; }
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// Shared definitions of the bamg library: status handling, device helpers,
+// and the plan structure. Everything here is CDNA4 (gfx950) HIP.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/bamg.h"
+
+namespace bamg {
+
+// ------------------------------------------------------------ errors
+
+void set_error(const char* fmt, ...);
+
+struct Fail {
+  ba_status st;
+};
+
+#define BA_HIP(call)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::bamg::set_error("%s:%d %s -> %s", __FILE__, __LINE__, #call,              \
+                        hipGetErrorString(e_));                                   \
+      throw ::bamg::Fail{BA_ERR_HIP};                                             \
+    }                                                                             \
+  } while (0)
+
+#define BA_CHECK(cond, status, ...)                                               \
+  do {                                                                            \
+    if (!(cond)) {                                                                \
+      ::bamg::set_error(__VA_ARGS__);                                             \
+      throw ::bamg::Fail{status};                                                 \
+    }                                                                             \
+  } while (0)
+
+#define BA_LAUNCH_CHECK() BA_HIP(hipGetLastError())
+
+// Device-side error flags (bit set in a device word, read back by the host).
+enum : uint32_t {
+  ERRF_GEOMETRY = 1u,     // point at or behind a camera
+  ERRF_NONFINITE = 2u,    // non-finite input or intermediate
+  ERRF_NOT_SPD = 4u,      // a block Cholesky pivot <= 0
+  ERRF_BREAKDOWN = 8u,    // PCG breakdown
+  ERRF_LIMIT = 16u,       // a kernel capacity was exceeded
+};
+
+// ------------------------------------------------------------ device memory
+
+// A device buffer owned by the plan.
+template <class T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    free();
+    n = count;
+    if (count) BA_HIP(hipMalloc(&p, count * sizeof(T)));
+  }
+  void free() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  size_t bytes() const { return n * sizeof(T); }
+  void upload(const std::vector<T>& h, hipStream_t s) {
+    alloc(h.size());
+    if (!h.empty()) BA_HIP(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  std::vector<T> download(hipStream_t s) const {
+    std::vector<T> h(n);
+    if (n) {
+      BA_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+      BA_HIP(hipStreamSynchronize(s));
+    }
+    return h;
+  }
+  ~DBuf() { free(); }
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) { free(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+};
+
+// ------------------------------------------------------------ small helpers
+
+// Packed symmetric storage of an n x n matrix: upper triangle row by row.
+__host__ __device__ constexpr int sym_index(int n, int i, int j) {
+  // requires i <= j
+  return i * n - i * (i - 1) / 2 + (j - i);
+}
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Tile geometry of the point-major observation layout.
+constexpr int TILE_OBS = 256;     // observations per tile (one per thread)
+constexpr int TILE_SLOTS = 96;    // cameras of a tile kept in LDS (others go to global atomics)
+
+// Block size of the MG levels above level 0 (16 near-nullspace columns, Section 3.3).
+constexpr int NS = 16;
+
+}  // namespace bamg

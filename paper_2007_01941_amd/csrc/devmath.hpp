@@ -1,0 +1,137 @@
+// Small device-side linear algebra and rotation helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace bamg {
+
+// sin(x)/x without a division by zero (no cancellation anywhere).
+__device__ __forceinline__ double sinc(double x) { return x == 0.0 ? 1.0 : sin(x) / x; }
+
+// R(w) = I + a [w]x + b [w]x^2 with a = sin(th)/th and
+// b = (1 - cos th)/th^2 = 1/2 (sin(th/2)/(th/2))^2 (half-angle form, no cancellation).
+// Also returns b (needed by the right Jacobian).
+__device__ __forceinline__ void rotation(const double w[3], double R[9], double* b_out) {
+  const double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  const double a = sinc(th);
+  const double h = sinc(0.5 * th);
+  const double b = 0.5 * h * h;
+  const double xx = w[0] * w[0], yy = w[1] * w[1], zz = w[2] * w[2];
+  const double xy = w[0] * w[1], xz = w[0] * w[2], yz = w[1] * w[2];
+  // [w]x^2 = w w^T - th^2 I
+  R[0] = 1.0 + b * (-yy - zz);
+  R[1] = -a * w[2] + b * xy;
+  R[2] = a * w[1] + b * xz;
+  R[3] = a * w[2] + b * xy;
+  R[4] = 1.0 + b * (-xx - zz);
+  R[5] = -a * w[0] + b * yz;
+  R[6] = -a * w[1] + b * xz;
+  R[7] = a * w[0] + b * yz;
+  R[8] = 1.0 + b * (-xx - yy);
+  if (b_out) *b_out = b;
+}
+
+// Right Jacobian of SO(3): R(w + d) = R(w) exp([J_r(w) d]x) + O(d^2),
+// J_r = I - b [w]x + c [w]x^2, b = (1 - cos th)/th^2, c = (th - sin th)/th^3.
+// Then d(R X)/dw = -R [X]x J_r.
+__device__ __forceinline__ void right_jacobian(const double w[3], double b, double J[9]) {
+  const double t2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  const double th = sqrt(t2);
+  double c;
+  if (th < 0.25) {
+    // sum_n (-1)^n th^2n / (2n+3)!
+    c = 1.0 / 6.0 + t2 * (-1.0 / 120.0 + t2 * (1.0 / 5040.0 + t2 * (-1.0 / 362880.0 + t2 * (1.0 / 39916800.0))));
+  } else {
+    c = (th - sin(th)) / (t2 * th);
+  }
+  const double xx = w[0] * w[0], yy = w[1] * w[1], zz = w[2] * w[2];
+  const double xy = w[0] * w[1], xz = w[0] * w[2], yz = w[1] * w[2];
+  J[0] = 1.0 + c * (-yy - zz);
+  J[1] = b * w[2] + c * xy;
+  J[2] = -b * w[1] + c * xz;
+  J[3] = -b * w[2] + c * xy;
+  J[4] = 1.0 + c * (-xx - zz);
+  J[5] = b * w[0] + c * yz;
+  J[6] = b * w[1] + c * xz;
+  J[7] = -b * w[0] + c * yz;
+  J[8] = 1.0 + c * (-xx - yy);
+}
+
+// Inverse right Jacobian: J_r^-1 = I + 1/2 [w]x + e [w]x^2,
+// e = 1/th^2 - cot(th/2) / (2 th); series 1/12 + th^2/720 + th^4/30240 + ... near 0.
+__device__ __forceinline__ void right_jacobian_inv(const double w[3], double J[9]) {
+  const double t2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  const double th = sqrt(t2);
+  double e;
+  if (th < 0.25) {
+    e = 1.0 / 12.0 + t2 * (1.0 / 720.0 + t2 * (1.0 / 30240.0 + t2 * (1.0 / 1209600.0 + t2 * (1.0 / 47900160.0))));
+  } else {
+    const double hh = 0.5 * th;
+    e = 1.0 / t2 - cos(hh) / (2.0 * th * sin(hh));
+  }
+  const double xx = w[0] * w[0], yy = w[1] * w[1], zz = w[2] * w[2];
+  const double xy = w[0] * w[1], xz = w[0] * w[2], yz = w[1] * w[2];
+  J[0] = 1.0 + e * (-yy - zz);
+  J[1] = -0.5 * w[2] + e * xy;
+  J[2] = 0.5 * w[1] + e * xz;
+  J[3] = 0.5 * w[2] + e * xy;
+  J[4] = 1.0 + e * (-xx - zz);
+  J[5] = -0.5 * w[0] + e * yz;
+  J[6] = -0.5 * w[1] + e * xz;
+  J[7] = 0.5 * w[0] + e * yz;
+  J[8] = 1.0 + e * (-xx - yy);
+}
+
+// In-place Cholesky of an n x n SPD matrix held row-major in `a` (lower factor
+// written to the lower triangle). Returns false if a pivot is <= 0 or not finite.
+template <int N, class T>
+__device__ __forceinline__ bool cholesky(T* a) {
+  for (int j = 0; j < N; ++j) {
+    T d = a[j * N + j];
+    for (int k = 0; k < j; ++k) d -= a[j * N + k] * a[j * N + k];
+    if (!(d > T(0))) return false;
+    const T l = sqrt(d);
+    a[j * N + j] = l;
+    const T il = T(1) / l;
+    for (int i = j + 1; i < N; ++i) {
+      T s = a[i * N + j];
+      for (int k = 0; k < j; ++k) s -= a[i * N + k] * a[j * N + k];
+      a[i * N + j] = s * il;
+    }
+  }
+  return true;
+}
+
+// Inverse of an SPD matrix from its Cholesky factor L (lower triangle of a):
+// inv = L^-T L^-1, written to `out` (full, row-major). `a` is destroyed.
+template <int N, class T>
+__device__ __forceinline__ void cholesky_inverse(T* a, T* out) {
+  // invert L in place (lower triangle)
+  for (int j = 0; j < N; ++j) {
+    a[j * N + j] = T(1) / a[j * N + j];
+    for (int i = j + 1; i < N; ++i) {
+      T s = 0;
+      for (int k = j; k < i; ++k) s -= a[i * N + k] * a[k * N + j];
+      a[i * N + j] = s / a[i * N + i];
+    }
+  }
+  // out = Linv^T Linv
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j <= i; ++j) {
+      T s = 0;
+      for (int k = i; k < N; ++k) s += a[k * N + i] * a[k * N + j];
+      out[i * N + j] = s;
+      out[j * N + i] = s;
+    }
+}
+
+// Wave-wide sum (64 lanes).
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+}  // namespace bamg

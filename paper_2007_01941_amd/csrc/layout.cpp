@@ -1,0 +1,315 @@
+// Plan construction: the integer structure of one visibility graph.
+//
+// Host part (once per visibility structure): validation, point-major order,
+// point reordering by lowest observing camera (so that a tile of consecutive
+// points touches few cameras), camera-major lists and tiles. Device part: the
+// covisibility counts, strength ordering and greedy aggregation of every
+// multigrid level (mg_plan_kernels.hip); the host then derives the block
+// patterns and Galerkin gather lists from the aggregates.
+#include <algorithm>
+#include <numeric>
+
+#include "kernels.hpp"
+
+namespace bamg {
+
+static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
+                                     const std::vector<int32_t>& op, hipStream_t s) {
+  const int n_cam = P->n_cam, n_pt = P->n_pt;
+  const int64_t n_obs = P->n_obs;
+  for (int64_t o = 0; o < n_obs; ++o) {
+    BA_CHECK(oc[o] >= 0 && oc[o] < n_cam, BA_ERR_INDEX, "observation %lld: camera index %d out of [0, %d)",
+             (long long)o, oc[o], n_cam);
+    BA_CHECK(op[o] >= 0 && op[o] < n_pt, BA_ERR_INDEX, "observation %lld: point index %d out of [0, %d)",
+             (long long)o, op[o], n_pt);
+  }
+  std::vector<int32_t> cnt(n_pt, 0), ccnt(n_cam, 0);
+  for (int64_t o = 0; o < n_obs; ++o) { ++cnt[op[o]]; ++ccnt[oc[o]]; }
+  int max_k = 0;
+  for (int p = 0; p < n_pt; ++p) {
+    BA_CHECK(cnt[p] >= 2, BA_ERR_STRUCTURE, "point %d has %d observation(s); at least 2 are required", p, cnt[p]);
+    max_k = std::max(max_k, cnt[p]);
+  }
+  BA_CHECK(max_k <= 65535, BA_ERR_LIMIT, "a point is seen by %d cameras (limit 65535)", max_k);
+  for (int c = 0; c < n_cam; ++c)
+    BA_CHECK(ccnt[c] >= 1, BA_ERR_STRUCTURE, "camera %d observes no point", c);
+  // point-major, stable in the caller's order, then each point's views by camera
+  std::vector<int64_t> off(n_pt + 1, 0);
+  for (int p = 0; p < n_pt; ++p) off[p + 1] = off[p] + cnt[p];
+  std::vector<int32_t> pm(n_obs);
+  {
+    std::vector<int64_t> cur(off.begin(), off.end() - 1);
+    for (int64_t o = 0; o < n_obs; ++o) pm[cur[op[o]]++] = (int32_t)o;
+  }
+  for (int p = 0; p < n_pt; ++p) {
+    auto b = pm.begin() + off[p], e = pm.begin() + off[p + 1];
+    std::sort(b, e, [&](int32_t x, int32_t y) { return oc[x] < oc[y]; });
+    for (auto it = b + 1; it < e; ++it)
+      BA_CHECK(oc[*it] != oc[*(it - 1)], BA_ERR_STRUCTURE,
+               "camera %d observes point %d more than once", oc[*it], p);
+  }
+  // reorder points by their lowest observing camera (stable)
+  std::vector<int32_t> key(n_pt);
+  for (int p = 0; p < n_pt; ++p) key[p] = oc[pm[off[p]]];
+  std::vector<int64_t> kstart(n_cam + 1, 0);
+  for (int p = 0; p < n_pt; ++p) ++kstart[key[p] + 1];
+  for (int c = 0; c < n_cam; ++c) kstart[c + 1] += kstart[c];
+  P->h_pt_orig.assign(n_pt, 0);
+  for (int p = 0; p < n_pt; ++p) P->h_pt_orig[kstart[key[p]]++] = p;
+  std::vector<int32_t> pt_new(n_pt);
+  for (int q = 0; q < n_pt; ++q) pt_new[P->h_pt_orig[q]] = q;
+  // observation arrays in the new order
+  P->h_obs_cam.resize(n_obs);
+  P->h_obs_pt.resize(n_obs);
+  P->h_obs_orig.resize(n_obs);
+  P->h_pt_off.assign(n_pt + 1, 0);
+  int64_t w = 0;
+  for (int q = 0; q < n_pt; ++q) {
+    const int p = P->h_pt_orig[q];
+    P->h_pt_off[q] = w;
+    for (int64_t k = off[p]; k < off[p + 1]; ++k) {
+      const int32_t o = pm[k];
+      P->h_obs_cam[w] = oc[o];
+      P->h_obs_pt[w] = q;
+      P->h_obs_orig[w] = o;
+      ++w;
+    }
+  }
+  P->h_pt_off[n_pt] = w;
+  std::vector<int32_t> rank(n_obs);
+  for (int64_t o = 0; o < n_obs; ++o) rank[P->h_obs_orig[o]] = (int32_t)o;
+  // camera-major lists of point-major observation indices (ascending)
+  P->h_cam_off.assign(n_cam + 1, 0);
+  for (int c = 0; c < n_cam; ++c) P->h_cam_off[c + 1] = P->h_cam_off[c] + ccnt[c];
+  P->h_cam_obs.resize(n_obs);
+  {
+    std::vector<int64_t> cur(P->h_cam_off.begin(), P->h_cam_off.end() - 1);
+    for (int64_t o = 0; o < n_obs; ++o) P->h_cam_obs[cur[P->h_obs_cam[o]]++] = (int32_t)o;
+  }
+  // tiles of whole points with <= TILE_OBS observations
+  std::vector<int32_t> t_obs{0}, t_pt{0};
+  {
+    int cur = 0;
+    for (int q = 0; q < n_pt; ++q) {
+      const int k = (int)(P->h_pt_off[q + 1] - P->h_pt_off[q]);
+      if (cur > 0 && cur + k > TILE_OBS) {
+        t_obs.push_back((int32_t)P->h_pt_off[q]);
+        t_pt.push_back(q);
+        cur = 0;
+      }
+      cur += k;
+    }
+    t_obs.push_back((int32_t)n_obs);
+    t_pt.push_back(n_pt);
+  }
+  const int n_tiles = (int)t_obs.size() - 1;
+  std::vector<int32_t> t_coff{0}, t_cams;
+  std::vector<uint32_t> slot(n_obs);
+  std::vector<int32_t> mark(n_cam, -1), slot_of(n_cam, 0);
+  int max_tc = 0;
+  for (int t = 0; t < n_tiles; ++t) {
+    std::vector<int32_t> cams;
+    for (int64_t o = t_obs[t]; o < t_obs[t + 1]; ++o) {
+      const int c = P->h_obs_cam[o];
+      if (mark[c] != t) { mark[c] = t; cams.push_back(c); }
+    }
+    std::sort(cams.begin(), cams.end());
+    BA_CHECK(cams.size() <= 65535, BA_ERR_LIMIT, "tile with too many cameras");
+    for (size_t i = 0; i < cams.size(); ++i) slot_of[cams[i]] = (int32_t)i;
+    for (int64_t o = t_obs[t]; o < t_obs[t + 1]; ++o)
+      slot[o] = (uint32_t)slot_of[P->h_obs_cam[o]] | ((uint32_t)(P->h_obs_pt[o] - t_pt[t]) << 16);
+    t_cams.insert(t_cams.end(), cams.begin(), cams.end());
+    t_coff.push_back((int32_t)t_cams.size());
+    max_tc = std::max(max_tc, (int)cams.size());
+  }
+  P->n_tiles = n_tiles;
+  P->max_tile_cams = max_tc;
+  P->max_pt_obs = max_k;
+  // upload
+  std::vector<int32_t> pt_off32(P->h_pt_off.begin(), P->h_pt_off.end());
+  std::vector<int32_t> cam_off32(P->h_cam_off.begin(), P->h_cam_off.end());
+  P->obs_cam.upload(P->h_obs_cam, s);
+  P->obs_pt.upload(P->h_obs_pt, s);
+  P->obs_orig.upload(P->h_obs_orig, s);
+  P->obs_rank.upload(rank, s);
+  P->pt_off.upload(pt_off32, s);
+  P->pt_orig.upload(P->h_pt_orig, s);
+  P->pt_new.upload(pt_new, s);
+  P->cam_off.upload(cam_off32, s);
+  P->cam_obs.upload(P->h_cam_obs, s);
+  P->tile_obs.upload(t_obs, s);
+  P->tile_pt.upload(t_pt, s);
+  P->tile_coff.upload(t_coff, s);
+  P->tile_cams.upload(t_cams, s);
+  P->obs_slot.upload(slot, s);
+  BA_HIP(hipStreamSynchronize(s));
+}
+
+static uint32_t read_err(ba_plan* P, hipStream_t s) {
+  uint32_t e = 0;
+  BA_HIP(hipMemcpyAsync(&e, P->errflag.p, sizeof(e), hipMemcpyDeviceToHost, s));
+  BA_HIP(hipStreamSynchronize(s));
+  return e;
+}
+
+// Per-level CSR helpers computed on the host from the sorted pattern.
+static void finish_level_pattern(Level& L, hipStream_t s) {
+  const int n = L.n;
+  std::vector<int32_t> diag(n), rowof(L.nnz), trans(L.nnz);
+  for (int i = 0; i < n; ++i) {
+    for (int64_t e = L.h_rowptr[i]; e < L.h_rowptr[i + 1]; ++e) {
+      rowof[e] = i;
+      if (L.h_col[e] == i) diag[i] = (int32_t)e;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    for (int64_t e = L.h_rowptr[i]; e < L.h_rowptr[i + 1]; ++e) {
+      const int j = L.h_col[e];
+      auto b = L.h_col.begin() + L.h_rowptr[j], en = L.h_col.begin() + L.h_rowptr[j + 1];
+      auto it = std::lower_bound(b, en, i);
+      trans[e] = (int32_t)(it - L.h_col.begin());
+    }
+  }
+  std::vector<int32_t> rp32(L.h_rowptr.begin(), L.h_rowptr.end());
+  L.rowptr32.upload(rp32, s);
+  L.diag_pos.upload(diag, s);
+  L.row_of.upload(rowof, s);
+  L.trans_pos.upload(trans, s);
+}
+
+// Covisibility of one level on the device (two passes: sizes, then entries),
+// then the row sort and strength order.
+template <class LaunchPass>
+static void build_covisibility(ba_plan* P, Level& L, LaunchPass launch, hipStream_t s) {
+  const int n = L.n;
+  DBuf<int32_t> row_nnz;
+  row_nnz.alloc(n);
+  L.wdiag.alloc(n);
+  launch(0, row_nnz.p, L.wdiag.p, (const int64_t*)nullptr, (int32_t*)nullptr, (int64_t*)nullptr);
+  BA_LAUNCH_CHECK();
+  std::vector<int32_t> h_nnz = row_nnz.download(s);
+  uint32_t e = read_err(P, s);
+  BA_CHECK(!(e & ERRF_LIMIT), BA_ERR_LIMIT, "a covisibility row exceeds %d entries", HASH_SLOTS * 3 / 4);
+  L.h_rowptr.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) L.h_rowptr[i + 1] = L.h_rowptr[i] + h_nnz[i];
+  L.nnz = L.h_rowptr[n];
+  L.rowptr.upload(L.h_rowptr, s);
+  L.col.alloc(L.nnz);
+  L.wval.alloc(L.nnz);
+  L.order.alloc(std::max<int64_t>(1, L.nnz - n));
+  launch(1, row_nnz.p, L.wdiag.p, L.rowptr.p, L.col.p, L.wval.p);
+  BA_LAUNCH_CHECK();
+  hipLaunchKernelGGL(k_row_sort, dim3(n), dim3(256), 0, s, L.rowptr.p, L.col.p, L.wval.p, L.wdiag.p,
+                     L.order.p, P->errflag.p);
+  BA_LAUNCH_CHECK();
+  e = read_err(P, s);
+  BA_CHECK(!(e & ERRF_LIMIT), BA_ERR_LIMIT, "a node is covisible with more than %d others", ROW_SORT_MAX - 1);
+  L.h_col = L.col.download(s);
+}
+
+static void aggregate_level(ba_plan* P, Level& L, int cap, hipStream_t s) {
+  const int n = L.n;
+  DBuf<int32_t> agg, nagg;
+  agg.alloc(n);
+  nagg.alloc(1);
+  const size_t lds = (size_t)n * 2 * sizeof(int);
+  if (lds <= 150 * 1024) {
+    hipLaunchKernelGGL(k_aggregate_lds, dim3(1), dim3(64), lds, s, n, L.rowptr.p, L.order.p, cap,
+                       agg.p, nagg.p);
+  } else {
+    DBuf<int32_t> size;
+    size.alloc(n);
+    hipLaunchKernelGGL(k_aggregate_global, dim3(1), dim3(64), 0, s, n, L.rowptr.p, L.order.p, cap,
+                       agg.p, size.p, nagg.p);
+    BA_HIP(hipStreamSynchronize(s));
+  }
+  BA_LAUNCH_CHECK();
+  std::vector<int32_t> hn = nagg.download(s);
+  L.h_agg = agg.download(s);
+  L.n_agg = hn[0];
+  L.agg = std::move(agg);
+}
+
+static void build_hierarchy(ba_plan* P, const ba_opts* o, hipStream_t s) {
+  P->levels.clear();
+  P->levels.reserve(std::max(1, o->max_levels));
+  P->levels.emplace_back();
+  {
+    Level& L0 = P->levels[0];
+    L0.n = P->n_cam;
+    L0.bs = 9;
+    build_covisibility(P, L0, [&](int pass, int32_t* nnz, int64_t* wd, const int64_t* rp, int32_t* col, int64_t* val) {
+      if (pass == 0)
+        hipLaunchKernelGGL(k_covis0<0>, dim3(L0.n), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->obs_pt.p,
+                           P->pt_off.p, P->obs_cam.p, nnz, wd, rp, col, val, P->errflag.p);
+      else
+        hipLaunchKernelGGL(k_covis0<1>, dim3(L0.n), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->obs_pt.p,
+                           P->pt_off.p, P->obs_cam.p, nnz, wd, rp, col, val, P->errflag.p);
+    }, s);
+    finish_level_pattern(L0, s);
+  }
+  for (;;) {
+    const int l = (int)P->levels.size() - 1;
+    Level& L = P->levels[l];
+    if (L.n <= o->coarse_max_nodes || (int)P->levels.size() >= o->max_levels) break;
+    aggregate_level(P, L, o->agg_cap, s);
+    if (L.n_agg > o->min_coarsen_ratio * L.n) {
+      L.n_agg = 0;
+      L.agg.free();
+      L.h_agg.clear();
+      break;
+    }
+    // members of every aggregate, ascending
+    std::vector<int32_t> aptr(L.n_agg + 1, 0), amem(L.n), apos(L.n);
+    for (int i = 0; i < L.n; ++i) ++aptr[L.h_agg[i] + 1];
+    for (int a = 0; a < L.n_agg; ++a) aptr[a + 1] += aptr[a];
+    {
+      std::vector<int32_t> cur(aptr.begin(), aptr.end() - 1);
+      for (int i = 0; i < L.n; ++i) { apos[i] = cur[L.h_agg[i]] - aptr[L.h_agg[i]]; amem[cur[L.h_agg[i]]++] = i; }
+    }
+    L.max_agg = 0;
+    for (int a = 0; a < L.n_agg; ++a) L.max_agg = std::max(L.max_agg, aptr[a + 1] - aptr[a]);
+    L.agg_ptr.upload(aptr, s);
+    L.agg_mem.upload(amem, s);
+    L.agg_pos.upload(apos, s);
+    P->levels.emplace_back();
+    Level& F = P->levels[l];
+    Level& C = P->levels[l + 1];
+    C.n = F.n_agg;
+    C.bs = NS;
+    build_covisibility(P, C, [&](int pass, int32_t* nnz, int64_t* wd, const int64_t* rp, int32_t* col, int64_t* val) {
+      if (pass == 0)
+        hipLaunchKernelGGL(k_covisL<0>, dim3(C.n), dim3(256), 0, s, F.agg_ptr.p, F.agg_mem.p, F.rowptr.p, F.col.p,
+                           F.wval.p, F.agg.p, nnz, wd, rp, col, val, P->errflag.p);
+      else
+        hipLaunchKernelGGL(k_covisL<1>, dim3(C.n), dim3(256), 0, s, F.agg_ptr.p, F.agg_mem.p, F.rowptr.p, F.col.p,
+                           F.wval.p, F.agg.p, nnz, wd, rp, col, val, P->errflag.p);
+    }, s);
+    finish_level_pattern(C, s);
+    // Galerkin gather lists: coarse entry (A, B) <- fine entries (i, j), agg(i)=A, agg(j)=B
+    std::vector<int32_t> cidx(F.nnz);
+    std::vector<int32_t> gptr(C.nnz + 1, 0);
+    for (int i = 0; i < F.n; ++i) {
+      const int A = F.h_agg[i];
+      for (int64_t e = F.h_rowptr[i]; e < F.h_rowptr[i + 1]; ++e) {
+        const int B = F.h_agg[F.h_col[e]];
+        auto b = C.h_col.begin() + C.h_rowptr[A], en = C.h_col.begin() + C.h_rowptr[A + 1];
+        auto it = std::lower_bound(b, en, B);
+        BA_CHECK(it != en && *it == B, BA_ERR_STRUCTURE, "internal: coarse pattern misses an entry");
+        cidx[e] = (int32_t)(it - C.h_col.begin());
+        ++gptr[cidx[e] + 1];
+      }
+    }
+    for (int64_t e = 0; e < C.nnz; ++e) gptr[e + 1] += gptr[e];
+    std::vector<int32_t> gfine(F.nnz);
+    {
+      std::vector<int32_t> cur(gptr.begin(), gptr.end() - 1);
+      for (int64_t e = 0; e < F.nnz; ++e) gfine[cur[cidx[e]]++] = (int32_t)e;
+    }
+    F.gal_ptr.upload(gptr, s);
+    F.gal_fine.upload(gfine, s);
+  }
+  BA_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace bamg

@@ -1,0 +1,214 @@
+// Multigrid V-cycle kernels (Algorithm 1 of Konolige and Brown, Chebyshev
+// smoothing of Section 3.4): block-sparse products with the explicit level
+// operators, point-block-Jacobi applications, the Chebyshev recurrence,
+// restriction R = P^T, prolongation and the dense coarse solve.
+// Every kernel takes the PCG `done` flag and returns at once when it is set.
+#include "kernels.hpp"
+
+namespace bamg {
+
+// y = S x for a block-sparse S (BS x BS blocks, CSR of blocks). One wave per
+// block row: lane (part, comp) accumulates component `comp` over the row's
+// blocks part, part + P, ... and the parts are summed through LDS.
+template <int BS, class T>
+__global__ __launch_bounds__(256) void k_bsr_spmv(int n, const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ col,
+                                                  const T* __restrict__ S, const T* __restrict__ x,
+                                                  T* __restrict__ y, const int* done) {
+  if (done && *done) return;
+  constexpr int PARTS = 64 / BS;
+  __shared__ T red[4][64];
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + wid;
+  const int part = lane / BS, comp = lane % BS;
+  T acc = 0;
+  if (row < n && part < PARTS) {
+    for (int e = rowptr[row] + part; e < rowptr[row + 1]; e += PARTS) {
+      const T* blk = S + (size_t)e * BS * BS + comp * BS;
+      const T* xv = x + (size_t)col[e] * BS;
+#pragma unroll
+      for (int k = 0; k < BS; ++k) acc += blk[k] * xv[k];
+    }
+  }
+  red[wid][lane] = acc;
+  __syncthreads();
+  if (row < n && lane < BS) {
+    T s = 0;
+#pragma unroll
+    for (int p = 0; p < PARTS; ++p) s += red[wid][p * BS + lane];
+    y[(size_t)row * BS + lane] = s;
+  }
+}
+
+// z = D^-1 r block by block (BS x BS inverse blocks), one thread per dof.
+template <int BS, class T>
+__global__ __launch_bounds__(256) void k_blockdiag(int n, const T* __restrict__ Dinv,
+                                                   const T* __restrict__ r, T* __restrict__ z,
+                                                   const int* done) {
+  if (done && *done) return;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * BS) return;
+  const int i = g / BS, a = g % BS;
+  const T* m = Dinv + (size_t)i * BS * BS + a * BS;
+  const T* rv = r + (size_t)i * BS;
+  T s = 0;
+#pragma unroll
+  for (int k = 0; k < BS; ++k) s += m[k] * rv[k];
+  z[g] = s;
+}
+
+// First Chebyshev step. mode 0 (pre-smoothing from x = 0, r = b):
+//   d = D^-1 b / theta; x = d; r = b.
+// mode 1 (post-smoothing from x, t = S x): r = b - t; d = D^-1 r / theta; x += d.
+template <int BS, class T>
+__global__ __launch_bounds__(256) void k_cheb_first(int n, int mode, const T* __restrict__ Dinv,
+                                                    const T* __restrict__ b, const T* __restrict__ t,
+                                                    T* __restrict__ r, T* __restrict__ d,
+                                                    T* __restrict__ x, T inv_theta, const int* done) {
+  if (done && *done) return;
+  __shared__ T rs[256];
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nodes_per_block = 256 / BS;
+  const int ln = threadIdx.x / BS, a = threadIdx.x % BS;
+  const int i = blockIdx.x * nodes_per_block + ln;
+  const bool act = ln < nodes_per_block && i < n;
+  (void)g;
+  if (act) {
+    const size_t k = (size_t)i * BS + a;
+    const T rv = mode == 0 ? b[k] : b[k] - t[k];
+    rs[ln * BS + a] = rv;
+    r[k] = rv;
+  }
+  __syncthreads();
+  if (!act) return;
+  const T* m = Dinv + (size_t)i * BS * BS + a * BS;
+  T s = 0;
+#pragma unroll
+  for (int k2 = 0; k2 < BS; ++k2) s += m[k2] * rs[ln * BS + k2];
+  const size_t k = (size_t)i * BS + a;
+  const T dv = s * inv_theta;
+  d[k] = dv;
+  x[k] = mode == 0 ? dv : x[k] + dv;
+}
+
+// Later Chebyshev steps: r -= t (t = S d); d = c1 d + c2 D^-1 r; x += d.
+template <int BS, class T>
+__global__ __launch_bounds__(256) void k_cheb_next(int n, const T* __restrict__ Dinv, const T* __restrict__ t,
+                                                   T* __restrict__ r, T* __restrict__ d, T* __restrict__ x,
+                                                   T c1, T c2, const int* done) {
+  if (done && *done) return;
+  __shared__ T rs[256];
+  const int nodes_per_block = 256 / BS;
+  const int ln = threadIdx.x / BS, a = threadIdx.x % BS;
+  const int i = blockIdx.x * nodes_per_block + ln;
+  const bool act = ln < nodes_per_block && i < n;
+  if (act) {
+    const size_t k = (size_t)i * BS + a;
+    const T rv = r[k] - t[k];
+    rs[ln * BS + a] = rv;
+    r[k] = rv;
+  }
+  __syncthreads();
+  if (!act) return;
+  const T* m = Dinv + (size_t)i * BS * BS + a * BS;
+  T s = 0;
+#pragma unroll
+  for (int k2 = 0; k2 < BS; ++k2) s += m[k2] * rs[ln * BS + k2];
+  const size_t k = (size_t)i * BS + a;
+  const T dv = c1 * d[k] + c2 * s;
+  d[k] = dv;
+  x[k] += dv;
+}
+
+// Restriction b_c[a] = sum_{i in a} P_i^T (r_i - t_i) (t optional: the last
+// residual update of the pre-smoother is fused here). One thread per (aggregate, m).
+template <int BS, class T>
+__global__ __launch_bounds__(256) void k_restrict(int n_agg, const int32_t* __restrict__ agg_ptr,
+                                                  const int32_t* __restrict__ agg_mem,
+                                                  const T* __restrict__ P, const T* __restrict__ r,
+                                                  const T* __restrict__ t, T* __restrict__ bc,
+                                                  const int* done) {
+  if (done && *done) return;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_agg * NS) return;
+  const int a = g / NS, m = g % NS;
+  T s = 0;
+  for (int q = agg_ptr[a]; q < agg_ptr[a + 1]; ++q) {
+    const int i = agg_mem[q];
+    const T* Pi = P + (size_t)i * BS * NS + m;
+    const T* ri = r + (size_t)i * BS;
+    const T* ti = t ? t + (size_t)i * BS : nullptr;
+#pragma unroll
+    for (int k = 0; k < BS; ++k) s += Pi[k * NS] * (t ? ri[k] - ti[k] : ri[k]);
+  }
+  bc[g] = s;
+}
+
+// Prolongation x_i += P_i x_c[agg(i)], one thread per fine dof.
+template <int BS, class T>
+__global__ __launch_bounds__(256) void k_prolong(int n, const int32_t* __restrict__ agg,
+                                                 const T* __restrict__ P, const T* __restrict__ xc,
+                                                 T* __restrict__ x, const int* done) {
+  if (done && *done) return;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * BS) return;
+  const int i = g / BS, k = g % BS;
+  const T* Pi = P + (size_t)i * BS * NS + k * NS;
+  const T* xv = xc + (size_t)agg[i] * NS;
+  T s = 0;
+#pragma unroll
+  for (int m = 0; m < NS; ++m) s += Pi[m] * xv[m];
+  x[g] += s;
+}
+
+// Coarse solve x = inv b with the dense FP64 inverse (nd x nd, nd >= nv);
+// one wave per row, FP64 accumulation whatever the vector type.
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_solve(int nv, int nd, const double* __restrict__ inv,
+                                                     const T* __restrict__ b, T* __restrict__ x,
+                                                     const int* done) {
+  if (done && *done) return;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nv) return;
+  const double* m = inv + (size_t)row * nd;
+  double s = 0.0;
+  for (int k = lane; k < nv; k += 64) s += m[k] * (double)b[k];
+  s = wave_sum(s);
+  if (lane == 0) x[row] = (T)s;
+}
+
+// Lanczos start vector on dof i of a level: (splitmix64(seed ^ i) >> 11) 2^-53 - 1/2,
+// seed = 0x9E3779B97F4A7C15 ^ level (splitmix64: Steele, Lea and Flood 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+  uint64_t z = x + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_lanczos_start(int n, int level, double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t seed = 0x9E3779B97F4A7C15ull ^ (uint64_t)level;
+  v[i] = (double)(splitmix64(seed ^ (uint64_t)i) >> 11) * 0x1.0p-53 - 0.5;
+}
+
+// y = a x + b y, z optional second output
+__global__ void k_axpby2(int n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+// w = Dinv_av - alpha v - beta vp ; Dw = av - alpha u - beta up (Lanczos update)
+__global__ void k_lanczos_update(int n, const double* __restrict__ dinv_av, const double* __restrict__ av,
+                                 const double* __restrict__ v, const double* __restrict__ vp,
+                                 const double* __restrict__ u, const double* __restrict__ up, double alpha,
+                                 double beta, double* __restrict__ w, double* __restrict__ dw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  w[i] = dinv_av[i] - alpha * v[i] - beta * vp[i];
+  dw[i] = av[i] - alpha * u[i] - beta * up[i];
+}
+
+}  // namespace bamg

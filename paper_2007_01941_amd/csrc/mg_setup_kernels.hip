@@ -1,0 +1,461 @@
+// Multigrid numeric setup (Sections 3.1, 3.3, 3.4, 3.6 of Konolige and Brown):
+// camera near-nullspace, per-aggregate QR tentative prolongation, the explicit
+// level-0 Schur complement, Galerkin coarse operators P^T S P, smoother block
+// inverses, and the dense coarse factorization (the FP64 MFMA site).
+#include "kernels.hpp"
+
+namespace bamg {
+
+// ---------------------------------------------------------------- near-nullspace
+
+// K rows of camera c (9 x 16, row-major): columns 0..8 constant in each camera
+// parameter; 9..11 world translations tau_k (dt = -R e_k); 12..14 world
+// rotations (dw = -J_r(w)^-1 e_k); 15 world scale (dt = t). Section 3.1.
+__global__ void k_nullspace0(int n_cam, const double* __restrict__ cams, const double* __restrict__ campre,
+                             double* __restrict__ K) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_cam) return;
+  const double w[3] = {cams[c * 9], cams[c * 9 + 1], cams[c * 9 + 2]};
+  double Ji[9];
+  right_jacobian_inv(w, Ji);
+  const double* R = campre + (size_t)c * 24;
+  double* k = K + (size_t)c * 9 * NS;
+  for (int i = 0; i < 9 * NS; ++i) k[i] = 0.0;
+  for (int i = 0; i < 9; ++i) k[i * NS + i] = 1.0;
+  for (int j = 0; j < 3; ++j) {
+    for (int i = 0; i < 3; ++i) {
+      k[(3 + i) * NS + 9 + j] = -R[i * 3 + j];
+      k[i * NS + 12 + j] = -Ji[i * 3 + j];
+    }
+  }
+  for (int i = 0; i < 3; ++i) k[(3 + i) * NS + 15] = cams[c * 9 + 3 + i];
+}
+
+// ---------------------------------------------------------------- QR per aggregate
+
+// Householder QR (LAPACK conventions: beta = -sign(alpha) |x|, v_0 = 1) of the
+// stacked near-nullspace rows of one aggregate's members (ascending), thin Q,
+// then signs flipped so that diag(R) >= 0. One wave per aggregate; the
+// aggregate's matrix lives in dynamic LDS.
+__global__ __launch_bounds__(64) void k_qr_aggregates(int bs, const int32_t* __restrict__ agg_ptr,
+                                                      const int32_t* __restrict__ agg_mem,
+                                                      const double* __restrict__ Kf,
+                                                      double* __restrict__ P, double* __restrict__ Kc) {
+  extern __shared__ double sm[];
+  const int a = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int m0 = agg_ptr[a], nm = agg_ptr[a + 1] - m0;
+  const int rows = nm * bs;
+  double* A = sm;                    // rows x NS, row-major
+  double* Q = sm + rows * NS;        // rows x NS
+  __shared__ double tau[NS];
+  for (int idx = lane; idx < rows * NS; idx += 64) {
+    const int r = idx / NS, c = idx % NS;
+    const int mem = agg_mem[m0 + r / bs];
+    A[idx] = Kf[((size_t)mem * bs + (r % bs)) * NS + c];
+  }
+  __syncthreads();
+  const int ncol = rows < NS ? rows : NS;
+  for (int j = 0; j < ncol; ++j) {
+    double s = 0.0;
+    for (int r = j + 1 + lane; r < rows; r += 64) s += A[r * NS + j] * A[r * NS + j];
+    s = wave_sum(s);
+    const double alpha = A[j * NS + j];
+    double t = 0.0, beta = alpha, scal = 0.0;
+    if (s > 0.0) {
+      const double nrm = sqrt(alpha * alpha + s);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      t = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (s > 0.0)
+      for (int r = j + 1 + lane; r < rows; r += 64) A[r * NS + j] *= scal;
+    if (lane == 0) { A[j * NS + j] = beta; tau[j] = t; }
+    __syncthreads();
+    // apply H_j = I - t v v^T (v = [1; A[j+1:, j]]) to columns j+1..NS-1
+    for (int c = j + 1; c < NS; ++c) {
+      double w = 0.0;
+      for (int r = j + lane; r < rows; r += 64) w += (r == j ? 1.0 : A[r * NS + j]) * A[r * NS + c];
+      w = wave_sum(w) * t;
+      __syncthreads();
+      for (int r = j + lane; r < rows; r += 64) A[r * NS + c] -= w * (r == j ? 1.0 : A[r * NS + j]);
+      __syncthreads();
+    }
+  }
+  // Q = H_0 ... H_{ncol-1} [I; 0]
+  for (int idx = lane; idx < rows * NS; idx += 64) {
+    const int r = idx / NS, c = idx % NS;
+    Q[idx] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int j = ncol - 1; j >= 0; --j) {
+    const double t = tau[j];
+    for (int c = j; c < NS; ++c) {
+      double w = 0.0;
+      for (int r = j + lane; r < rows; r += 64) w += (r == j ? 1.0 : A[r * NS + j]) * Q[r * NS + c];
+      w = wave_sum(w) * t;
+      __syncthreads();
+      for (int r = j + lane; r < rows; r += 64) Q[r * NS + c] -= w * (r == j ? 1.0 : A[r * NS + j]);
+      __syncthreads();
+    }
+  }
+  // sign convention diag(R) >= 0; R = upper triangle of A's first NS rows
+  __shared__ double sgn[NS];
+  if (lane < NS) sgn[lane] = (lane < ncol && A[lane * NS + lane] < 0.0) ? -1.0 : 1.0;
+  __syncthreads();
+  for (int idx = lane; idx < rows * NS; idx += 64) {
+    const int r = idx / NS, c = idx % NS;
+    const int mem = agg_mem[m0 + r / bs];
+    P[((size_t)mem * bs + (r % bs)) * NS + c] = Q[idx] * sgn[c];
+  }
+  for (int idx = lane; idx < NS * NS; idx += 64) {
+    const int r = idx / NS, c = idx % NS;
+    Kc[(size_t)a * NS * NS + idx] = (r < ncol && c >= r) ? sgn[r] * A[r * NS + c] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- explicit level-0 S
+
+// Off-diagonal block (i, j), i < j, of S = A - W C^-1 W^T:
+//   S_ij = - sum_{p seen by i and j} F_{o_i}^T (E_{o_i} C_p^-1 E_{o_j}^T) F_{o_j}.
+// One workgroup per upper entry: camera i's observations are scanned in
+// chunks; each finds camera j among its point's (camera-sorted) observers,
+// matched pairs are compacted into LDS, then 81 threads accumulate the block.
+// Diagonal blocks are the block-Jacobi blocks S_cc. Both (i, j) and (j, i) are
+// written (the transpose).
+__global__ __launch_bounds__(128) void k_explicit_s0(
+    const int32_t* __restrict__ row_of, const int32_t* __restrict__ col,
+    const int32_t* __restrict__ trans_pos, const int32_t* __restrict__ cam_off,
+    const int32_t* __restrict__ cam_obs, const int32_t* __restrict__ obs_pt,
+    const int32_t* __restrict__ pt_off, const int32_t* __restrict__ obs_cam, int64_t stride,
+    const double* __restrict__ F, const double* __restrict__ E, const double* __restrict__ Cinv,
+    const double* __restrict__ Scc, double* __restrict__ S) {
+  const int e = blockIdx.x;
+  const int i = row_of[e], j = col[e];
+  if (i == j) {
+    if (threadIdx.x < 81) S[(size_t)e * 81 + threadIdx.x] = Scc[(size_t)i * 81 + threadIdx.x];
+    return;
+  }
+  if (i > j) return;
+  __shared__ double Fi[128][18];
+  __shared__ double Fj[128][18];
+  __shared__ double Mm[128][4];
+  __shared__ int wcount[2];
+  double acc = 0.0;
+  const int r = threadIdx.x / 9, c = threadIdx.x % 9;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int base = cam_off[i]; base < cam_off[i + 1]; base += 128) {
+    const int k = base + threadIdx.x;
+    int oi = -1, oj = -1;
+    if (k < cam_off[i + 1]) {
+      oi = cam_obs[k];
+      const int q = obs_pt[oi];
+      int lo = pt_off[q], hi = pt_off[q + 1] - 1;
+      while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int cm = obs_cam[mid];
+        if (cm == j) { oj = mid; break; }
+        if (cm < j) lo = mid + 1; else hi = mid - 1;
+      }
+    }
+    const bool hit = oj >= 0;
+    const unsigned long long m = __ballot(hit);
+    if (lane == 0) wcount[wid] = __popcll(m);
+    __syncthreads();
+    const int nhit = wcount[0] + wcount[1];
+    if (hit) {
+      const int pos = (wid ? wcount[0] : 0) + __popcll(m & ((1ull << lane) - 1ull));
+      const int q = obs_pt[oi];
+      const double* ci = Cinv + (size_t)q * 6;
+      const double C[9] = {ci[0], ci[1], ci[2], ci[1], ci[3], ci[4], ci[2], ci[4], ci[5]};
+      double ei[6], ej[6];
+      for (int t = 0; t < 6; ++t) { ei[t] = E[t * stride + oi]; ej[t] = E[t * stride + oj]; }
+      // M = E_i C^-1 E_j^T (2 x 2)
+      for (int a = 0; a < 2; ++a) {
+        double ec[3];
+        for (int t = 0; t < 3; ++t) ec[t] = ei[a * 3] * C[t] + ei[a * 3 + 1] * C[3 + t] + ei[a * 3 + 2] * C[6 + t];
+        for (int b = 0; b < 2; ++b) Mm[pos][a * 2 + b] = ec[0] * ej[b * 3] + ec[1] * ej[b * 3 + 1] + ec[2] * ej[b * 3 + 2];
+      }
+      for (int t = 0; t < 18; ++t) { Fi[pos][t] = F[t * stride + oi]; Fj[pos][t] = F[t * stride + oj]; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 81) {
+      for (int h = 0; h < nhit; ++h) {
+        const double a0 = Mm[h][0] * Fj[h][c] + Mm[h][1] * Fj[h][9 + c];
+        const double a1 = Mm[h][2] * Fj[h][c] + Mm[h][3] * Fj[h][9 + c];
+        acc += Fi[h][r] * a0 + Fi[h][9 + r] * a1;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 81) {
+    S[(size_t)e * 81 + r * 9 + c] = -acc;
+    S[(size_t)trans_pos[e] * 81 + c * 9 + r] = -acc;
+  }
+}
+
+// ---------------------------------------------------------------- Galerkin product
+
+// Coarse entry (A, B) = sum over fine entries (i, j) with agg(i) = A, agg(j) = B
+// of P_i^T S_ij P_j (fine blocks bs x bs, P blocks bs x 16). One workgroup of
+// 256 threads per coarse entry; thread (r, c) owns entry (r, c).
+__global__ __launch_bounds__(256) void k_galerkin(int bs, const int32_t* __restrict__ gal_ptr,
+                                                  const int32_t* __restrict__ gal_fine,
+                                                  const int32_t* __restrict__ row_of,
+                                                  const int32_t* __restrict__ col,
+                                                  const double* __restrict__ Sf,
+                                                  const double* __restrict__ P,
+                                                  double* __restrict__ Sc) {
+  __shared__ double Ss[NS * NS], Pi[NS * NS], Pj[NS * NS], T[NS * NS];
+  const int ec = blockIdx.x;
+  const int r = threadIdx.x / NS, c = threadIdx.x % NS;
+  double acc = 0.0;
+  for (int g = gal_ptr[ec]; g < gal_ptr[ec + 1]; ++g) {
+    const int e = gal_fine[g];
+    const int i = row_of[e], j = col[e];
+    if (threadIdx.x < bs * bs) Ss[threadIdx.x] = Sf[(size_t)e * bs * bs + threadIdx.x];
+    if (threadIdx.x < bs * NS) {
+      Pi[threadIdx.x] = P[(size_t)i * bs * NS + threadIdx.x];
+      Pj[threadIdx.x] = P[(size_t)j * bs * NS + threadIdx.x];
+    }
+    __syncthreads();
+    // T = S_ij P_j  (bs x 16)
+    if (r < bs) {
+      double s = 0.0;
+      for (int k = 0; k < bs; ++k) s += Ss[r * bs + k] * Pj[k * NS + c];
+      T[r * NS + c] = s;
+    }
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < bs; ++k) s += Pi[k * NS + r] * T[k * NS + c];
+    acc += s;
+    __syncthreads();
+  }
+  Sc[(size_t)ec * NS * NS + threadIdx.x] = acc;
+}
+
+// ---------------------------------------------------------------- block inverses
+
+// Inverse of the diagonal 16 x 16 block of every node (one wave per node).
+__global__ __launch_bounds__(64) void k_diag_inverse16(const int32_t* __restrict__ diag_pos,
+                                                       const double* __restrict__ S,
+                                                       double* __restrict__ Dinv, uint32_t* err) {
+  __shared__ double a[NS * NS], inv[NS * NS];
+  const int i = blockIdx.x;
+  const double* blk = S + (size_t)diag_pos[i] * NS * NS;
+  for (int k = threadIdx.x; k < NS * NS; k += 64) a[k] = blk[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!cholesky<NS>(a)) {
+      atomicOr(err, ERRF_NOT_SPD);
+      for (int k = 0; k < NS * NS; ++k) inv[k] = 0.0;
+    } else {
+      cholesky_inverse<NS>(a, inv);
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NS * NS; k += 64) Dinv[(size_t)i * NS * NS + k] = inv[k];
+}
+
+// ---------------------------------------------------------------- coarse level
+
+// Scatter a BSR operator into a dense nd x nd matrix (padding rows get 1 on the
+// diagonal). One thread per stored value.
+__global__ void k_bsr_to_dense(int n, int bs, int nd, const int32_t* __restrict__ row_of,
+                               const int32_t* __restrict__ col, int64_t nnz,
+                               const double* __restrict__ S, double* __restrict__ D) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = nnz * bs * bs;
+  if (idx < total) {
+    const int64_t e = idx / (bs * bs);
+    const int rc = (int)(idx % (bs * bs));
+    const int r = rc / bs, c = rc % bs;
+    D[(size_t)(row_of[e] * bs + r) * nd + (size_t)col[e] * bs + c] = S[idx];
+  }
+  const int64_t pad = idx - total;
+  if (pad >= 0 && pad < nd - (int64_t)n * bs) {
+    const size_t d = (size_t)n * bs + pad;
+    D[d * nd + d] = 1.0;
+  }
+}
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Orders the LDS/global accesses of the lanes of one wave (no block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One 16x16 FP64 tile product on the matrix cores, 4 MFMA 16x16x4 steps:
+//   XT = false: C += sx * X Y^T,   XT = true: C += sx * X^T Y,
+// X, Y row-major 16 x 16 tiles with leading dimensions ldx, ldy.
+// MFMA 16x16x4 f64 operand layout: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; accumulator element i of lane l is C[4*i + l/16][l%16]
+// (rows interleaved across the four lane groups).
+template <bool XT>
+__device__ __forceinline__ d4 tile_mma(d4 acc, const double* X, int ldx, const double* Y, int ldy,
+                                       double sx) {
+  const int l = threadIdx.x & 63;
+  const int m = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = kk * 4 + kq;
+    const double a = XT ? X[(size_t)k * ldx + m] : X[(size_t)m * ldx + k];
+    const double b = XT ? Y[(size_t)k * ldy + m] : Y[(size_t)m * ldy + k];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sx * a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// C += sx * X Y (plain product), same layout conventions.
+__device__ __forceinline__ d4 tile_mma_nn(d4 acc, const double* X, int ldx, const double* Y, int ldy,
+                                          double sx) {
+  const int l = threadIdx.x & 63;
+  const int m = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int k = kk * 4 + kq;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sx * X[(size_t)m * ldx + k], Y[(size_t)k * ldy + m], acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ d4 tile_load(const double* C, int ld) {
+  const int l = threadIdx.x & 63;
+  d4 v;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = C[(size_t)(4 * i + (l >> 4)) * ld + (l & 15)];
+  return v;
+}
+
+__device__ __forceinline__ void tile_store(double* C, int ld, d4 v) {
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) C[(size_t)(4 * i + (l >> 4)) * ld + (l & 15)] = v[i];
+}
+
+// Probe of the tile products (checked by a test of the MFMA operand layout):
+// mode 0: C += X Y^T, 1: C += X^T Y, 2: C += X Y.
+__global__ __launch_bounds__(64) void k_mfma_probe(const double* X, const double* Y, double* C, int mode) {
+  d4 acc = tile_load(C, 16);
+  if (mode == 0) acc = tile_mma<false>(acc, X, 16, Y, 16, 1.0);
+  else if (mode == 1) acc = tile_mma<true>(acc, X, 16, Y, 16, 1.0);
+  else acc = tile_mma_nn(acc, X, 16, Y, 16, 1.0);
+  tile_store(C, 16, acc);
+}
+
+// Cholesky of the 16x16 diagonal tile k (one wave, in LDS) and the inverse of
+// its factor; L_kk is written back to A (upper part zeroed).
+__device__ void chol_diag_tile(double* A, int nd, int k, double* Lt, double* Linv, uint32_t* err) {
+  const int lane = threadIdx.x & 63;
+  for (int idx = lane; idx < 256; idx += 64) Lt[idx] = A[(size_t)(k * 16 + idx / 16) * nd + k * 16 + idx % 16];
+  wave_sync();
+  if (lane == 0) {
+    if (!cholesky<16>(Lt)) atomicOr(err, ERRF_NOT_SPD);
+    for (int j = 0; j < 16; ++j) {
+      for (int i = 0; i < 16; ++i) Linv[i * 16 + j] = 0.0;
+      Linv[j * 16 + j] = 1.0 / Lt[j * 16 + j];
+      for (int i = j + 1; i < 16; ++i) {
+        double s = 0.0;
+        for (int t = j; t < i; ++t) s -= Lt[i * 16 + t] * Linv[t * 16 + j];
+        Linv[i * 16 + j] = s / Lt[i * 16 + i];
+      }
+    }
+  }
+  wave_sync();
+  for (int idx = lane; idx < 256; idx += 64) {
+    const int i = idx / 16, j = idx % 16;
+    A[(size_t)(k * 16 + i) * nd + k * 16 + j] = j <= i ? Lt[idx] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void tri_index(int p, int* i, int* j) {
+  int r = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while ((r + 1) * (r + 2) / 2 <= p) ++r;
+  while (r * (r + 1) / 2 > p) --r;
+  *i = r;
+  *j = p - r * (r + 1) / 2;
+}
+
+// Dense SPD inverse by blocked Cholesky in one workgroup of 16 waves with
+// 16 x 16 tiles; every tile product runs on the FP64 matrix cores:
+//   1. A = L L^T (right-looking: factor A_kk; A_ik <- A_ik L_kk^-T;
+//      A_ij -= A_ik A_jk^T);
+//   2. X = L^-1 by column blocks: X_kk = L_kk^-1, X_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij X_jk;
+//   3. inv = X^T X.
+// A (nd x nd) is overwritten; nd is a multiple of 16. Linv_all: nb x 256.
+constexpr int CHOL_WAVES = 16;
+
+__global__ __launch_bounds__(64 * CHOL_WAVES) void k_dense_spd_inverse(int nd, double* A, double* inv,
+                                                                       double* Linv_all, uint32_t* err) {
+  __shared__ double Lt[256], Li[256];
+  __shared__ double stage[CHOL_WAVES][256];
+  const int nb = nd / 16;
+  const int wave = threadIdx.x >> 6;
+  // ---- 1. Cholesky
+  for (int k = 0; k < nb; ++k) {
+    if (wave == 0) {
+      chol_diag_tile(A, nd, k, Lt, Li, err);
+      for (int idx = threadIdx.x; idx < 256; idx += 64) Linv_all[(size_t)k * 256 + idx] = Li[idx];
+    }
+    __syncthreads();
+    for (int i = k + 1 + wave; i < nb; i += CHOL_WAVES) {
+      double* Aik = A + (size_t)(i * 16) * nd + k * 16;
+      d4 acc = {0, 0, 0, 0};
+      acc = tile_mma<false>(acc, Aik, nd, Li, 16, 1.0);
+      tile_store(Aik, nd, acc);
+    }
+    __syncthreads();
+    const int m = nb - k - 1;
+    const int npairs = m * (m + 1) / 2;
+    for (int p = wave; p < npairs; p += CHOL_WAVES) {
+      int ii, jj;
+      tri_index(p, &ii, &jj);
+      const int i = k + 1 + ii, j = k + 1 + jj;
+      double* Cij = A + (size_t)(i * 16) * nd + j * 16;
+      d4 acc = tile_load(Cij, nd);
+      acc = tile_mma<false>(acc, A + (size_t)(i * 16) * nd + k * 16, nd, A + (size_t)(j * 16) * nd + k * 16, nd, -1.0);
+      tile_store(Cij, nd, acc);
+    }
+    __syncthreads();
+  }
+  // ---- 2. X = L^-1 (lower), into inv; one wave per column block
+  double* st = stage[wave];
+  for (int k = wave; k < nb; k += CHOL_WAVES) {
+    for (int idx = threadIdx.x & 63; idx < 256; idx += 64)
+      inv[(size_t)(k * 16 + idx / 16) * nd + k * 16 + idx % 16] = Linv_all[(size_t)k * 256 + idx];
+    wave_sync();
+    for (int i = k + 1; i < nb; ++i) {
+      d4 acc = {0, 0, 0, 0};
+      for (int j = k; j < i; ++j)
+        acc = tile_mma_nn(acc, A + (size_t)(i * 16) * nd + j * 16, nd, inv + (size_t)(j * 16) * nd + k * 16, nd, 1.0);
+      tile_store(st, 16, acc);
+      wave_sync();
+      d4 out = {0, 0, 0, 0};
+      out = tile_mma_nn(out, Linv_all + (size_t)i * 256, 16, st, 16, -1.0);
+      tile_store(inv + (size_t)(i * 16) * nd + k * 16, nd, out);
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  // ---- 3. inv = X^T X: lower tiles (i >= j) into A, then mirrored into inv
+  const int ntiles = nb * (nb + 1) / 2;
+  for (int p = wave; p < ntiles; p += CHOL_WAVES) {
+    int i, j;
+    tri_index(p, &i, &j);
+    d4 acc = {0, 0, 0, 0};
+    for (int k = i; k < nb; ++k)
+      acc = tile_mma<true>(acc, inv + (size_t)(k * 16) * nd + i * 16, nd, inv + (size_t)(k * 16) * nd + j * 16, nd, 1.0);
+    tile_store(A + (size_t)(i * 16) * nd + j * 16, nd, acc);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) {
+    const int r = idx / nd, c = idx % nd;
+    inv[idx] = ((r >> 4) > (c >> 4) || ((r >> 4) == (c >> 4) && r >= c)) ? A[idx] : A[(size_t)c * nd + r];
+  }
+}
+
+}  // namespace bamg

@@ -1,0 +1,113 @@
+// The plan: integer structure of one visibility graph (observation layout,
+// tiles, multigrid hierarchy pattern) plus the per-step numeric buffers.
+#pragma once
+
+#include "common.hpp"
+
+namespace bamg {
+
+// One multigrid level. Nodes are cameras on level 0 and aggregates above.
+struct Level {
+  int n = 0;    // nodes
+  int bs = 9;   // dofs per node: 9 on level 0, 16 above
+  // covisibility W of this level: CSR, sorted columns, diagonal included.
+  // Its pattern is also the block pattern of this level's operator.
+  int64_t nnz = 0;
+  std::vector<int64_t> h_rowptr;
+  std::vector<int32_t> h_col;
+  DBuf<int64_t> rowptr;
+  DBuf<int32_t> rowptr32;    // same as rowptr, int32 (block kernels)
+  DBuf<int32_t> col;
+  DBuf<int64_t> wval;
+  DBuf<int64_t> wdiag;       // W_ii
+  DBuf<int32_t> order;       // neighbours by decreasing strength: row i at [rowptr[i]-i, rowptr[i+1]-i-1)
+  DBuf<int32_t> diag_pos;    // CSR position of (i, i)
+  DBuf<int32_t> trans_pos;   // CSR position of (j, i) for entry (i, j)
+  DBuf<int32_t> row_of;      // row index of every CSR entry
+  // aggregation of this level into the next (absent on the coarsest level)
+  int n_agg = 0;
+  std::vector<int32_t> h_agg;
+  DBuf<int32_t> agg;         // aggregate id per node (creation order)
+  DBuf<int32_t> agg_ptr;     // members of aggregate a: agg_mem[agg_ptr[a] .. agg_ptr[a+1])
+  DBuf<int32_t> agg_mem;     // ascending node ids
+  DBuf<int32_t> agg_pos;     // position of node i inside its aggregate
+  int max_agg = 0;           // largest aggregate
+  // Galerkin map: coarse CSR entry e gathers fine entries gal_fine[gal_ptr[e] .. gal_ptr[e+1])
+  DBuf<int32_t> gal_ptr;
+  DBuf<int32_t> gal_fine;
+  // ---- numeric, per step
+  DBuf<double> S;            // nnz * bs * bs  explicit operator (level 0: explicit Schur S)
+  DBuf<float> S32;
+  DBuf<double> K;            // n * bs * NS near-nullspace rows
+  DBuf<double> P;            // n * bs * NS tentative prolongator blocks (to level + 1)
+  DBuf<float> P32;
+  DBuf<double> Dinv;         // n * bs * bs inverse diagonal blocks
+  DBuf<float> Dinv32;
+  double lmax = 0.0;         // lambda_max estimate of D^-1 S (generalized Lanczos)
+  bool explicit_op = true;   // level 0: use explicit S for smoothing (else implicit)
+  // coarsest level: dense inverse of the operator (FP64), padded to nd x nd
+  int nd = 0;
+  DBuf<double> dense;        // factor workspace nd x nd
+  DBuf<double> inv;          // inverse nd x nd
+  // V-cycle work vectors, FP64 and FP32 (n * bs each)
+  DBuf<double> vb, vx, vr, vd, vt;
+  DBuf<float> fb, fx, fr, fd, ft;
+};
+
+struct Scratch;  // defined in api.cpp
+
+}  // namespace bamg
+
+struct ba_plan {
+  int32_t n_cam = 0, n_pt = 0;
+  int64_t n_obs = 0;
+  int64_t n_obs_pad = 0;     // plane stride of the observation SoA arrays
+  // ---- point-major observation layout
+  std::vector<int32_t> h_obs_cam, h_obs_pt, h_obs_orig, h_pt_orig;
+  std::vector<int64_t> h_pt_off, h_cam_off;
+  std::vector<int32_t> h_cam_obs;
+  bamg::DBuf<int32_t> obs_cam;    // [n_obs] camera of each observation (point-major)
+  bamg::DBuf<int32_t> obs_pt;     // [n_obs] reordered point index
+  bamg::DBuf<int32_t> obs_orig;   // [n_obs] caller's observation index
+  bamg::DBuf<int32_t> pt_off;     // [n_pt + 1] observation range of each reordered point
+  bamg::DBuf<int32_t> pt_orig;    // [n_pt] caller's point index of each reordered point
+  bamg::DBuf<int32_t> pt_new;     // [n_pt] reordered index of each caller point
+  bamg::DBuf<int32_t> cam_off;    // [n_cam + 1]
+  bamg::DBuf<int32_t> cam_obs;    // [n_obs] point-major observation indices, camera-major
+  bamg::DBuf<int32_t> obs_rank;   // [n_obs] point-major index of caller observation i
+  // ---- tiles for the implicit Schur product
+  int32_t n_tiles = 0;
+  bamg::DBuf<int32_t> tile_obs;   // [n_tiles + 1]
+  bamg::DBuf<int32_t> tile_pt;    // [n_tiles + 1]
+  bamg::DBuf<int32_t> tile_coff;  // [n_tiles + 1] offsets into tile_cams
+  bamg::DBuf<int32_t> tile_cams;  // distinct cameras of each tile, ascending
+  bamg::DBuf<uint32_t> obs_slot;  // [n_obs] (point slot << 16) | camera slot
+  int32_t max_tile_cams = 0;
+  int32_t max_pt_obs = 0;
+  // ---- multigrid hierarchy
+  std::vector<bamg::Level> levels;
+  // ---- per-step numeric state (FP64 unless suffixed 32)
+  bamg::DBuf<double> campre;      // [n_cam][24]: R, J_r, t, f, k1, k2
+  bamg::DBuf<double> F, E, fres;  // SoA planes: 18, 6, 2 x n_obs_pad
+  bamg::DBuf<float> F32, E32;
+  bamg::DBuf<double> Cinv;        // [n_pt][6] packed symmetric C^-1 (reordered points)
+  bamg::DBuf<float> Cinv32;
+  bamg::DBuf<double> vgp;         // [n_pt][3] C^-1 g_p
+  bamg::DBuf<double> gp;          // [n_pt][3] g_p
+  bamg::DBuf<double> Dp;          // [n_pt][3] damping of the point block
+  bamg::DBuf<double> A;           // [n_cam][45] packed damped A
+  bamg::DBuf<float> A32;
+  bamg::DBuf<double> Dc;          // [n_cam][9] damping of the camera block
+  bamg::DBuf<double> b;           // [n_cam][9]
+  bamg::DBuf<double> gc;          // [n_cam][9]
+  bamg::DBuf<double> Scc;         // [n_cam][81] block-Jacobi blocks (before inversion)
+  bamg::DBuf<double> Sinv;        // [n_cam][81] inverses
+  bamg::DBuf<float> Sinv32;
+  bamg::DBuf<uint32_t> errflag;   // device error bits
+  bool prepared = false;
+  bool prepared_mg = false;
+  bool inspectable_mg = false;   // hierarchy data readable (also after a failed setup)
+  bool have_mixed = false;
+  double lambda = 1e-4;
+  bamg::Scratch* scratch = nullptr;
+};

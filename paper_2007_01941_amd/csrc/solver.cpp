@@ -1,0 +1,599 @@
+// Host orchestration of one LM step on the device: evaluation, numeric
+// multigrid setup, the V-cycle, PCG and mixed-precision refinement.
+// (Included by api.cpp inside namespace-level scope.)
+#include <algorithm>
+#include <cmath>
+
+namespace bamg {
+
+template <class T>
+static int grid_of(int64_t n, int per = 256) { return std::max(1, ceil_div(n, per)); }
+
+static size_t plan_bytes(const ba_plan* P) {
+  size_t b = 0;
+  b += P->obs_cam.bytes() + P->obs_pt.bytes() + P->obs_orig.bytes() + P->pt_off.bytes() + P->pt_orig.bytes();
+  b += P->pt_new.bytes() + P->cam_off.bytes() + P->cam_obs.bytes() + P->obs_rank.bytes();
+  b += P->tile_obs.bytes() + P->tile_pt.bytes() + P->tile_coff.bytes() + P->tile_cams.bytes() + P->obs_slot.bytes();
+  b += P->campre.bytes() + P->F.bytes() + P->E.bytes() + P->fres.bytes() + P->F32.bytes() + P->E32.bytes();
+  b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
+  b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->gc.bytes() + P->Scc.bytes();
+  b += P->Sinv.bytes() + P->Sinv32.bytes();
+  for (const Level& L : P->levels) {
+    b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
+    b += L.diag_pos.bytes() + L.trans_pos.bytes() + L.row_of.bytes() + L.agg.bytes() + L.agg_ptr.bytes();
+    b += L.agg_mem.bytes() + L.agg_pos.bytes() + L.gal_ptr.bytes() + L.gal_fine.bytes();
+    b += L.S.bytes() + L.S32.bytes() + L.K.bytes() + L.P.bytes() + L.P32.bytes() + L.Dinv.bytes() + L.Dinv32.bytes();
+    b += L.dense.bytes() + L.inv.bytes();
+    b += L.vb.bytes() + L.vx.bytes() + L.vr.bytes() + L.vd.bytes() + L.vt.bytes();
+    b += L.fb.bytes() + L.fx.bytes() + L.fr.bytes() + L.fd.bytes() + L.ft.bytes();
+  }
+  return b;
+}
+
+static void allocate_step(ba_plan* P) {
+  const int64_t st = P->n_obs_pad;
+  P->campre.alloc((size_t)P->n_cam * 24);
+  P->F.alloc(18 * st);
+  P->E.alloc(6 * st);
+  P->fres.alloc(2 * st);
+  P->Cinv.alloc((size_t)P->n_pt * 6);
+  P->vgp.alloc((size_t)P->n_pt * 3);
+  P->gp.alloc((size_t)P->n_pt * 3);
+  P->Dp.alloc((size_t)P->n_pt * 3);
+  P->A.alloc((size_t)P->n_cam * 45);
+  P->Dc.alloc((size_t)P->n_cam * 9);
+  P->b.alloc((size_t)P->n_cam * 9);
+  P->gc.alloc((size_t)P->n_cam * 9);
+  P->Scc.alloc((size_t)P->n_cam * 81);
+  P->Sinv.alloc((size_t)P->n_cam * 81);
+  P->scratch = new Scratch();
+  P->scratch->init(P->n_cam, P->n_pt);
+  const int nl = (int)P->levels.size();
+  for (int l = 0; l < nl; ++l) {
+    Level& L = P->levels[l];
+    const size_t nv = (size_t)L.n * L.bs;
+    L.S.alloc((size_t)L.nnz * L.bs * L.bs);
+    L.K.alloc(nv * NS);
+    if (l + 1 < nl) {
+      L.P.alloc(nv * NS);
+      if (l > 0) L.Dinv.alloc((size_t)L.n * L.bs * L.bs);
+    }
+    for (DBuf<double>* v : {&L.vb, &L.vx, &L.vr, &L.vd, &L.vt}) v->alloc(nv);
+    if (l + 1 == nl) {
+      L.nd = (int)((nv + 15) / 16 * 16);
+      L.dense.alloc((size_t)L.nd * L.nd);
+      L.inv.alloc((size_t)L.nd * L.nd);
+    }
+  }
+}
+
+static void ensure_mixed(ba_plan* P) {
+  if (P->F32.p) return;
+  const int64_t st = P->n_obs_pad;
+  P->F32.alloc(18 * st);
+  P->E32.alloc(6 * st);
+  P->Cinv32.alloc((size_t)P->n_pt * 6);
+  P->A32.alloc((size_t)P->n_cam * 45);
+  P->Sinv32.alloc((size_t)P->n_cam * 81);
+  const int nl = (int)P->levels.size();
+  for (int l = 0; l < nl; ++l) {
+    Level& L = P->levels[l];
+    const size_t nv = (size_t)L.n * L.bs;
+    L.S32.alloc((size_t)L.nnz * L.bs * L.bs);
+    if (l + 1 < nl) {
+      L.P32.alloc(nv * NS);
+      if (l > 0) L.Dinv32.alloc((size_t)L.n * L.bs * L.bs);
+    }
+    for (DBuf<float>* v : {&L.fb, &L.fx, &L.fr, &L.fd, &L.ft}) v->alloc(nv);
+  }
+}
+
+template <class T, class U>
+static void convert(size_t n, const T* a, U* b, hipStream_t s) {
+  if (n) hipLaunchKernelGGL((k_convert<T, U>), dim3(grid_of<T>(n)), dim3(256), 0, s, (int)n, a, b);
+}
+
+static void eval_jacobian(ba_plan* P, const double* cams, const double* pts, const double* uv, bool mixed,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_campre, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
+                     P->errflag.p);
+  hipLaunchKernelGGL(k_jacobian, dim3(grid_of<double>(P->n_obs)), dim3(256), 0, s, (int)P->n_obs, P->obs_cam.p,
+                     P->obs_pt.p, P->obs_orig.p, P->pt_orig.p, P->campre.p, pts, uv, P->n_obs_pad, P->F.p, P->E.p,
+                     P->fres.p, mixed ? P->F32.p : nullptr, mixed ? P->E32.p : nullptr, P->errflag.p);
+  BA_LAUNCH_CHECK();
+  check_errflag(P, s);
+}
+
+// ---------------------------------------------------------------- level operators
+
+static bool level0_explicit(const ba_plan* P, const ba_opts* o, int s_bytes) {
+  if (o->level0_op == BA_OP_EXPLICIT) return true;
+  if (o->level0_op == BA_OP_IMPLICIT) return false;
+  const Level& L = P->levels[0];
+  const double implicit = (double)P->n_obs * (24.0 * s_bytes + 4) + (double)P->n_pt * (6.0 * s_bytes + 4) +
+                          (double)P->n_cam * 63.0 * s_bytes;
+  const double expl = (double)L.nnz * (81.0 * s_bytes + 4) + (double)P->n_cam * 18.0 * s_bytes;
+  return expl < implicit;
+}
+
+template <class T> static const T* lvS(const Level& L);
+template <> const double* lvS<double>(const Level& L) { return L.S.p; }
+template <> const float* lvS<float>(const Level& L) { return L.S32.p; }
+template <class T> static const T* lvP(const Level& L);
+template <> const double* lvP<double>(const Level& L) { return L.P.p; }
+template <> const float* lvP<float>(const Level& L) { return L.P32.p; }
+template <class T> static const T* lvDinv(const ba_plan* P, int l);
+template <> const double* lvDinv<double>(const ba_plan* P, int l) { return l == 0 ? P->Sinv.p : P->levels[l].Dinv.p; }
+template <> const float* lvDinv<float>(const ba_plan* P, int l) { return l == 0 ? P->Sinv32.p : P->levels[l].Dinv32.p; }
+template <class T> struct LvVec;
+template <> struct LvVec<double> {
+  static double* b(Level& L) { return L.vb.p; }
+  static double* x(Level& L) { return L.vx.p; }
+  static double* r(Level& L) { return L.vr.p; }
+  static double* d(Level& L) { return L.vd.p; }
+  static double* t(Level& L) { return L.vt.p; }
+};
+template <> struct LvVec<float> {
+  static float* b(Level& L) { return L.fb.p; }
+  static float* x(Level& L) { return L.fx.p; }
+  static float* r(Level& L) { return L.fr.p; }
+  static float* d(Level& L) { return L.fd.p; }
+  static float* t(Level& L) { return L.ft.p; }
+};
+
+template <class T>
+static void op_apply(ba_plan* P, int l, const T* x, T* y, const int* done, hipStream_t s) {
+  Level& L = P->levels[l];
+  if (l == 0 && !L.explicit_op) {
+    schur_apply_dev<T>(P, x, y, done, s);
+    return;
+  }
+  if (L.bs == 9)
+    hipLaunchKernelGGL((k_bsr_spmv<9, T>), dim3(grid_of<T>(L.n, 4)), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p,
+                       lvS<T>(L), x, y, done);
+  else
+    hipLaunchKernelGGL((k_bsr_spmv<16, T>), dim3(grid_of<T>(L.n, 4)), dim3(256), 0, s, L.n, L.rowptr32.p,
+                       L.col.p, lvS<T>(L), x, y, done);
+}
+
+template <int BS, class T>
+static void blockdiag_apply(ba_plan* P, int l, const T* r, T* z, const int* done, hipStream_t s) {
+  const Level& L = P->levels[l];
+  hipLaunchKernelGGL((k_blockdiag<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n,
+                     lvDinv<T>(P, l), r, z, done);
+}
+
+template <int BS, class T>
+static void vcycle_level(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done, hipStream_t s);
+
+template <class T>
+static void vcycle(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done, hipStream_t s) {
+  Level& L = P->levels[l];
+  if (l + 1 == (int)P->levels.size()) {
+    const int nv = L.n * L.bs;
+    hipLaunchKernelGGL((k_dense_solve<T>), dim3(grid_of<T>(nv, 4)), dim3(256), 0, s, nv, L.nd, L.inv.p, b, x, done);
+    return;
+  }
+  if (L.bs == 9) vcycle_level<9, T>(P, o, l, b, x, done, s);
+  else vcycle_level<16, T>(P, o, l, b, x, done, s);
+}
+
+template <int BS, class T>
+static void vcycle_level(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done, hipStream_t s) {
+  Level& L = P->levels[l];
+  Level& C = P->levels[l + 1];
+  T* r = LvVec<T>::r(L);
+  T* d = LvVec<T>::d(L);
+  T* t = LvVec<T>::t(L);
+  const T* Dinv = lvDinv<T>(P, l);
+  const double lmax = L.lmax;
+  const double theta = 0.5 * (o->cheb_hi + o->cheb_lo) * lmax;
+  const double delta = 0.5 * (o->cheb_hi - o->cheb_lo) * lmax;
+  const double sigma1 = theta / delta;
+  const int m = o->cheb_degree;
+  const int nb = std::max(1, ceil_div(L.n, 256 / BS));
+  // pre-smoothing from x = 0
+  double rho = 1.0 / sigma1;
+  hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, 0, Dinv, b, (const T*)nullptr, r, d, x,
+                     (T)(1.0 / theta), done);
+  for (int k = 0; k < m; ++k) {
+    op_apply<T>(P, l, d, t, done, s);
+    if (k == m - 1) break;
+    const double rn = 1.0 / (2.0 * sigma1 - rho);
+    hipLaunchKernelGGL((k_cheb_next<BS, T>), dim3(nb), dim3(256), 0, s, L.n, Dinv, (const T*)t, r, d, x,
+                       (T)(rn * rho), (T)(2.0 * rn / delta), done);
+    rho = rn;
+  }
+  // restriction of the pre-smoother's residual r - t
+  T* bc = LvVec<T>::b(C);
+  T* xc = LvVec<T>::x(C);
+  hipLaunchKernelGGL((k_restrict<BS, T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n, L.agg_ptr.p,
+                     L.agg_mem.p, lvP<T>(L), (const T*)r, (const T*)t, bc, done);
+  vcycle<T>(P, o, l + 1, bc, xc, done, s);
+  hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
+                     lvP<T>(L), (const T*)xc, x, done);
+  // post-smoothing from x
+  op_apply<T>(P, l, x, t, done, s);
+  rho = 1.0 / sigma1;
+  hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, 1, Dinv, b, (const T*)t, r, d, x,
+                     (T)(1.0 / theta), done);
+  for (int k = 0; k < m - 1; ++k) {
+    op_apply<T>(P, l, d, t, done, s);
+    const double rn = 1.0 / (2.0 * sigma1 - rho);
+    hipLaunchKernelGGL((k_cheb_next<BS, T>), dim3(nb), dim3(256), 0, s, L.n, Dinv, (const T*)t, r, d, x,
+                       (T)(rn * rho), (T)(2.0 * rn / delta), done);
+    rho = rn;
+  }
+}
+
+template <class T> static const T* Sinv_of(const ba_plan* P);
+template <> const double* Sinv_of<double>(const ba_plan* P) { return P->Sinv.p; }
+template <> const float* Sinv_of<float>(const ba_plan* P) { return P->Sinv32.p; }
+template <class T> static const T* A_of(const ba_plan* P);
+template <> const double* A_of<double>(const ba_plan* P) { return P->A.p; }
+template <> const float* A_of<float>(const ba_plan* P) { return P->A32.p; }
+
+template <class T>
+static void precond_apply(ba_plan* P, const ba_opts* o, const T* r, T* z, const int* done, hipStream_t s) {
+  if (o->precond == BA_PC_BLOCK_JACOBI) {
+    hipLaunchKernelGGL((k_bj_apply<T>), dim3(grid_of<T>(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam,
+                       Sinv_of<T>(P), r, z, done);
+  } else {
+    BA_CHECK(P->prepared_mg, BA_ERR_ARG, "the step was prepared without the multigrid preconditioner");
+    vcycle<T>(P, o, 0, r, z, done, s);
+  }
+}
+
+static void precond_apply_fp64boundary(ba_plan* P, const ba_opts* o, int precision, const double* r, double* z,
+                                       hipStream_t s) {
+  const int n = 9 * P->n_cam;
+  if (precision == BA_MIXED) {
+    BA_CHECK(P->have_mixed, BA_ERR_ARG, "step was prepared without BA_MIXED");
+    Scratch& W = *P->scratch;
+    convert(n, r, W.fr.p, s);
+    precond_apply<float>(P, o, W.fr.p, W.fz.p, nullptr, s);
+    convert(n, W.fz.p, z, s);
+  } else {
+    precond_apply<double>(P, o, r, z, nullptr, s);
+  }
+  BA_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------- Lanczos
+
+static double plain_dot(ba_plan* P, int n, const double* a, const double* b, hipStream_t s) {
+  Scratch& W = *P->scratch;
+  hipLaunchKernelGGL((k_dot<DOT_PLAIN, double>), dim3(red_grid(n)), dim3(256), 0, s, n, a, b, W.partial.p,
+                     W.scal.p + 1, W.dots.p);
+  double v = 0;
+  BA_HIP(hipMemcpyAsync(&v, W.dots.p, sizeof(double), hipMemcpyDeviceToHost, s));
+  BA_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+// Largest eigenvalue of a symmetric tridiagonal matrix by bisection on the
+// Sturm sequence count.
+static double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int n = (int)a.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int c = 0;
+    double d = 1.0;
+    for (int i = 0; i < n; ++i) {
+      d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (count_below(mid) < n) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+static double lanczos_lmax(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
+  Level& L = P->levels[l];
+  const int n = L.n * L.bs;
+  DBuf<double> u, v, up, vp, av, dav, w, dw;
+  for (DBuf<double>* x : {&u, &v, &up, &vp, &av, &dav, &w, &dw}) x->alloc(n);
+  BA_HIP(hipMemsetAsync(up.p, 0, n * sizeof(double), s));
+  BA_HIP(hipMemsetAsync(vp.p, 0, n * sizeof(double), s));
+  const int g = grid_of<double>(n);
+  hipLaunchKernelGGL(k_lanczos_start, dim3(g), dim3(256), 0, s, n, l, u.p);
+  auto dinv = [&](const double* in, double* out) {
+    if (L.bs == 9) blockdiag_apply<9, double>(P, l, in, out, nullptr, s);
+    else blockdiag_apply<16, double>(P, l, in, out, nullptr, s);
+  };
+  dinv(u.p, v.p);
+  const double nrm = std::sqrt(plain_dot(P, n, v.p, u.p, s));
+  BA_CHECK(nrm > 0.0 && std::isfinite(nrm), BA_ERR_NOT_SPD, "smoother blocks are not positive definite");
+  hipLaunchKernelGGL(k_axpby2, dim3(g), dim3(256), 0, s, n, 1.0 / nrm, v.p, 0.0, v.p);
+  hipLaunchKernelGGL(k_axpby2, dim3(g), dim3(256), 0, s, n, 1.0 / nrm, u.p, 0.0, u.p);
+  std::vector<double> alphas, betas;
+  double beta = 0.0;
+  for (int j = 0; j < o->lanczos_steps; ++j) {
+    op_apply<double>(P, l, v.p, av.p, nullptr, s);
+    const double alpha = plain_dot(P, n, av.p, v.p, s);
+    alphas.push_back(alpha);
+    if (j == o->lanczos_steps - 1) break;
+    dinv(av.p, dav.p);
+    hipLaunchKernelGGL(k_lanczos_update, dim3(g), dim3(256), 0, s, n, dav.p, av.p, v.p, vp.p, u.p, up.p, alpha, beta,
+                       w.p, dw.p);
+    const double b2 = plain_dot(P, n, w.p, dw.p, s);
+    if (!(b2 > 1e-300) || std::sqrt(b2) <= 1e-14 * std::fabs(alpha)) break;
+    beta = std::sqrt(b2);
+    betas.push_back(beta);
+    std::swap(vp, v);
+    std::swap(up, u);
+    hipLaunchKernelGGL(k_axpby2, dim3(g), dim3(256), 0, s, n, 1.0 / beta, w.p, 0.0, v.p);
+    hipLaunchKernelGGL(k_axpby2, dim3(g), dim3(256), 0, s, n, 1.0 / beta, dw.p, 0.0, u.p);
+  }
+  BA_LAUNCH_CHECK();
+  return tridiag_max_eig(alphas, betas);
+}
+
+// ---------------------------------------------------------------- multigrid setup
+
+static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixed, hipStream_t s) {
+  const int nl = (int)P->levels.size();
+  Level& L0 = P->levels[0];
+  // explicit level-0 S (Section 3.6): needed for the Galerkin product and, when
+  // cheaper than the implicit form, for smoothing
+  hipLaunchKernelGGL(k_explicit_s0, dim3((unsigned)L0.nnz), dim3(128), 0, s, L0.row_of.p, L0.col.p, L0.trans_pos.p,
+                     P->cam_off.p, P->cam_obs.p, P->obs_pt.p, P->pt_off.p, P->obs_cam.p, P->n_obs_pad, P->F.p,
+                     P->E.p, P->Cinv.p, P->Scc.p, L0.S.p);
+  L0.explicit_op = level0_explicit(P, o, mixed ? 4 : 8);
+  hipLaunchKernelGGL(k_nullspace0, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
+                     L0.K.p);
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level& F = P->levels[l];
+    Level& C = P->levels[l + 1];
+    const size_t lds = (size_t)2 * F.max_agg * F.bs * NS * sizeof(double);
+    BA_CHECK(lds <= 160 * 1024, BA_ERR_LIMIT, "aggregate with %d nodes exceeds the QR kernel's LDS", F.max_agg);
+    hipLaunchKernelGGL(k_qr_aggregates, dim3(F.n_agg), dim3(64), lds, s, F.bs, F.agg_ptr.p, F.agg_mem.p, F.K.p, F.P.p,
+                       C.K.p);
+    hipLaunchKernelGGL(k_galerkin, dim3((unsigned)C.nnz), dim3(256), 0, s, F.bs, F.gal_ptr.p, F.gal_fine.p,
+                       F.row_of.p, F.col.p, F.S.p, F.P.p, C.S.p);
+    if (l + 1 < nl - 1)
+      hipLaunchKernelGGL(k_diag_inverse16, dim3(C.n), dim3(64), 0, s, C.diag_pos.p, C.S.p, C.Dinv.p, P->errflag.p);
+  }
+  BA_LAUNCH_CHECK();
+  P->inspectable_mg = true;
+  check_errflag(P, s, "multigrid setup (QR, Galerkin, smoother blocks)");
+  for (int l = 0; l + 1 < nl; ++l) P->levels[l].lmax = lanczos_lmax(P, o, l, s);
+  // coarsest level: dense FP64 inverse
+  Level& Lc = P->levels[nl - 1];
+  BA_HIP(hipMemsetAsync(Lc.dense.p, 0, (size_t)Lc.nd * Lc.nd * sizeof(double), s));
+  const int64_t tot = Lc.nnz * Lc.bs * Lc.bs + Lc.nd;
+  hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(tot)), dim3(256), 0, s, Lc.n, Lc.bs, Lc.nd, Lc.row_of.p,
+                     Lc.col.p, Lc.nnz, Lc.S.p, Lc.dense.p);
+  DBuf<double> linv;
+  linv.alloc((size_t)(Lc.nd / 16) * 256);
+  hipLaunchKernelGGL(k_dense_spd_inverse, dim3(1), dim3(64 * CHOL_WAVES), 0, s, Lc.nd, Lc.dense.p, Lc.inv.p, linv.p,
+                     P->errflag.p);
+  BA_LAUNCH_CHECK();
+  check_errflag(P, s, "coarse Cholesky");
+  if (mixed) {
+    for (int l = 0; l < nl; ++l) {
+      Level& L = P->levels[l];
+      convert((size_t)L.nnz * L.bs * L.bs, L.S.p, L.S32.p, s);
+      if (l + 1 < nl) {
+        convert((size_t)L.n * L.bs * NS, L.P.p, L.P32.p, s);
+        if (l > 0) convert((size_t)L.n * L.bs * L.bs, L.Dinv.p, L.Dinv32.p, s);
+      }
+    }
+  }
+  P->prepared_mg = true;
+}
+
+// ---------------------------------------------------------------- prepare
+
+static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const double* pts, const double* uv,
+                    const double* D, ba_stats* st, hipStream_t s) {
+  const bool mixed = o->precision == BA_MIXED;
+  if (mixed) ensure_mixed(P);
+  P->prepared = false;
+  P->prepared_mg = false;
+  P->inspectable_mg = false;
+  P->lambda = o->lambda;
+  Timer tj(s);
+  eval_jacobian(P, cams, pts, uv, mixed, s);
+  hipLaunchKernelGGL(k_point_blocks, dim3(grid_of<double>(P->n_pt)), dim3(256), 0, s, P->n_pt, P->pt_off.p,
+                     P->pt_orig.p, P->n_obs_pad, P->E.p, P->fres.p, o->lambda, D, P->n_cam, P->Cinv.p,
+                     mixed ? P->Cinv32.p : nullptr, P->vgp.p, P->gp.p, P->Dp.p, P->errflag.p);
+  hipLaunchKernelGGL(k_camera_blocks, dim3(P->n_cam), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->obs_pt.p,
+                     P->n_obs_pad, P->F.p, P->E.p, P->fres.p, P->Cinv.p, P->vgp.p, o->lambda, D, P->A.p,
+                     mixed ? P->A32.p : nullptr, P->Dc.p, P->b.p, P->gc.p, P->Scc.p, P->Sinv.p,
+                     mixed ? P->Sinv32.p : nullptr, P->errflag.p);
+  BA_LAUNCH_CHECK();
+  check_errflag(P, s, "normal blocks");
+  const double tjac = tj.ms();
+  P->have_mixed = mixed;
+  P->prepared = true;
+  Timer ts(s);
+  if (o->precond == BA_PC_MULTIGRID) mg_setup(P, o, cams, mixed, s);
+  const double tset = ts.ms();
+  if (st) {
+    st->t_jacobian_ms = tjac;
+    st->t_setup_ms = tset;
+    st->levels = (int)P->levels.size();
+    for (size_t l = 0; l < P->levels.size() && l < 16; ++l) st->nodes[l] = P->levels[l].n;
+  }
+}
+
+// ---------------------------------------------------------------- PCG
+
+template <class T>
+struct PcgVecs { T *x, *r, *z, *p, *q; };
+
+struct PcgOut {
+  int iters = 0;
+  double rr = 0, bb = 0;
+  bool converged = false;
+  bool breakdown = false;
+};
+
+template <class T>
+static PcgOut pcg_run(ba_plan* P, const ba_opts* o, const T* b, PcgVecs<T> v, double rtol, int max_iter,
+                      hipStream_t s) {
+  Scratch& W = *P->scratch;
+  PcgScal* sc = W.scal.p;
+  const int* done = &sc->done;
+  const int n = W.n;
+  const int g = red_grid(n);
+  hipLaunchKernelGGL((k_pcg_start<T>), dim3(g), dim3(256), 0, s, n, b, v.x, v.r, v.p, W.partial.p, sc);
+  precond_apply<T>(P, o, v.r, v.z, nullptr, s);
+  hipLaunchKernelGGL((k_dot<DOT_INIT, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.r, (const T*)v.z, W.partial.p,
+                     sc, (double*)nullptr);
+  const double rtol2 = rtol * rtol;
+  PcgOut out;
+  for (int it = 0; it < max_iter; ++it) {
+    hipLaunchKernelGGL((k_pcg_p_Ap<T>), dim3(grid_of<T>(9 * P->n_cam, 252 / 9 * 9)), dim3(256), 0, s, P->n_cam,
+                       (const T*)v.z, v.p, A_of<T>(P), v.q, (const PcgScal*)sc);
+    if (sizeof(T) == 8)
+      hipLaunchKernelGGL(k_schur_tiles<double>, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
+                         P->tile_coff.p, P->tile_cams.p, P->obs_slot.p, P->F.p, P->E.p, P->n_obs_pad, P->Cinv.p,
+                         (const double*)v.p, (double*)v.q, done);
+    else
+      hipLaunchKernelGGL(k_schur_tiles<float>, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
+                         P->tile_coff.p, P->tile_cams.p, P->obs_slot.p, P->F32.p, P->E32.p, P->n_obs_pad,
+                         P->Cinv32.p, (const float*)v.p, (float*)v.q, done);
+    hipLaunchKernelGGL((k_dot<DOT_ALPHA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, W.partial.p,
+                       sc, (double*)nullptr);
+    hipLaunchKernelGGL((k_pcg_xr<T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, v.x, v.r,
+                       W.partial.p, sc, rtol2);
+    precond_apply<T>(P, o, v.r, v.z, done, s);
+    hipLaunchKernelGGL((k_dot<DOT_BETA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.r, (const T*)v.z, W.partial.p,
+                       sc, (double*)nullptr);
+    if ((it + 1) % o->check_every == 0 || it + 1 == max_iter) {
+      BA_HIP(hipMemcpyAsync(W.h_scal, sc, sizeof(PcgScal), hipMemcpyDeviceToHost, s));
+      BA_HIP(hipStreamSynchronize(s));
+      if (W.h_scal->done) break;
+    }
+  }
+  BA_LAUNCH_CHECK();
+  BA_HIP(hipMemcpyAsync(W.h_scal, sc, sizeof(PcgScal), hipMemcpyDeviceToHost, s));
+  BA_HIP(hipStreamSynchronize(s));
+  out.iters = W.h_scal->iters;
+  out.rr = W.h_scal->rr;
+  out.bb = W.h_scal->bb;
+  out.breakdown = W.h_scal->flag != 0;
+  out.converged = W.h_scal->done && !out.breakdown;
+  return out;
+}
+
+// Solve S x = b (b: FP64 device [n_cam*9]) into W.x; returns status and fills stats.
+static ba_status solve_camera_system(ba_plan* P, const ba_opts* o, const double* b, ba_stats* st, hipStream_t s) {
+  Scratch& W = *P->scratch;
+  const int n = W.n;
+  ba_status status = BA_OK;
+  if (o->precision == BA_FP64) {
+    PcgOut r = pcg_run<double>(P, o, b, PcgVecs<double>{W.x.p, W.r.p, W.z.p, W.p.p, W.q.p}, o->rtol, o->max_iter, s);
+    BA_CHECK(!r.breakdown, BA_ERR_NOT_SPD, "PCG breakdown: the operator or preconditioner is not SPD");
+    if (st) {
+      st->iters = r.iters;
+      st->rel_res = r.bb > 0 ? std::sqrt(r.rr / r.bb) : 0.0;
+    }
+    if (!r.converged) status = BA_NOT_CONVERGED;
+  } else {
+    // FP64 iterative refinement around FP32 PCG
+    BA_HIP(hipMemsetAsync(W.x.p, 0, n * sizeof(double), s));
+    BA_HIP(hipMemcpyAsync(W.t.p, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));   // t = residual
+    const double bb = plain_dot(P, n, b, b, s);
+    double rr = bb;
+    int iters = 0, ref = 0;
+    bool conv = bb == 0.0;
+    for (; ref < o->max_refine && !conv; ++ref) {
+      convert(n, W.t.p, W.fb.p, s);
+      PcgOut r = pcg_run<float>(P, o, W.fb.p, PcgVecs<float>{W.fx.p, W.fr.p, W.fz.p, W.fp.p, W.fq.p}, o->inner_rtol,
+                                o->max_iter, s);
+      BA_CHECK(!r.breakdown, BA_ERR_NOT_SPD, "PCG breakdown in an FP32 inner solve");
+      iters += r.iters;
+      hipLaunchKernelGGL(k_add_f32, dim3(grid_of<double>(n)), dim3(256), 0, s, n, W.fx.p, W.x.p);
+      schur_apply_dev<double>(P, W.x.p, W.q.p, nullptr, s);
+      hipLaunchKernelGGL(k_axpby, dim3(grid_of<double>(n)), dim3(256), 0, s, n, b, -1.0, W.q.p, W.t.p);
+      rr = plain_dot(P, n, W.t.p, W.t.p, s);
+      conv = rr <= o->rtol * o->rtol * bb;
+    }
+    if (st) {
+      st->iters = iters;
+      st->refine_steps = ref;
+      st->rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    }
+    if (!conv) status = BA_NOT_CONVERGED;
+  }
+  return status;
+}
+
+static ba_status solve(ba_plan* P, const ba_opts* o, double* delta_cam, double* delta_pt, ba_stats* st,
+                       hipStream_t s) {
+  BA_CHECK(o->precond == BA_PC_BLOCK_JACOBI || P->prepared_mg, BA_ERR_ARG,
+           "the step was prepared without the multigrid preconditioner");
+  BA_CHECK(o->precision == BA_FP64 || P->have_mixed, BA_ERR_ARG, "the step was prepared without BA_MIXED");
+  Timer ts(s);
+  Scratch& W = *P->scratch;
+  const ba_status status = solve_camera_system(P, o, P->b.p, st, s);
+  BA_HIP(hipMemcpyAsync(delta_cam, W.x.p, (size_t)W.n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // back-substitution delta_p = C^-1 (-g_p - W^T delta_c)
+  hipLaunchKernelGGL(k_recover_points, dim3(grid_of<double>(P->n_pt)), dim3(256), 0, s, P->n_pt, P->pt_off.p,
+                     P->pt_orig.p, P->obs_cam.p, P->n_obs_pad, P->F.p, P->E.p, P->Cinv.p, P->gp.p, -1.0, W.x.p,
+                     delta_pt);
+  BA_LAUNCH_CHECK();
+  const double t = ts.ms();
+  if (st) st->t_solve_ms = t;
+  return status;
+}
+
+// ---------------------------------------------------------------- inspection
+
+static void level_data(const ba_plan* Pc, int l, int what, double* out, hipStream_t s) {
+  ba_plan* P = const_cast<ba_plan*>(Pc);
+  Level& L = P->levels[l];
+  const int nl = (int)P->levels.size();
+  const size_t nv = (size_t)L.n * L.bs;
+  switch (what) {
+    case 0: {
+      BA_CHECK(nv <= 16384, BA_ERR_LIMIT, "level too large for a dense copy");
+      BA_HIP(hipMemsetAsync(out, 0, nv * nv * sizeof(double), s));
+      hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(L.nnz * L.bs * L.bs)), dim3(256), 0, s, L.n, L.bs,
+                         (int)nv, L.row_of.p, L.col.p, L.nnz, L.S.p, out);
+      break;
+    }
+    case 1:
+      BA_CHECK(l + 1 < nl, BA_ERR_ARG, "the coarsest level has no prolongator");
+      BA_HIP(hipMemcpyAsync(out, L.P.p, L.P.bytes(), hipMemcpyDeviceToDevice, s));
+      break;
+    case 2:
+      BA_HIP(hipMemcpyAsync(out, L.K.p, L.K.bytes(), hipMemcpyDeviceToDevice, s));
+      break;
+    case 3:
+      BA_CHECK(l + 1 < nl, BA_ERR_ARG, "the coarsest level has no smoother");
+      BA_HIP(hipMemcpyAsync(out, lvDinv<double>(P, l), (size_t)L.n * L.bs * L.bs * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+      break;
+    case 4:
+      BA_HIP(hipMemcpyAsync(out, &L.lmax, sizeof(double), hipMemcpyHostToDevice, s));
+      break;
+    case 5:
+      BA_CHECK(l + 1 == nl, BA_ERR_ARG, "only the coarsest level has an inverse");
+      BA_HIP(hipMemcpy2DAsync(out, nv * sizeof(double), L.inv.p, (size_t)L.nd * sizeof(double), nv * sizeof(double),
+                              nv, hipMemcpyDeviceToDevice, s));
+      break;
+    default:
+      BA_CHECK(false, BA_ERR_ARG, "bad `what`");
+  }
+  BA_LAUNCH_CHECK();
+  BA_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace bamg
+
+#include "backward.cpp"

@@ -1,0 +1,210 @@
+"""GPU parity: each stage of the LM step against the CPU oracle (same seeded
+inputs), through the C ABI. Sizes span several tiles and a ragged tail."""
+import numpy as np
+import pytest
+
+from oracle import camera, multigrid as omg, step as ostep
+from scenes import tiny_scene
+from tests._fixtures import scene
+from tests._gpu import host, inputs, plan_for, rel
+
+# Forward-error bounds: a sum of products computed in FP64 in any order differs
+# from the exact value by at most n u sum|terms| (u = 2^-53, n = terms in the
+# longest chain). Both sides round, so their difference is bounded by twice
+# that; TOL_U = 1e-12 covers n up to ~4000 terms with margin.
+TOL_U = 1e-12
+
+
+def schur_abs(nrm, x):
+    """|A||x| + |F|^T(|E|(|C^-1|(|E|^T(|F||x|)))): the sum of magnitudes of the
+    terms of S x, which bounds the rounding error of any evaluation order."""
+    from oracle.normal import block_sum
+    xa = np.abs(np.asarray(x)).reshape(nrm.n_cam, 9)
+    F, E = np.abs(nrm.F), np.abs(nrm.E)
+    s = np.einsum("nkj,nj->nk", F, xa[nrm.obs_cam])
+    z = block_sum(nrm.obs_pt, np.einsum("nki,nk->ni", E, s), nrm.n_pt)
+    u = np.einsum("pij,pj->pi", np.abs(nrm.Cinv), z)
+    w = np.einsum("nkj,nj->nk", E, u[nrm.obs_pt])
+    y = block_sum(nrm.obs_cam, np.einsum("nki,nk->ni", F, w), nrm.n_cam)
+    return np.einsum("cij,cj->ci", np.abs(nrm.A), xa) + y
+
+
+def rhs_abs(nrm):
+    """Magnitude bound of the terms of b = -g_c + W C^-1 g_p."""
+    from oracle.normal import block_sum
+    F, E, f = np.abs(nrm.F), np.abs(nrm.E), np.abs(nrm.f)
+    gc = block_sum(nrm.obs_cam, np.einsum("nki,nk->ni", F, f), nrm.n_cam)
+    gp = block_sum(nrm.obs_pt, np.einsum("nki,nk->ni", E, f), nrm.n_pt)
+    v = np.einsum("pij,pj->pi", np.abs(nrm.Cinv), gp)
+    Y = np.einsum("nki,nkj->nij", F, E)
+    return gc + block_sum(nrm.obs_cam, np.einsum("nij,nj->ni", Y, v[nrm.obs_pt]), nrm.n_cam)
+
+
+def schur_abs_dense(nrm):
+    """Entrywise magnitude bound of the terms of S = A - F^T E C^-1 E^T F."""
+    import scipy.sparse as sp
+    n = nrm.obs_cam.shape[0]
+    Yabs = np.einsum("nki,nkj->nij", np.abs(nrm.F), np.abs(nrm.E))
+    rows = np.broadcast_to((9 * nrm.obs_cam)[:, None, None] + np.arange(9)[None, :, None], (n, 9, 3))
+    cols = np.broadcast_to((3 * nrm.obs_pt)[:, None, None] + np.arange(3)[None, None, :], (n, 9, 3))
+    W = sp.csr_matrix((Yabs.ravel(), (rows.ravel(), cols.ravel())), shape=(9 * nrm.n_cam, 3 * nrm.n_pt))
+    from oracle.normal import _blockdiag
+    return (_blockdiag(np.abs(nrm.A)) + W @ _blockdiag(np.abs(nrm.Cinv)) @ W.T).toarray()
+
+
+pytestmark = pytest.mark.gpu
+
+SCENES = ["ring64", "city200"]
+
+
+def _sc(name):
+    if name.startswith("tiny"):
+        return tiny_scene(9, 120, seed=7, k_min=2, k_max=6)
+    return scene(name)
+
+
+@pytest.mark.parametrize("name", SCENES + ["tiny"])
+def test_residual_and_jacobian(name):
+    sc = _sc(name)
+    plan, _ = plan_for(sc)
+    f, F, E = plan.eval_jacobian(*inputs(sc))
+    f_ref = camera.residuals(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    F_ref, E_ref = camera.jacobian_blocks(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt)
+    # FP64 on both sides: agreement to a few ulps of the block scale
+    assert np.abs(host(f) - f_ref).max() <= 1e-9 * max(1.0, np.abs(f_ref).max())
+    for got, ref in ((host(F), F_ref), (host(E), E_ref)):
+        scale = np.abs(ref).max(axis=(1, 2), keepdims=True)
+        assert (np.abs(got - ref) / scale).max() <= 1e-11
+
+
+@pytest.mark.parametrize("name", SCENES + ["tiny"])
+def test_normal_blocks(name):
+    sc = _sc(name)
+    plan, opts = plan_for(sc, precond="bj")
+    plan.prepare(*inputs(sc))
+    b, Cinv, Scc = (host(t) for t in plan.step_blocks())
+    nrm = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    assert np.all(np.abs(b - nrm.rhs().reshape(-1, 9)) <= TOL_U * rhs_abs(nrm))
+    # C^-1 of a 3x3 block: error ~ u cond(C) |C^-1|
+    condC = np.linalg.cond(nrm.C)
+    assert np.all(np.abs(Cinv - nrm.Cinv) <= 1e-13 * condC[:, None, None] * np.abs(nrm.Cinv).max(axis=(1, 2), keepdims=True))
+    B = nrm.block_jacobi_blocks()
+    # S_cc = A - sum Y C^-1 Y^T: bound by the magnitudes of its terms
+    from oracle.normal import block_sum
+    Babs = np.abs(nrm.A) + block_sum(nrm.obs_cam, np.einsum("nij,njk,nlk->nil", np.abs(nrm.Y),
+                                                           np.abs(nrm.Cinv[nrm.obs_pt]), np.abs(nrm.Y)), nrm.n_cam)
+    assert np.all(np.abs(Scc - B) <= TOL_U * Babs)
+
+
+@pytest.mark.parametrize("name", SCENES + ["tiny"])
+def test_implicit_schur_product(name):
+    sc = _sc(name)
+    plan, _ = plan_for(sc, precond="bj", precision="mixed")
+    plan.prepare(*inputs(sc), opts=plan.opts)
+    nrm = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    rng = np.random.default_rng(0)
+    import torch
+    for _ in range(3):
+        x = rng.normal(size=(sc.n_cam, 9))
+        xt = torch.as_tensor(x, device="cuda")
+        y64 = host(plan.schur_apply(xt, "fp64"))
+        y32 = host(plan.schur_apply(xt, "mixed"))
+        ref = nrm.S_apply(x).reshape(-1, 9)
+        bound = schur_abs(nrm, x)
+        # FP64: any summation order stays within the forward-error bound;
+        # FP32 operands and accumulation: the same bound with u = 2^-24
+        assert np.all(np.abs(y64 - ref) <= TOL_U * bound)
+        assert np.all(np.abs(y32 - ref) <= 1e-4 * bound)
+
+
+@pytest.mark.parametrize("name", SCENES)
+@pytest.mark.parametrize("pc", ["bj", "mg"])
+def test_step_fp64(name, pc):
+    sc = _sc(name)
+    kw = dict(coarse_max_nodes=16) if pc == "mg" else {}
+    plan, opts = plan_for(sc, precond=pc, rtol=1e-10, **kw)
+    dc, dp, st = plan.lm_step(*inputs(sc))
+    ref = ostep.lm_step(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv, method=pc, rtol=1e-10,
+                        opts=omg.MGOptions(coarse_max_nodes=16))
+    full = ostep.lm_step(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv, method="full")
+    print(f"[gpu] {name} {pc}: iters {st.iters} (oracle {ref.iters}) levels {st.nodes} "
+          f"rel_res {st.rel_res:.2e} err_vs_oracle {rel(host(dc), ref.delta_c):.2e} "
+          f"err_vs_direct {rel(host(dc), full.delta_c):.2e}", flush=True)
+    assert st.converged and st.rel_res <= 1e-10
+    # the oracle's own residual of the GPU step
+    nrm = ref.normal
+    r = nrm.rhs() - nrm.S_apply(host(dc).ravel())
+    # the GPU's S and b differ from the oracle's by at most the rounding bounds
+    slack = TOL_U * np.linalg.norm(schur_abs(nrm, host(dc)) + rhs_abs(nrm))
+    assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(nrm.rhs()) + slack
+    assert abs(st.iters - ref.iters) <= 2
+    assert rel(host(dc), ref.delta_c) <= 1e-6
+    assert rel(host(dp), ref.delta_p) <= 1e-6
+
+
+def test_hierarchy_structure_matches_oracle():
+    sc = scene("city200")
+    plan, _ = plan_for(sc, precond="mg", coarse_max_nodes=16)
+    nrm = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    lev = ostep.hierarchy_for(nrm, sc.cams, sc.obs_cam, sc.obs_pt, omg.MGOptions(coarse_max_nodes=16))
+    nodes = plan.mg_levels()
+    assert nodes == [l.W.shape[0] for l in lev]
+    for l in range(len(lev)):
+        rp, col, val = (host(t) for t in plan.mg_covisibility(l))
+        W = lev[l].W.tocsr()
+        W.sort_indices()
+        assert np.array_equal(rp, W.indptr) and np.array_equal(col, W.indices)
+        assert np.array_equal(val, W.data)
+        if l + 1 < len(lev):
+            assert np.array_equal(host(plan.mg_aggregates(l)), lev[l].agg)
+
+
+def test_hierarchy_numeric_matches_oracle():
+    sc = scene("city200")
+    import paper_2007_01941_amd as bamg
+    plan, opts = plan_for(sc, precond="mg", coarse_max_nodes=16)
+    failure = None
+    try:
+        plan.prepare(*inputs(sc), opts=opts)
+    except bamg.BAError as e:       # keep inspecting: the hierarchy data stays readable
+        failure = e
+        print(f"[gpu] prepare failed: {e}", flush=True)
+    nrm = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    lev = ostep.hierarchy_for(nrm, sc.cams, sc.obs_cam, sc.obs_pt, omg.MGOptions(coarse_max_nodes=16))
+    nl = len(lev)
+    for l in range(nl):
+        Sl = host(plan.mg_level_data(l, "operator"))
+        ev = np.linalg.eigvalsh(0.5 * (Sl + Sl.T))
+        print(f"[gpu] level {l}: asym {np.abs(Sl - Sl.T).max() / np.abs(Sl).max():.2e} "
+              f"eig [{ev[0]:.3e}, {ev[-1]:.3e}] oracle eig_min {np.linalg.eigvalsh(lev[l].S.toarray())[0]:.3e}",
+              flush=True)
+    assert failure is None
+    # level-0 explicit S equals the oracle's S
+    S0 = host(plan.mg_level_data(0, "operator"))
+    S0_ref = lev[0].S.toarray()
+    assert np.all(np.abs(S0 - S0_ref) <= TOL_U * schur_abs_dense(nrm))
+    for l in range(nl - 1):
+        K = host(plan.mg_level_data(l, "K")).reshape(-1, 16)
+        P = host(plan.mg_level_data(l, "P"))
+        Pm = lev[l].P.toarray()
+        # P orthonormal, exactly represents K
+        nagg = lev[l].n_agg
+        Pd = np.zeros_like(Pm)
+        bs = lev[l].bs
+        for i in range(P.shape[0]):
+            a = lev[l].agg[i]
+            Pd[i * bs:(i + 1) * bs, a * 16:(a + 1) * 16] = P[i]
+        np.testing.assert_allclose(Pd.T @ Pd, np.eye(16 * nagg), atol=1e-10)
+        np.testing.assert_allclose(Pd @ (Pd.T @ K), K, atol=1e-9 * np.abs(K).max())
+        # coarse operator is the Galerkin product of the GPU's own P and S_l
+        Sl = host(plan.mg_level_data(l, "operator"))
+        Sc = host(plan.mg_level_data(l + 1, "operator"))
+        np.testing.assert_allclose(Sc, Pd.T @ Sl @ Pd, atol=1e-9 * np.abs(Sc).max())
+        # lambda_max from the same Lanczos process
+        lm = host(plan.mg_level_data(l, "lmax"))[0]
+        assert abs(lm - lev[l].lmax) <= 1e-6 * lev[l].lmax
+    # coarse inverse (FP64 MFMA Cholesky) against the dense inverse
+    Sc = host(plan.mg_level_data(nl - 1, "operator"))
+    inv = host(plan.mg_level_data(nl - 1, "coarse_inverse"))
+    ref = np.linalg.inv(Sc)
+    assert np.abs(inv - ref).max() <= 1e-8 * np.abs(ref).max()
