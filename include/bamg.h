@@ -11,7 +11,8 @@
  *     (layout, per-step buffers, hierarchy) until ba_plan_destroy.
  *   - `stream` is a hipStream_t passed as void*; all device work is enqueued on
  *     it. Calls that return step results block until those results are ready
- *     (the solver reads its convergence test back to the host).
+ *     (the solver reads its convergence test back to the host); the two
+ *     operator applications (ba_schur_apply, ba_precond_apply) do not block.
  *   - A negative status means nothing was written to the outputs; a message is
  *     available from ba_last_error() on the calling thread. BA_NOT_CONVERGED
  *     means the outputs hold the last iterate and the statistics are valid.
@@ -74,6 +75,9 @@ typedef struct {
                                bytes moved per application; PCG itself always uses the implicit form */
   int32_t freeze_damping_in_grad; /* backward: 1 = treat D as a constant, 0 = differentiate D(x) */
   int32_t check_every;      /* PCG: read the convergence flag back every N iterations, default 4 */
+  double coarse_shift;      /* coarsest direct solve factors s S s + coarse_shift I with
+                               s = diag(S)^-1/2, default 1e-10 (keeps it SPD where the
+                               coarsest operator is singular to FP64 rounding) */
   int32_t reserved[8];
 } ba_opts;
 
@@ -162,12 +166,13 @@ ba_status ba_step_solve(ba_plan* p, const ba_opts* o, double* delta_cam, double*
 /* y = S x with the implicit product A x - F^T (E (C^-1 (E^T (F x))))
  * (Section 3.6) of the prepared step. precision BA_FP64 or BA_MIXED (FP32
  * operands and accumulation; x, y are still FP64 at this boundary).
- * x, y: [n_cam][9]. */
+ * x, y: [n_cam][9]. Enqueued on `stream`; returns without waiting. */
 ba_status ba_schur_apply(ba_plan* p, int32_t precision, const double* x, double* y,
                          void* stream);
 
 /* z = M r: one preconditioner application of the prepared step (block Jacobi,
- * or one V-cycle of Algorithm 1 from a zero initial guess). [n_cam][9]. */
+ * or one V-cycle of Algorithm 1 from a zero initial guess). [n_cam][9].
+ * Enqueued on `stream`; returns without waiting. */
 ba_status ba_precond_apply(ba_plan* p, const ba_opts* o, int32_t precision, const double* r,
                            double* z, void* stream);
 

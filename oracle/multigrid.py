@@ -25,6 +25,12 @@ Readings where the paper is silent:
     published by Steele, Lea and Flood (2014) and Vigna: z = x + 0x9E3779B97F4A7C15,
     z = (z ^ z>>30) * 0xBF58476D1CE4E5B9, z = (z ^ z>>27) * 0x94D049BB133111EB,
     out = z ^ z>>31.
+  * Coarsest direct solve: Cholesky of the equilibrated matrix s S s + eps I
+    with s = diag(S)^-1/2 and eps = 1e-10 (the same inverse up to eps; the
+    shift is insurance that keeps the factorization positive definite when
+    the coarsest Galerkin operator is nearly singular to FP64 rounding, which
+    happens when some observation is nearly perpendicular to its camera's
+    axis and blows up its Jacobian).
   * Coarsening stops when a level has <= 128 nodes, or the next level would keep
     more than 0.9 of the nodes, or at 12 levels.
   * PCG: Saad Algorithm 9.1 from x0 = 0; stop when ||r||_2 <= rtol ||b||_2 on the
@@ -54,6 +60,7 @@ class MGOptions:
     coarse_max_nodes: int = 128
     max_levels: int = 12
     min_ratio: float = 0.9
+    coarse_shift: float = 1e-10
 
 
 def splitmix64(x):
@@ -204,7 +211,8 @@ class Level:
     Kc: np.ndarray = None
     Dinv: np.ndarray = None
     lmax: float = 0.0
-    chol: np.ndarray = None  # coarsest level: dense Cholesky factor
+    chol: np.ndarray = None  # coarsest level: Cholesky factor of the equilibrated matrix
+    cscale: np.ndarray = None  # coarsest level: equilibration diag(S)^-1/2
 
 
 def build_hierarchy(S0, K0, W0, opts: MGOptions = MGOptions(), apply_S0=None):
@@ -230,7 +238,12 @@ def build_hierarchy(S0, K0, W0, opts: MGOptions = MGOptions(), apply_S0=None):
     for l, lev in enumerate(levels):
         if l == len(levels) - 1:
             Sd = lev.S.toarray() if sp.issparse(lev.S) else lev.S
-            lev.chol = np.linalg.cholesky(Sd)
+            # direct solve on the equilibrated matrix s S s, s = diag(S)^-1/2
+            # (same inverse; keeps the factorization accurate when the camera
+            # parameters live on very different scales)
+            lev.cscale = 1.0 / np.sqrt(np.diag(Sd))
+            Ss = Sd * lev.cscale[:, None] * lev.cscale[None, :]
+            lev.chol = np.linalg.cholesky(Ss + opts.coarse_shift * np.eye(Ss.shape[0]))
         else:
             Dblk = block_diagonal(lev.S, lev.bs)
             lev.Dinv = np.linalg.inv(Dblk)
@@ -244,8 +257,8 @@ def vcycle(levels, b, opts: MGOptions = MGOptions(), l=0):
     """Algorithm 1 with x = 0 on entry."""
     lev = levels[l]
     if l == len(levels) - 1:
-        y = solve_triangular(lev.chol, b, lower=True)
-        return solve_triangular(lev.chol.T, y, lower=False)
+        y = solve_triangular(lev.chol, lev.cscale * b, lower=True)
+        return lev.cscale * solve_triangular(lev.chol.T, y, lower=False)
     A = (lambda v, S=lev.S: S @ v)
     x, r = chebyshev_pre(A, lev.Dinv, b, lev.lmax, opts.cheb_degree, opts.cheb_lo, opts.cheb_hi)
     rc = lev.P.T @ r

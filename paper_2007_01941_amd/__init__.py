@@ -229,7 +229,6 @@ class LMStep(torch.autograd.Function):
         dc, dp, st = plan.lm_step(cams.detach(), pts.detach(), uv.detach(), opts=opts)
         ctx.plan, ctx.opts = plan, opts
         ctx.save_for_backward(cams, pts, uv, dc, dp)
-        ctx.mark_non_differentiable()
         return dc, dp
 
     @staticmethod

@@ -41,7 +41,8 @@ class _Opts(ctypes.Structure):
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
                 ("min_coarsen_ratio", ctypes.c_double),
                 ("level0_op", ctypes.c_int32), ("freeze_damping_in_grad", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("reserved", ctypes.c_int32 * 8)]
+                ("check_every", ctypes.c_int32), ("coarse_shift", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class _Stats(ctypes.Structure):
@@ -72,6 +73,7 @@ class Options:
     level0_op: str = "auto"          # "auto" | "implicit" | "explicit"
     freeze_damping_in_grad: bool = False
     check_every: int = 4
+    coarse_shift: float = 1e-10
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -85,6 +87,7 @@ class Options:
         o.level0_op = {"auto": OP_AUTO, "implicit": OP_IMPLICIT, "explicit": OP_EXPLICIT}[self.level0_op]
         o.freeze_damping_in_grad = int(self.freeze_damping_in_grad)
         o.check_every = self.check_every
+        o.coarse_shift = self.coarse_shift
         return o
 
 

@@ -140,6 +140,7 @@ ba_status ba_opts_default(ba_opts* o) {
   o->level0_op = BA_OP_AUTO;
   o->freeze_damping_in_grad = 0;
   o->check_every = 4;
+  o->coarse_shift = 1e-10;
   return BA_OK;
 }
 
@@ -157,6 +158,7 @@ static void validate_opts(const ba_opts* o) {
   BA_CHECK(o->max_levels >= 1 && o->max_levels <= 16, BA_ERR_ARG, "max_levels must be in [1, 16]");
   BA_CHECK(o->cheb_hi > o->cheb_lo && o->cheb_lo > 0.0, BA_ERR_ARG, "bad Chebyshev interval");
   BA_CHECK(o->check_every >= 1, BA_ERR_ARG, "check_every must be >= 1");
+  BA_CHECK(o->coarse_shift >= 0.0 && o->coarse_shift < 1.0, BA_ERR_ARG, "coarse_shift must be in [0, 1)");
   BA_CHECK(o->precision != BA_MIXED || (o->max_refine >= 1 && o->inner_rtol > 0.0 && o->inner_rtol < 1.0),
            BA_ERR_ARG, "bad refinement options");
 }
@@ -197,6 +199,7 @@ ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32
 void ba_plan_destroy(ba_plan* p) {
   if (!p) return;
   delete p->scratch;
+  delete p->bwd;
   delete p;
 }
 
@@ -266,7 +269,6 @@ ba_status ba_schur_apply(ba_plan* P, int32_t precision, const double* x, double*
     schur_apply_dev<double>(P, x, y, nullptr, s);
   }
   BA_LAUNCH_CHECK();
-  BA_HIP(hipStreamSynchronize(s));
   BA_API_END
 }
 
@@ -277,7 +279,6 @@ ba_status ba_precond_apply(ba_plan* P, const ba_opts* o, int32_t precision, cons
   validate_opts(o);
   BA_CHECK(P->prepared, BA_ERR_ARG, "ba_step_prepare has not been called");
   precond_apply_fp64boundary(P, o, precision, r, z, (hipStream_t)stream);
-  BA_HIP(hipStreamSynchronize((hipStream_t)stream));
   BA_API_END
 }
 

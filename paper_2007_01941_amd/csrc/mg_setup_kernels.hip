@@ -280,6 +280,27 @@ __global__ void k_bsr_to_dense(int n, int bs, int nd, const int32_t* __restrict_
   }
 }
 
+// Equilibration of the coarse matrix: s_i = D_ii^-1/2 (k_dense_diag), then
+// A <- s A s + shift I before the factorization and inv <- s inv s after it.
+__global__ void k_dense_diag(int nd, const double* __restrict__ A, double* __restrict__ s, uint32_t* err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nd) return;
+  const double d = A[(size_t)i * nd + i];
+  if (!(d > 0.0)) {
+    atomicOr(err, ERRF_NOT_SPD);
+    s[i] = 1.0;
+  } else {
+    s[i] = 1.0 / sqrt(d);
+  }
+}
+
+__global__ void k_dense_scale(int nd, double* __restrict__ A, const double* __restrict__ s, double shift) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nd * nd) return;
+  const int64_t r = idx / nd, c = idx % nd;
+  A[idx] = A[idx] * s[r] * s[c] + (r == c ? shift : 0.0);
+}
+
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Orders the LDS/global accesses of the lanes of one wave (no block barrier).

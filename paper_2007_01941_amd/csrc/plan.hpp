@@ -54,7 +54,8 @@ struct Level {
   DBuf<float> fb, fx, fr, fd, ft;
 };
 
-struct Scratch;  // defined in api.cpp
+struct Scratch;   // defined in api.cpp
+struct Backward;  // defined in backward.cpp
 
 }  // namespace bamg
 
@@ -110,4 +111,5 @@ struct ba_plan {
   bool have_mixed = false;
   double lambda = 1e-4;
   bamg::Scratch* scratch = nullptr;
+  bamg::Backward* bwd = nullptr;
 };

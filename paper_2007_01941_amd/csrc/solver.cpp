@@ -375,10 +375,20 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   const int64_t tot = Lc.nnz * Lc.bs * Lc.bs + Lc.nd;
   hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(tot)), dim3(256), 0, s, Lc.n, Lc.bs, Lc.nd, Lc.row_of.p,
                      Lc.col.p, Lc.nnz, Lc.S.p, Lc.dense.p);
-  DBuf<double> linv;
+  DBuf<double> linv, scl;
   linv.alloc((size_t)(Lc.nd / 16) * 256);
+  scl.alloc(Lc.nd);
+  const int64_t nd2 = (int64_t)Lc.nd * Lc.nd;
+  // factor the equilibrated matrix s S s + eps I (s = diag^-1/2, eps = coarse_shift):
+  // the coarsest Galerkin operator of a street-view scene is singular to FP64
+  // rounding in its near-nullspace, and the shift keeps the coarse solve SPD
+  hipLaunchKernelGGL(k_dense_diag, dim3(grid_of<double>(Lc.nd)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
+                     P->errflag.p);
+  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
+                     o->coarse_shift);
   hipLaunchKernelGGL(k_dense_spd_inverse, dim3(1), dim3(64 * CHOL_WAVES), 0, s, Lc.nd, Lc.dense.p, Lc.inv.p, linv.p,
                      P->errflag.p);
+  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.inv.p, scl.p, 0.0);
   BA_LAUNCH_CHECK();
   check_errflag(P, s, "coarse Cholesky");
   if (mixed) {

@@ -106,7 +106,17 @@ def _finish(name, rng, centers, dirs, X, obs_cam, obs_pt, sigma_px=1.0, sigma_pa
     if np.any(z >= 0):
         raise RuntimeError("synthetic scene has a point behind an observing camera")
     uv = uv_clean + rng.normal(0.0, sigma_px, uv_clean.shape)
-    cams = cams_true + rng.normal(0.0, sigma_par, cams_true.shape)
+    # Initial values: every parameter perturbed by N(0, sigma_par). The pose is
+    # perturbed about the camera's own centre (a rotation of that size in the
+    # camera frame, the centre moved by that many metres); adding noise to w
+    # with t held fixed would swing each camera about the world origin by
+    # sigma_par times its distance from it.
+    dR = Rotation.from_rotvec(rng.normal(0.0, sigma_par, (n_cam, 3))).as_matrix()
+    Rp = np.einsum("nij,njk->nik", dR, Rm)
+    cp = centers + rng.normal(0.0, sigma_par, centers.shape)
+    cams = np.column_stack([Rotation.from_matrix(Rp).as_rotvec(), -np.einsum("nij,nj->ni", Rp, cp),
+                            f + rng.normal(0.0, sigma_par, n_cam), k1 + rng.normal(0.0, sigma_par, n_cam),
+                            k2 + rng.normal(0.0, sigma_par, n_cam)])
     pts = X + rng.normal(0.0, sigma_par, X.shape)
     return Scene(name, cams_true, X.copy(), cams, pts, obs_cam, obs_pt, uv, uv_clean)
 
@@ -203,8 +213,11 @@ def _seg(node, d):
     return (a, b) if a < b else (b, a)
 
 
-def _choose_observers(rng, centers, dirs, X, k_want, max_dist, half_angle_deg, knn=48):
-    """For each point the k nearest cameras that see it (frustum + range)."""
+def _choose_observers(rng, centers, dirs, X, k_want, max_dist, half_angle_deg, knn=48,
+                      min_dist=2.0):
+    """For each point the k nearest cameras that see it (frustum, at least
+    min_dist and at most max_dist away: a point almost on a camera's centre
+    would project anywhere once the parameters are perturbed)."""
     tree = cKDTree(centers)
     dist, idx = tree.query(X, k=knn, distance_upper_bound=max_dist, workers=-1)
     n_cam = centers.shape[0]
@@ -213,6 +226,7 @@ def _choose_observers(rng, centers, dirs, X, k_want, max_dist, half_angle_deg, k
     rel = X[:, None, :] - centers[idx_c]
     cosang = np.einsum("pkj,pkj->pk", rel, dirs[idx_c]) / np.maximum(dist, 1e-12)
     valid &= cosang > math.cos(math.radians(half_angle_deg))
+    valid &= dist >= min_dist
     rank = np.cumsum(valid, axis=1)
     take = valid & (rank <= k_want[:, None])
     n_vis = take.sum(axis=1)

@@ -200,9 +200,22 @@ def test_hierarchy_numeric_matches_oracle():
         Sl = host(plan.mg_level_data(l, "operator"))
         Sc = host(plan.mg_level_data(l + 1, "operator"))
         np.testing.assert_allclose(Sc, Pd.T @ Sl @ Pd, atol=1e-9 * np.abs(Sc).max())
-        # lambda_max from the same Lanczos process
+        # lambda_max from the same Lanczos process: identical basis on level 0;
+        # above it, rank-deficient aggregates make the extra columns of P
+        # non-unique, so the 5-step estimate is compared by its invariants
         lm = host(plan.mg_level_data(l, "lmax"))[0]
-        assert abs(lm - lev[l].lmax) <= 1e-6 * lev[l].lmax
+        if l == 0:
+            assert abs(lm - lev[l].lmax) <= 1e-8 * lev[l].lmax
+        else:
+            Dinv = host(plan.mg_level_data(l, "Dinv"))
+            Dm = np.zeros_like(Sl)
+            for i in range(Dinv.shape[0]):
+                Dm[i * bs:(i + 1) * bs, i * bs:(i + 1) * bs] = np.linalg.inv(Dinv[i])
+            Lc = np.linalg.cholesky(Dm)
+            Li = np.linalg.inv(Lc)
+            true = np.linalg.eigvalsh(Li @ Sl @ Li.T)[-1]
+            assert lm <= true * (1 + 1e-10)
+            assert abs(lm - lev[l].lmax) <= 1e-2 * lev[l].lmax
     # coarse inverse (FP64 MFMA Cholesky) against the dense inverse
     Sc = host(plan.mg_level_data(nl - 1, "operator"))
     inv = host(plan.mg_level_data(nl - 1, "coarse_inverse"))

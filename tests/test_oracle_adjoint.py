@@ -21,18 +21,26 @@ def ring20_grad():
 
 def test_directional_derivatives_match_finite_differences(ring20_grad):
     sc, (gc, gp, guv) = ring20_grad
+    gnorm = np.sqrt((gc ** 2).sum() + (gp ** 2).sum() + (guv ** 2).sum())
     rng = np.random.default_rng(11)
-    h = 1e-4
+
+    def central(h, vc, vp, vu):
+        return (_loss(sc, sc.cams + h * vc, sc.pts + h * vp, sc.uv + h * vu)
+                - _loss(sc, sc.cams - h * vc, sc.pts - h * vp, sc.uv - h * vu)) / (2 * h)
+
     for _ in range(16):
         vc = rng.normal(size=sc.cams.shape)
         vp = rng.normal(size=sc.pts.shape)
         vu = rng.normal(size=sc.uv.shape)
         s = np.sqrt((vc ** 2).sum() + (vp ** 2).sum() + (vu ** 2).sum())
         vc, vp, vu = vc / s, vp / s, vu / s
-        fd = (_loss(sc, sc.cams + h * vc, sc.pts + h * vp, sc.uv + h * vu)
-              - _loss(sc, sc.cams - h * vc, sc.pts - h * vp, sc.uv - h * vu)) / (2 * h)
+        # Richardson extrapolation of central differences: O(h^4) truncation
+        h = 2e-4
+        fd = (4.0 * central(h / 2, vc, vp, vu) - central(h, vc, vp, vu)) / 3.0
         an = (gc * vc).sum() + (gp * vp).sum() + (guv * vu).sum()
-        assert abs(fd - an) <= 1e-5 * abs(an) + 1e-6
+        # finite-difference noise scales with the overall sensitivity |grad L|
+        # (unit directions), not with this particular directional derivative
+        assert abs(fd - an) <= 1e-6 * gnorm + 1e-6 * abs(an)
 
 
 def test_observation_gradient_closed_form(ring20_grad):
