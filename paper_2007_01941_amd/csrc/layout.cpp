@@ -207,6 +207,35 @@ static void build_covisibility(ba_plan* P, Level& L, LaunchPass launch, hipStrea
   L.h_col = L.col.download(s);
 }
 
+// Observation pairs of every upper off-diagonal block of the level-0 pattern:
+// for each point (in order) and each pair a < b of its camera-sorted
+// observations, the pair goes to block (camera(a), camera(b)).
+static void build_s0_pairs(ba_plan* P, const Level& L0, hipStream_t s) {
+  const int n_pt = P->n_pt;
+  std::vector<int32_t> cnt(L0.nnz + 1, 0);
+  auto entry = [&](int ci, int cj) {
+    auto b = L0.h_col.begin() + L0.h_rowptr[ci], e = L0.h_col.begin() + L0.h_rowptr[ci + 1];
+    return (int32_t)(std::lower_bound(b, e, cj) - L0.h_col.begin());
+  };
+  int64_t total = 0;
+  for (int q = 0; q < n_pt; ++q)
+    for (int64_t a = P->h_pt_off[q]; a < P->h_pt_off[q + 1]; ++a)
+      for (int64_t b = a + 1; b < P->h_pt_off[q + 1]; ++b) {
+        ++cnt[entry(P->h_obs_cam[a], P->h_obs_cam[b]) + 1];
+        ++total;
+      }
+  BA_CHECK(total < INT32_MAX, BA_ERR_LIMIT, "too many covisible observation pairs");
+  for (int64_t e = 0; e < L0.nnz; ++e) cnt[e + 1] += cnt[e];
+  std::vector<int2> pairs(std::max<int64_t>(1, total));
+  std::vector<int32_t> cur(cnt.begin(), cnt.end() - 1);
+  for (int q = 0; q < n_pt; ++q)
+    for (int64_t a = P->h_pt_off[q]; a < P->h_pt_off[q + 1]; ++a)
+      for (int64_t b = a + 1; b < P->h_pt_off[q + 1]; ++b)
+        pairs[cur[entry(P->h_obs_cam[a], P->h_obs_cam[b])]++] = make_int2((int)a, (int)b);
+  P->s0_ptr.upload(cnt, s);
+  P->s0_pairs.upload(pairs, s);
+}
+
 static void aggregate_level(ba_plan* P, Level& L, int cap, hipStream_t s) {
   const int n = L.n;
   DBuf<int32_t> agg, nagg;
@@ -247,6 +276,7 @@ static void build_hierarchy(ba_plan* P, const ba_opts* o, hipStream_t s) {
                            P->pt_off.p, P->obs_cam.p, nnz, wd, rp, col, val, P->errflag.p);
     }, s);
     finish_level_pattern(L0, s);
+    build_s0_pairs(P, L0, s);
   }
   for (;;) {
     const int l = (int)P->levels.size() - 1;
@@ -272,6 +302,9 @@ static void build_hierarchy(ba_plan* P, const ba_opts* o, hipStream_t s) {
     L.agg_ptr.upload(aptr, s);
     L.agg_mem.upload(amem, s);
     L.agg_pos.upload(apos, s);
+    std::vector<int32_t> slot(L.n);
+    for (int i = 0; i < L.n; ++i) slot[i] = aptr[L.h_agg[i]] + apos[i];
+    L.slot_of.upload(slot, s);
     P->levels.emplace_back();
     Level& F = P->levels[l];
     Level& C = P->levels[l + 1];

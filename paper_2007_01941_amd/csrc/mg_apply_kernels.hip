@@ -121,26 +121,43 @@ __global__ __launch_bounds__(256) void k_cheb_next(int n, const T* __restrict__ 
 }
 
 // Restriction b_c[a] = sum_{i in a} P_i^T (r_i - t_i) (t optional: the last
-// residual update of the pre-smoother is fused here). One thread per (aggregate, m).
+// residual update of the pre-smoother is fused here), in two passes so that
+// no thread chases member indices: (1) one thread per (fine node, m) writes
+// P_i^T (r_i - t_i) to the node's slot in aggregate order; (2) one thread per
+// (aggregate, m) sums its members' contiguous slots.
 template <int BS, class T>
-__global__ __launch_bounds__(256) void k_restrict(int n_agg, const int32_t* __restrict__ agg_ptr,
-                                                  const int32_t* __restrict__ agg_mem,
-                                                  const T* __restrict__ P, const T* __restrict__ r,
-                                                  const T* __restrict__ t, T* __restrict__ bc,
-                                                  const int* done) {
+__global__ __launch_bounds__(256) void k_restrict_nodes(int n, const int32_t* __restrict__ slot_of,
+                                                        const T* __restrict__ P, const T* __restrict__ r,
+                                                        const T* __restrict__ t, T* __restrict__ part,
+                                                        const int* done) {
+  if (done && *done) return;
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n * NS) return;
+  const int i = g / NS, m = g % NS;
+  const T* Pi = P + (size_t)i * BS * NS + m;
+  const T* ri = r + (size_t)i * BS;
+  T s = 0;
+  if (t) {
+    const T* ti = t + (size_t)i * BS;
+#pragma unroll
+    for (int k = 0; k < BS; ++k) s += Pi[k * NS] * (ri[k] - ti[k]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < BS; ++k) s += Pi[k * NS] * ri[k];
+  }
+  part[(size_t)slot_of[i] * NS + m] = s;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_restrict_sum(int n_agg, const int32_t* __restrict__ agg_ptr,
+                                                      const T* __restrict__ part, T* __restrict__ bc,
+                                                      const int* done) {
   if (done && *done) return;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_agg * NS) return;
   const int a = g / NS, m = g % NS;
   T s = 0;
-  for (int q = agg_ptr[a]; q < agg_ptr[a + 1]; ++q) {
-    const int i = agg_mem[q];
-    const T* Pi = P + (size_t)i * BS * NS + m;
-    const T* ri = r + (size_t)i * BS;
-    const T* ti = t ? t + (size_t)i * BS : nullptr;
-#pragma unroll
-    for (int k = 0; k < BS; ++k) s += Pi[k * NS] * (t ? ri[k] - ti[k] : ri[k]);
-  }
+  for (int q = agg_ptr[a]; q < agg_ptr[a + 1]; ++q) s += part[(size_t)q * NS + m];
   bc[g] = s;
 }
 

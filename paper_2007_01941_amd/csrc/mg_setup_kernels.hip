@@ -118,17 +118,15 @@ __global__ __launch_bounds__(64) void k_qr_aggregates(int bs, const int32_t* __r
 // ---------------------------------------------------------------- explicit level-0 S
 
 // Off-diagonal block (i, j), i < j, of S = A - W C^-1 W^T:
-//   S_ij = - sum_{p seen by i and j} F_{o_i}^T (E_{o_i} C_p^-1 E_{o_j}^T) F_{o_j}.
-// One workgroup per upper entry: camera i's observations are scanned in
-// chunks; each finds camera j among its point's (camera-sorted) observers,
-// matched pairs are compacted into LDS, then 81 threads accumulate the block.
-// Diagonal blocks are the block-Jacobi blocks S_cc. Both (i, j) and (j, i) are
-// written (the transpose).
+//   S_ij = - sum_{p seen by i and j} F_{o_i}^T (E_{o_i} C_p^-1 E_{o_j}^T) F_{o_j},
+// over the block's observation pairs (built with the plan). One workgroup per
+// upper entry: pairs are staged in chunks of 128 (F_i, F_j and the 2 x 2 middle
+// factor), then 81 threads accumulate the block. Diagonal blocks are the
+// block-Jacobi blocks S_cc; both (i, j) and (j, i) are written.
 __global__ __launch_bounds__(128) void k_explicit_s0(
     const int32_t* __restrict__ row_of, const int32_t* __restrict__ col,
-    const int32_t* __restrict__ trans_pos, const int32_t* __restrict__ cam_off,
-    const int32_t* __restrict__ cam_obs, const int32_t* __restrict__ obs_pt,
-    const int32_t* __restrict__ pt_off, const int32_t* __restrict__ obs_cam, int64_t stride,
+    const int32_t* __restrict__ trans_pos, const int32_t* __restrict__ s0_ptr,
+    const int2* __restrict__ s0_pairs, const int32_t* __restrict__ obs_pt, int64_t stride,
     const double* __restrict__ F, const double* __restrict__ E, const double* __restrict__ Cinv,
     const double* __restrict__ Scc, double* __restrict__ S) {
   const int e = blockIdx.x;
@@ -141,50 +139,33 @@ __global__ __launch_bounds__(128) void k_explicit_s0(
   __shared__ double Fi[128][18];
   __shared__ double Fj[128][18];
   __shared__ double Mm[128][4];
-  __shared__ int wcount[2];
   double acc = 0.0;
   const int r = threadIdx.x / 9, c = threadIdx.x % 9;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int base = cam_off[i]; base < cam_off[i + 1]; base += 128) {
-    const int k = base + threadIdx.x;
-    int oi = -1, oj = -1;
-    if (k < cam_off[i + 1]) {
-      oi = cam_obs[k];
-      const int q = obs_pt[oi];
-      int lo = pt_off[q], hi = pt_off[q + 1] - 1;
-      while (lo <= hi) {
-        const int mid = (lo + hi) >> 1;
-        const int cm = obs_cam[mid];
-        if (cm == j) { oj = mid; break; }
-        if (cm < j) lo = mid + 1; else hi = mid - 1;
-      }
-    }
-    const bool hit = oj >= 0;
-    const unsigned long long m = __ballot(hit);
-    if (lane == 0) wcount[wid] = __popcll(m);
-    __syncthreads();
-    const int nhit = wcount[0] + wcount[1];
-    if (hit) {
-      const int pos = (wid ? wcount[0] : 0) + __popcll(m & ((1ull << lane) - 1ull));
-      const int q = obs_pt[oi];
-      const double* ci = Cinv + (size_t)q * 6;
+  const int beg = s0_ptr[e], end = s0_ptr[e + 1];
+  for (int base = beg; base < end; base += 128) {
+    const int h = base + threadIdx.x;
+    if (h < end) {
+      const int2 pr = s0_pairs[h];
+      const int oi = pr.x, oj = pr.y;
+      const double* ci = Cinv + (size_t)obs_pt[oi] * 6;
       const double C[9] = {ci[0], ci[1], ci[2], ci[1], ci[3], ci[4], ci[2], ci[4], ci[5]};
       double ei[6], ej[6];
       for (int t = 0; t < 6; ++t) { ei[t] = E[t * stride + oi]; ej[t] = E[t * stride + oj]; }
-      // M = E_i C^-1 E_j^T (2 x 2)
       for (int a = 0; a < 2; ++a) {
         double ec[3];
         for (int t = 0; t < 3; ++t) ec[t] = ei[a * 3] * C[t] + ei[a * 3 + 1] * C[3 + t] + ei[a * 3 + 2] * C[6 + t];
-        for (int b = 0; b < 2; ++b) Mm[pos][a * 2 + b] = ec[0] * ej[b * 3] + ec[1] * ej[b * 3 + 1] + ec[2] * ej[b * 3 + 2];
+        for (int b = 0; b < 2; ++b)
+          Mm[threadIdx.x][a * 2 + b] = ec[0] * ej[b * 3] + ec[1] * ej[b * 3 + 1] + ec[2] * ej[b * 3 + 2];
       }
-      for (int t = 0; t < 18; ++t) { Fi[pos][t] = F[t * stride + oi]; Fj[pos][t] = F[t * stride + oj]; }
+      for (int t = 0; t < 18; ++t) { Fi[threadIdx.x][t] = F[t * stride + oi]; Fj[threadIdx.x][t] = F[t * stride + oj]; }
     }
     __syncthreads();
+    const int nh = end - base < 128 ? end - base : 128;
     if (threadIdx.x < 81) {
-      for (int h = 0; h < nhit; ++h) {
-        const double a0 = Mm[h][0] * Fj[h][c] + Mm[h][1] * Fj[h][9 + c];
-        const double a1 = Mm[h][2] * Fj[h][c] + Mm[h][3] * Fj[h][9 + c];
-        acc += Fi[h][r] * a0 + Fi[h][9 + r] * a1;
+      for (int q = 0; q < nh; ++q) {
+        const double a0 = Mm[q][0] * Fj[q][c] + Mm[q][1] * Fj[q][9 + c];
+        const double a1 = Mm[q][2] * Fj[q][c] + Mm[q][3] * Fj[q][9 + c];
+        acc += Fi[q][r] * a0 + Fi[q][9 + r] * a1;
       }
     }
     __syncthreads();
@@ -368,114 +349,119 @@ __global__ __launch_bounds__(64) void k_mfma_probe(const double* X, const double
   tile_store(C, 16, acc);
 }
 
-// Cholesky of the 16x16 diagonal tile k (one wave, in LDS) and the inverse of
-// its factor; L_kk is written back to A (upper part zeroed).
-__device__ void chol_diag_tile(double* A, int nd, int k, double* Lt, double* Linv, uint32_t* err) {
-  const int lane = threadIdx.x & 63;
-  for (int idx = lane; idx < 256; idx += 64) Lt[idx] = A[(size_t)(k * 16 + idx / 16) * nd + k * 16 + idx % 16];
-  wave_sync();
-  if (lane == 0) {
-    if (!cholesky<16>(Lt)) atomicOr(err, ERRF_NOT_SPD);
-    for (int j = 0; j < 16; ++j) {
-      for (int i = 0; i < 16; ++i) Linv[i * 16 + j] = 0.0;
-      Linv[j * 16 + j] = 1.0 / Lt[j * 16 + j];
-      for (int i = j + 1; i < 16; ++i) {
-        double s = 0.0;
-        for (int t = j; t < i; ++t) s -= Lt[i * 16 + t] * Linv[t * 16 + j];
-        Linv[i * 16 + j] = s / Lt[i * 16 + i];
-      }
+// ---------------------------------------------------------------- coarse inverse
+
+// Dense inverse of the (equilibrated, SPD) coarsest operator by blocked
+// Gauss-Jordan elimination with 64 x 64 pivot blocks. With P = A_kk^-1, one
+// pivot step maps
+//   A_kk <- P,  A_kj <- P A_kj,  A_ik <- -A_ik P,  A_ij <- A_ij - A_ik P A_kj,
+// and after every block has served as pivot A holds A^-1. Each step is three
+// launches: the 64 x 64 pivot inverse (one workgroup, in LDS), the new pivot
+// row and column (one workgroup per block), and the rank-64 update of all
+// other blocks (one workgroup per block, 16 waves, each wave one 16 x 16 tile
+// on the FP64 matrix cores). nd is a multiple of 64; pivots are the diagonal
+// blocks of successive Schur complements, positive definite for SPD A.
+constexpr int GJB = 64;
+
+// P = A_kk^-1 by unblocked Gauss-Jordan: 1024 threads, each keeping 4 entries
+// of the block in registers (column j = t % 64, rows t / 64 + 16 m); the pivot
+// row and column of every step are exchanged through double-buffered LDS, so
+// each step costs one barrier.
+__global__ __launch_bounds__(1024) void k_gj_pivot(int nd, const double* __restrict__ A, int k,
+                                                   double* __restrict__ Pbuf, uint32_t* err) {
+  __shared__ double rowp[2][GJB], colp[2][GJB];
+  const size_t k0 = (size_t)k * GJB;
+  const int t = threadIdx.x, j = t % GJB, i0 = t / GJB;
+  double v[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) v[m] = A[(k0 + i0 + 16 * m) * nd + k0 + j];
+  bool bad = false;
+  for (int p = 0; p < GJB; ++p) {
+    const int buf = p & 1;
+    if (i0 == (p & 15)) rowp[buf][j] = v[p >> 4];
+    if (j == p) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) colp[buf][i0 + 16 * m] = v[m];
+    }
+    __syncthreads();
+    const double piv = rowp[buf][p];
+    if (!(piv > 0.0)) { bad = true; break; }   // uniform: all threads read the same pivot
+    const double ip = 1.0 / piv;
+    const double rp = rowp[buf][j] * ip;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = i0 + 16 * m;
+      const double cp = colp[buf][i];
+      if (i == p) v[m] = (j == p) ? ip : rp;
+      else v[m] = (j == p) ? -cp * ip : v[m] - cp * rp;
     }
   }
-  wave_sync();
-  for (int idx = lane; idx < 256; idx += 64) {
-    const int i = idx / 16, j = idx % 16;
-    A[(size_t)(k * 16 + i) * nd + k * 16 + j] = j <= i ? Lt[idx] : 0.0;
+  if (bad) {
+    if (t == 0) atomicOr(err, ERRF_NOT_SPD);
+    return;
   }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) Pbuf[(i0 + 16 * m) * GJB + j] = v[m];
 }
 
-__device__ __forceinline__ void tri_index(int p, int* i, int* j) {
-  int r = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
-  while ((r + 1) * (r + 2) / 2 <= p) ++r;
-  while (r * (r + 1) / 2 > p) --r;
-  *i = r;
-  *j = p - r * (r + 1) / 2;
+// One 64 x 64 block product on 16 waves: wave w owns output tile (w/4, w%4);
+// acc += sx * X Y (X, Y 64 x 64 row-major, leading dims ldx, ldy).
+__device__ __forceinline__ d4 block_mma(d4 acc, const double* X, int ldx, const double* Y, int ldy, double sx) {
+  const int w = threadIdx.x >> 6;
+  const int tr = w >> 2, tc = w & 3;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+    acc = tile_mma_nn(acc, X + (size_t)(tr * 16) * ldx + t * 16, ldx, Y + (size_t)(t * 16) * ldy + tc * 16, ldy, sx);
+  return acc;
 }
 
-// Dense SPD inverse by blocked Cholesky in one workgroup of 16 waves with
-// 16 x 16 tiles; every tile product runs on the FP64 matrix cores:
-//   1. A = L L^T (right-looking: factor A_kk; A_ik <- A_ik L_kk^-T;
-//      A_ij -= A_ik A_jk^T);
-//   2. X = L^-1 by column blocks: X_kk = L_kk^-1, X_ik = -L_ii^-1 sum_{j=k}^{i-1} L_ij X_jk;
-//   3. inv = X^T X.
-// A (nd x nd) is overwritten; nd is a multiple of 16. Linv_all: nb x 256.
-constexpr int CHOL_WAVES = 16;
+__device__ __forceinline__ double* block_tile(double* B, int ld) {
+  const int w = threadIdx.x >> 6;
+  return B + (size_t)((w >> 2) * 16) * ld + (w & 3) * 16;
+}
 
-__global__ __launch_bounds__(64 * CHOL_WAVES) void k_dense_spd_inverse(int nd, double* A, double* inv,
-                                                                       double* Linv_all, uint32_t* err) {
-  __shared__ double Lt[256], Li[256];
-  __shared__ double stage[CHOL_WAVES][256];
-  const int nb = nd / 16;
-  const int wave = threadIdx.x >> 6;
-  // ---- 1. Cholesky
-  for (int k = 0; k < nb; ++k) {
-    if (wave == 0) {
-      chol_diag_tile(A, nd, k, Lt, Li, err);
-      for (int idx = threadIdx.x; idx < 256; idx += 64) Linv_all[(size_t)k * 256 + idx] = Li[idx];
-    }
-    __syncthreads();
-    for (int i = k + 1 + wave; i < nb; i += CHOL_WAVES) {
-      double* Aik = A + (size_t)(i * 16) * nd + k * 16;
-      d4 acc = {0, 0, 0, 0};
-      acc = tile_mma<false>(acc, Aik, nd, Li, 16, 1.0);
-      tile_store(Aik, nd, acc);
-    }
-    __syncthreads();
-    const int m = nb - k - 1;
-    const int npairs = m * (m + 1) / 2;
-    for (int p = wave; p < npairs; p += CHOL_WAVES) {
-      int ii, jj;
-      tri_index(p, &ii, &jj);
-      const int i = k + 1 + ii, j = k + 1 + jj;
-      double* Cij = A + (size_t)(i * 16) * nd + j * 16;
-      d4 acc = tile_load(Cij, nd);
-      acc = tile_mma<false>(acc, A + (size_t)(i * 16) * nd + k * 16, nd, A + (size_t)(j * 16) * nd + k * 16, nd, -1.0);
-      tile_store(Cij, nd, acc);
-    }
-    __syncthreads();
-  }
-  // ---- 2. X = L^-1 (lower), into inv; one wave per column block
-  double* st = stage[wave];
-  for (int k = wave; k < nb; k += CHOL_WAVES) {
-    for (int idx = threadIdx.x & 63; idx < 256; idx += 64)
-      inv[(size_t)(k * 16 + idx / 16) * nd + k * 16 + idx % 16] = Linv_all[(size_t)k * 256 + idx];
-    wave_sync();
-    for (int i = k + 1; i < nb; ++i) {
-      d4 acc = {0, 0, 0, 0};
-      for (int j = k; j < i; ++j)
-        acc = tile_mma_nn(acc, A + (size_t)(i * 16) * nd + j * 16, nd, inv + (size_t)(j * 16) * nd + k * 16, nd, 1.0);
-      tile_store(st, 16, acc);
-      wave_sync();
-      d4 out = {0, 0, 0, 0};
-      out = tile_mma_nn(out, Linv_all + (size_t)i * 256, 16, st, 16, -1.0);
-      tile_store(inv + (size_t)(i * 16) * nd + k * 16, nd, out);
-      wave_sync();
-    }
-  }
-  __syncthreads();
-  // ---- 3. inv = X^T X: lower tiles (i >= j) into A, then mirrored into inv
-  const int ntiles = nb * (nb + 1) / 2;
-  for (int p = wave; p < ntiles; p += CHOL_WAVES) {
-    int i, j;
-    tri_index(p, &i, &j);
-    d4 acc = {0, 0, 0, 0};
-    for (int k = i; k < nb; ++k)
-      acc = tile_mma<true>(acc, inv + (size_t)(k * 16) * nd + i * 16, nd, inv + (size_t)(k * 16) * nd + j * 16, nd, 1.0);
-    tile_store(A + (size_t)(i * 16) * nd + j * 16, nd, acc);
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) {
-    const int r = idx / nd, c = idx % nd;
-    inv[idx] = ((r >> 4) > (c >> 4) || ((r >> 4) == (c >> 4) && r >= c)) ? A[idx] : A[(size_t)c * nd + r];
+// New pivot row and column: for block b != k, Row_b = P A_kb and Col_b = -A_bk P,
+// and the old column block kept for the update (Cold_b = A_bk).
+__global__ __launch_bounds__(1024) void k_gj_panel(int nd, const double* __restrict__ A, int k,
+                                                   const double* __restrict__ Pbuf, double* __restrict__ Row,
+                                                   double* __restrict__ Col, double* __restrict__ Cold) {
+  const int b = blockIdx.x;
+  if (b == k) return;
+  const size_t k0 = (size_t)k * GJB, b0 = (size_t)b * GJB;
+  const double* Akb = A + k0 * nd + b0;   // row k, block b
+  const double* Abk = A + b0 * nd + k0;   // row b, block k
+  d4 r = {0, 0, 0, 0}, c = {0, 0, 0, 0};
+  r = block_mma(r, Pbuf, GJB, Akb, nd, 1.0);
+  c = block_mma(c, Abk, nd, Pbuf, GJB, -1.0);
+  tile_store(block_tile(Row + b0, nd), nd, r);          // Row: 64 x nd
+  tile_store(block_tile(Col + b0 * GJB, GJB), GJB, c);  // Col: nd x 64
+  // copy of the old column block
+  for (int idx = threadIdx.x; idx < GJB * GJB; idx += 1024)
+    Cold[(b0 + idx / GJB) * GJB + idx % GJB] = Abk[(size_t)(idx / GJB) * nd + idx % GJB];
+}
+
+// Rank-64 update of every block (i, j), i, j != k: A_ij -= Cold_i Row_j; the
+// pivot row, column and block take their new values.
+__global__ __launch_bounds__(1024) void k_gj_update(int nd, double* __restrict__ A, int k,
+                                                    const double* __restrict__ Pbuf, const double* __restrict__ Row,
+                                                    const double* __restrict__ Col, const double* __restrict__ Cold) {
+  const int nb = nd / GJB;
+  const int i = blockIdx.x / nb, j = blockIdx.x % nb;
+  const size_t i0 = (size_t)i * GJB, j0 = (size_t)j * GJB;
+  double* Aij = A + i0 * nd + j0;
+  if (i == k && j == k) {
+    for (int idx = threadIdx.x; idx < GJB * GJB; idx += 1024) Aij[(size_t)(idx / GJB) * nd + idx % GJB] = Pbuf[idx];
+  } else if (i == k) {
+    for (int idx = threadIdx.x; idx < GJB * GJB; idx += 1024)
+      Aij[(size_t)(idx / GJB) * nd + idx % GJB] = Row[(size_t)(idx / GJB) * nd + j0 + idx % GJB];
+  } else if (j == k) {
+    for (int idx = threadIdx.x; idx < GJB * GJB; idx += 1024)
+      Aij[(size_t)(idx / GJB) * nd + idx % GJB] = Col[(i0 + idx / GJB) * GJB + idx % GJB];
+  } else {
+    double* t = block_tile(Aij, nd);
+    d4 acc = tile_load(t, nd);
+    acc = block_mma(acc, Cold + i0 * GJB, GJB, Row + j0, nd, -1.0);
+    tile_store(t, nd, acc);
   }
 }
 

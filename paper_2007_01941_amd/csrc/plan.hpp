@@ -31,6 +31,7 @@ struct Level {
   DBuf<int32_t> agg_ptr;     // members of aggregate a: agg_mem[agg_ptr[a] .. agg_ptr[a+1])
   DBuf<int32_t> agg_mem;     // ascending node ids
   DBuf<int32_t> agg_pos;     // position of node i inside its aggregate
+  DBuf<int32_t> slot_of;     // node i's position in aggregate order: agg_ptr[agg[i]] + agg_pos[i]
   int max_agg = 0;           // largest aggregate
   // Galerkin map: coarse CSR entry e gathers fine entries gal_fine[gal_ptr[e] .. gal_ptr[e+1])
   DBuf<int32_t> gal_ptr;
@@ -50,8 +51,8 @@ struct Level {
   DBuf<double> dense;        // factor workspace nd x nd
   DBuf<double> inv;          // inverse nd x nd
   // V-cycle work vectors, FP64 and FP32 (n * bs each)
-  DBuf<double> vb, vx, vr, vd, vt;
-  DBuf<float> fb, fx, fr, fd, ft;
+  DBuf<double> vb, vx, vr, vd, vt, vpart;
+  DBuf<float> fb, fx, fr, fd, ft, fpart;   // vpart/fpart: restriction partials (n * NS)
 };
 
 struct Scratch;   // defined in api.cpp
@@ -84,6 +85,10 @@ struct ba_plan {
   bamg::DBuf<int32_t> tile_cams;  // distinct cameras of each tile, ascending
   bamg::DBuf<uint32_t> obs_slot;  // [n_obs] (point slot << 16) | camera slot
   int32_t max_tile_cams = 0;
+  // ---- explicit level-0 S: for every upper off-diagonal block (i, j) of the
+  // level-0 pattern, the observation pairs (o_i, o_j) of the points i and j share
+  bamg::DBuf<int32_t> s0_ptr;     // [nnz0 + 1]
+  bamg::DBuf<int2> s0_pairs;      // point-major observation indices (camera i, camera j)
   int32_t max_pt_obs = 0;
   // ---- multigrid hierarchy
   std::vector<bamg::Level> levels;

@@ -14,6 +14,7 @@ static size_t plan_bytes(const ba_plan* P) {
   b += P->obs_cam.bytes() + P->obs_pt.bytes() + P->obs_orig.bytes() + P->pt_off.bytes() + P->pt_orig.bytes();
   b += P->pt_new.bytes() + P->cam_off.bytes() + P->cam_obs.bytes() + P->obs_rank.bytes();
   b += P->tile_obs.bytes() + P->tile_pt.bytes() + P->tile_coff.bytes() + P->tile_cams.bytes() + P->obs_slot.bytes();
+  b += P->s0_ptr.bytes() + P->s0_pairs.bytes();
   b += P->campre.bytes() + P->F.bytes() + P->E.bytes() + P->fres.bytes() + P->F32.bytes() + P->E32.bytes();
   b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
   b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->gc.bytes() + P->Scc.bytes();
@@ -21,7 +22,8 @@ static size_t plan_bytes(const ba_plan* P) {
   for (const Level& L : P->levels) {
     b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
     b += L.diag_pos.bytes() + L.trans_pos.bytes() + L.row_of.bytes() + L.agg.bytes() + L.agg_ptr.bytes();
-    b += L.agg_mem.bytes() + L.agg_pos.bytes() + L.gal_ptr.bytes() + L.gal_fine.bytes();
+    b += L.agg_mem.bytes() + L.agg_pos.bytes() + L.slot_of.bytes() + L.gal_ptr.bytes() + L.gal_fine.bytes();
+    b += L.vpart.bytes() + L.fpart.bytes();
     b += L.S.bytes() + L.S32.bytes() + L.K.bytes() + L.P.bytes() + L.P32.bytes() + L.Dinv.bytes() + L.Dinv32.bytes();
     b += L.dense.bytes() + L.inv.bytes();
     b += L.vb.bytes() + L.vx.bytes() + L.vr.bytes() + L.vd.bytes() + L.vt.bytes();
@@ -59,8 +61,9 @@ static void allocate_step(ba_plan* P) {
       if (l > 0) L.Dinv.alloc((size_t)L.n * L.bs * L.bs);
     }
     for (DBuf<double>* v : {&L.vb, &L.vx, &L.vr, &L.vd, &L.vt}) v->alloc(nv);
+    if (l + 1 < nl) L.vpart.alloc((size_t)L.n * NS);
     if (l + 1 == nl) {
-      L.nd = (int)((nv + 15) / 16 * 16);
+      L.nd = (int)((nv + GJB - 1) / GJB * GJB);
       L.dense.alloc((size_t)L.nd * L.nd);
       L.inv.alloc((size_t)L.nd * L.nd);
     }
@@ -85,6 +88,7 @@ static void ensure_mixed(ba_plan* P) {
       if (l > 0) L.Dinv32.alloc((size_t)L.n * L.bs * L.bs);
     }
     for (DBuf<float>* v : {&L.fb, &L.fx, &L.fr, &L.fd, &L.ft}) v->alloc(nv);
+    if (l + 1 < nl) L.fpart.alloc((size_t)L.n * NS);
   }
 }
 
@@ -132,6 +136,7 @@ template <> struct LvVec<double> {
   static double* r(Level& L) { return L.vr.p; }
   static double* d(Level& L) { return L.vd.p; }
   static double* t(Level& L) { return L.vt.p; }
+  static double* part(Level& L) { return L.vpart.p; }
 };
 template <> struct LvVec<float> {
   static float* b(Level& L) { return L.fb.p; }
@@ -139,6 +144,7 @@ template <> struct LvVec<float> {
   static float* r(Level& L) { return L.fr.p; }
   static float* d(Level& L) { return L.fd.p; }
   static float* t(Level& L) { return L.ft.p; }
+  static float* part(Level& L) { return L.fpart.p; }
 };
 
 template <class T>
@@ -207,8 +213,11 @@ static void vcycle_level(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, 
   // restriction of the pre-smoother's residual r - t
   T* bc = LvVec<T>::b(C);
   T* xc = LvVec<T>::x(C);
-  hipLaunchKernelGGL((k_restrict<BS, T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n, L.agg_ptr.p,
-                     L.agg_mem.p, lvP<T>(L), (const T*)r, (const T*)t, bc, done);
+  T* part = LvVec<T>::part(L);
+  hipLaunchKernelGGL((k_restrict_nodes<BS, T>), dim3(grid_of<T>((int64_t)L.n * NS)), dim3(256), 0, s, L.n,
+                     L.slot_of.p, lvP<T>(L), (const T*)r, (const T*)t, part, done);
+  hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n, L.agg_ptr.p,
+                     (const T*)part, bc, done);
   vcycle<T>(P, o, l + 1, bc, xc, done, s);
   hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
                      lvP<T>(L), (const T*)xc, x, done);
@@ -348,8 +357,8 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   // explicit level-0 S (Section 3.6): needed for the Galerkin product and, when
   // cheaper than the implicit form, for smoothing
   hipLaunchKernelGGL(k_explicit_s0, dim3((unsigned)L0.nnz), dim3(128), 0, s, L0.row_of.p, L0.col.p, L0.trans_pos.p,
-                     P->cam_off.p, P->cam_obs.p, P->obs_pt.p, P->pt_off.p, P->obs_cam.p, P->n_obs_pad, P->F.p,
-                     P->E.p, P->Cinv.p, P->Scc.p, L0.S.p);
+                     P->s0_ptr.p, P->s0_pairs.p, P->obs_pt.p, P->n_obs_pad, P->F.p, P->E.p, P->Cinv.p,
+                     P->Scc.p, L0.S.p);
   L0.explicit_op = level0_explicit(P, o, mixed ? 4 : 8);
   hipLaunchKernelGGL(k_nullspace0, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
                      L0.K.p);
@@ -375,22 +384,30 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   const int64_t tot = Lc.nnz * Lc.bs * Lc.bs + Lc.nd;
   hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(tot)), dim3(256), 0, s, Lc.n, Lc.bs, Lc.nd, Lc.row_of.p,
                      Lc.col.p, Lc.nnz, Lc.S.p, Lc.dense.p);
-  DBuf<double> linv, scl;
-  linv.alloc((size_t)(Lc.nd / 16) * 256);
+  DBuf<double> scl, pbuf, row, col, cold;
   scl.alloc(Lc.nd);
+  pbuf.alloc(GJB * GJB);
+  row.alloc((size_t)GJB * Lc.nd);
+  col.alloc((size_t)GJB * Lc.nd);
+  cold.alloc((size_t)GJB * Lc.nd);
   const int64_t nd2 = (int64_t)Lc.nd * Lc.nd;
-  // factor the equilibrated matrix s S s + eps I (s = diag^-1/2, eps = coarse_shift):
-  // the coarsest Galerkin operator of a street-view scene is singular to FP64
-  // rounding in its near-nullspace, and the shift keeps the coarse solve SPD
+  // invert the equilibrated matrix s S s + eps I (s = diag^-1/2, eps = coarse_shift),
+  // then scale back: inv = s (s S s + eps I)^-1 s
   hipLaunchKernelGGL(k_dense_diag, dim3(grid_of<double>(Lc.nd)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
                      P->errflag.p);
   hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
                      o->coarse_shift);
-  hipLaunchKernelGGL(k_dense_spd_inverse, dim3(1), dim3(64 * CHOL_WAVES), 0, s, Lc.nd, Lc.dense.p, Lc.inv.p, linv.p,
-                     P->errflag.p);
+  const int nbk = Lc.nd / GJB;
+  for (int k = 0; k < nbk; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, Lc.nd, Lc.dense.p, k, pbuf.p, P->errflag.p);
+    hipLaunchKernelGGL(k_gj_panel, dim3(nbk), dim3(1024), 0, s, Lc.nd, Lc.dense.p, k, pbuf.p, row.p, col.p, cold.p);
+    hipLaunchKernelGGL(k_gj_update, dim3(nbk * nbk), dim3(1024), 0, s, Lc.nd, Lc.dense.p, k, pbuf.p, row.p, col.p,
+                       cold.p);
+  }
+  std::swap(Lc.dense, Lc.inv);
   hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.inv.p, scl.p, 0.0);
   BA_LAUNCH_CHECK();
-  check_errflag(P, s, "coarse Cholesky");
+  check_errflag(P, s, "coarse inverse");
   if (mixed) {
     for (int l = 0; l < nl; ++l) {
       Level& L = P->levels[l];
