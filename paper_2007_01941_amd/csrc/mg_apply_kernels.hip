@@ -211,21 +211,55 @@ __global__ void k_lanczos_start(int n, int level, double* __restrict__ v) {
   v[i] = (double)(splitmix64(seed ^ (uint64_t)i) >> 11) * 0x1.0p-53 - 0.5;
 }
 
-// y = a x + b y, z optional second output
-__global__ void k_axpby2(int n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = a * x[i] + b * y[i];
-}
+// ---- generalized Lanczos on S x = lambda D x with device-resident scalars
+// Scalar slots: alpha[j] = s[j], beta[j] = s[32 + j], s[64] = norm^2,
+// s[65] = b2, s[66] = completed steps, s[67] = stop flag.
+constexpr int LZ_ALPHA = 0, LZ_BETA = 32, LZ_NRM = 64, LZ_B2 = 65, LZ_COUNT = 66, LZ_STOP = 67;
 
-// w = Dinv_av - alpha v - beta vp ; Dw = av - alpha u - beta up (Lanczos update)
-__global__ void k_lanczos_update(int n, const double* __restrict__ dinv_av, const double* __restrict__ av,
-                                 const double* __restrict__ v, const double* __restrict__ vp,
-                                 const double* __restrict__ u, const double* __restrict__ up, double alpha,
-                                 double beta, double* __restrict__ w, double* __restrict__ dw) {
+// v <- v / sqrt(s[64]), u <- u / sqrt(s[64])
+__global__ void k_lanczos_normalize(int n, double* __restrict__ v, double* __restrict__ u,
+                                    const double* __restrict__ lz) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  const double sc = 1.0 / sqrt(lz[LZ_NRM]);
+  v[i] *= sc;
+  u[i] *= sc;
+}
+
+// w = D^-1 A v - alpha_j v - beta_j v_prev ;  Dw = A v - alpha_j u - beta_j u_prev
+__global__ void k_lanczos_update(int n, int j, const double* __restrict__ dinv_av, const double* __restrict__ av,
+                                 const double* __restrict__ v, const double* __restrict__ vp,
+                                 const double* __restrict__ u, const double* __restrict__ up,
+                                 const double* __restrict__ lz, double* __restrict__ w, double* __restrict__ dw) {
+  if (lz[LZ_STOP] != 0.0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double alpha = lz[LZ_ALPHA + j], beta = j > 0 ? lz[LZ_BETA + j - 1] : 0.0;
   w[i] = dinv_av[i] - alpha * v[i] - beta * vp[i];
   dw[i] = av[i] - alpha * u[i] - beta * up[i];
+}
+
+// After step j (unless stopped): (v_prev, u_prev, v, u) <- (v, u, w / beta_j, Dw / beta_j).
+__global__ void k_lanczos_advance(int n, int j, double* __restrict__ v, double* __restrict__ vp,
+                                  double* __restrict__ u, double* __restrict__ up, const double* __restrict__ w,
+                                  const double* __restrict__ dw, const double* __restrict__ lz) {
+  if (lz[LZ_STOP] != 0.0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ib = 1.0 / lz[LZ_BETA + j];
+  vp[i] = v[i];
+  up[i] = u[i];
+  v[i] = w[i] * ib;
+  u[i] = dw[i] * ib;
+}
+
+// Bookkeeping after step j (one thread): record alpha_j as done, and beta_j or the stop.
+__global__ void k_lanczos_record(int j, double* __restrict__ lz) {
+  if (lz[LZ_STOP] != 0.0) return;
+  lz[LZ_COUNT] = (double)(j + 1);
+  const double b2 = lz[LZ_B2], alpha = lz[LZ_ALPHA + j];
+  if (!(b2 > 1e-300) || sqrt(b2) <= 1e-14 * fabs(alpha)) lz[LZ_STOP] = 1.0;
+  else lz[LZ_BETA + j] = sqrt(b2);
 }
 
 }  // namespace bamg

@@ -51,6 +51,9 @@ struct Level {
   DBuf<double> dense;        // factor workspace nd x nd
   DBuf<double> inv;          // inverse nd x nd
   // V-cycle work vectors, FP64 and FP32 (n * bs each)
+  DBuf<double> lz_u, lz_v, lz_up, lz_vp, lz_av, lz_dav, lz_w, lz_dw;   // Lanczos vectors
+  DBuf<double> lz_s;         // Lanczos scalars: alpha[32], beta[32], norm, b2, count, stop
+  DBuf<double> gj_scale, gj_piv, gj_row, gj_col, gj_cold;   // coarsest level: Gauss-Jordan work
   DBuf<double> vb, vx, vr, vd, vt, vpart;
   DBuf<float> fb, fx, fr, fd, ft, fpart;   // vpart/fpart: restriction partials (n * NS)
 };

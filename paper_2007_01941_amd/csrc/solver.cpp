@@ -66,6 +66,15 @@ static void allocate_step(ba_plan* P) {
       L.nd = (int)((nv + GJB - 1) / GJB * GJB);
       L.dense.alloc((size_t)L.nd * L.nd);
       L.inv.alloc((size_t)L.nd * L.nd);
+      L.gj_scale.alloc(L.nd);
+      L.gj_piv.alloc(GJB * GJB);
+      L.gj_row.alloc((size_t)GJB * L.nd);
+      L.gj_col.alloc((size_t)GJB * L.nd);
+      L.gj_cold.alloc((size_t)GJB * L.nd);
+    } else {
+      for (DBuf<double>* v : {&L.lz_u, &L.lz_v, &L.lz_up, &L.lz_vp, &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw})
+        v->alloc(nv);
+      L.lz_s.alloc(68);
     }
   }
 }
@@ -308,44 +317,51 @@ static double tridiag_max_eig(const std::vector<double>& a, const std::vector<do
   return 0.5 * (lo + hi);
 }
 
+// lambda_max of D^-1 S on one level: `lanczos_steps` steps of generalized
+// Lanczos in the D inner product (scalars stay on the device; one readback).
 static double lanczos_lmax(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
   Level& L = P->levels[l];
   const int n = L.n * L.bs;
-  DBuf<double> u, v, up, vp, av, dav, w, dw;
-  for (DBuf<double>* x : {&u, &v, &up, &vp, &av, &dav, &w, &dw}) x->alloc(n);
-  BA_HIP(hipMemsetAsync(up.p, 0, n * sizeof(double), s));
-  BA_HIP(hipMemsetAsync(vp.p, 0, n * sizeof(double), s));
+  Scratch& W = *P->scratch;
+  double* lz = L.lz_s.p;
+  BA_HIP(hipMemsetAsync(lz, 0, 68 * sizeof(double), s));
+  BA_HIP(hipMemsetAsync(L.lz_up.p, 0, n * sizeof(double), s));
+  BA_HIP(hipMemsetAsync(L.lz_vp.p, 0, n * sizeof(double), s));
   const int g = grid_of<double>(n);
-  hipLaunchKernelGGL(k_lanczos_start, dim3(g), dim3(256), 0, s, n, l, u.p);
+  const int rg = red_grid(n);
   auto dinv = [&](const double* in, double* out) {
     if (L.bs == 9) blockdiag_apply<9, double>(P, l, in, out, nullptr, s);
     else blockdiag_apply<16, double>(P, l, in, out, nullptr, s);
   };
-  dinv(u.p, v.p);
-  const double nrm = std::sqrt(plain_dot(P, n, v.p, u.p, s));
-  BA_CHECK(nrm > 0.0 && std::isfinite(nrm), BA_ERR_NOT_SPD, "smoother blocks are not positive definite");
-  hipLaunchKernelGGL(k_axpby2, dim3(g), dim3(256), 0, s, n, 1.0 / nrm, v.p, 0.0, v.p);
-  hipLaunchKernelGGL(k_axpby2, dim3(g), dim3(256), 0, s, n, 1.0 / nrm, u.p, 0.0, u.p);
-  std::vector<double> alphas, betas;
-  double beta = 0.0;
-  for (int j = 0; j < o->lanczos_steps; ++j) {
-    op_apply<double>(P, l, v.p, av.p, nullptr, s);
-    const double alpha = plain_dot(P, n, av.p, v.p, s);
-    alphas.push_back(alpha);
-    if (j == o->lanczos_steps - 1) break;
-    dinv(av.p, dav.p);
-    hipLaunchKernelGGL(k_lanczos_update, dim3(g), dim3(256), 0, s, n, dav.p, av.p, v.p, vp.p, u.p, up.p, alpha, beta,
-                       w.p, dw.p);
-    const double b2 = plain_dot(P, n, w.p, dw.p, s);
-    if (!(b2 > 1e-300) || std::sqrt(b2) <= 1e-14 * std::fabs(alpha)) break;
-    beta = std::sqrt(b2);
-    betas.push_back(beta);
-    std::swap(vp, v);
-    std::swap(up, u);
-    hipLaunchKernelGGL(k_axpby2, dim3(g), dim3(256), 0, s, n, 1.0 / beta, w.p, 0.0, v.p);
-    hipLaunchKernelGGL(k_axpby2, dim3(g), dim3(256), 0, s, n, 1.0 / beta, dw.p, 0.0, u.p);
+  auto dot = [&](const double* a, const double* b, int slot) {
+    hipLaunchKernelGGL((k_dot<DOT_PLAIN, double>), dim3(rg), dim3(256), 0, s, n, a, b, W.partial.p, W.scal.p + 1,
+                       lz + slot);
+  };
+  hipLaunchKernelGGL(k_lanczos_start, dim3(g), dim3(256), 0, s, n, l, L.lz_u.p);
+  dinv(L.lz_u.p, L.lz_v.p);
+  dot(L.lz_v.p, L.lz_u.p, LZ_NRM);
+  hipLaunchKernelGGL(k_lanczos_normalize, dim3(g), dim3(256), 0, s, n, L.lz_v.p, L.lz_u.p, (const double*)lz);
+  const int steps = o->lanczos_steps;
+  for (int j = 0; j < steps; ++j) {
+    op_apply<double>(P, l, L.lz_v.p, L.lz_av.p, nullptr, s);
+    dot(L.lz_av.p, L.lz_v.p, LZ_ALPHA + j);
+    if (j == steps - 1) break;
+    dinv(L.lz_av.p, L.lz_dav.p);
+    hipLaunchKernelGGL(k_lanczos_update, dim3(g), dim3(256), 0, s, n, j, L.lz_dav.p, L.lz_av.p, L.lz_v.p, L.lz_vp.p,
+                       L.lz_u.p, L.lz_up.p, (const double*)lz, L.lz_w.p, L.lz_dw.p);
+    dot(L.lz_w.p, L.lz_dw.p, LZ_B2);
+    hipLaunchKernelGGL(k_lanczos_record, dim3(1), dim3(1), 0, s, j, lz);
+    hipLaunchKernelGGL(k_lanczos_advance, dim3(g), dim3(256), 0, s, n, j, L.lz_v.p, L.lz_vp.p, L.lz_u.p, L.lz_up.p,
+                       (const double*)L.lz_w.p, (const double*)L.lz_dw.p, (const double*)lz);
   }
   BA_LAUNCH_CHECK();
+  double h[68];
+  BA_HIP(hipMemcpyAsync(h, lz, sizeof(h), hipMemcpyDeviceToHost, s));
+  BA_HIP(hipStreamSynchronize(s));
+  BA_CHECK(h[LZ_NRM] > 0.0 && std::isfinite(h[LZ_NRM]), BA_ERR_NOT_SPD, "smoother blocks are not positive definite");
+  // steps whose alpha is valid: all of them unless a breakdown stopped the process
+  const int na = h[LZ_STOP] != 0.0 ? (int)h[LZ_COUNT] : steps;
+  std::vector<double> alphas(h + LZ_ALPHA, h + LZ_ALPHA + na), betas(h + LZ_BETA, h + LZ_BETA + std::max(0, na - 1));
   return tridiag_max_eig(alphas, betas);
 }
 
@@ -384,12 +400,11 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   const int64_t tot = Lc.nnz * Lc.bs * Lc.bs + Lc.nd;
   hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(tot)), dim3(256), 0, s, Lc.n, Lc.bs, Lc.nd, Lc.row_of.p,
                      Lc.col.p, Lc.nnz, Lc.S.p, Lc.dense.p);
-  DBuf<double> scl, pbuf, row, col, cold;
-  scl.alloc(Lc.nd);
-  pbuf.alloc(GJB * GJB);
-  row.alloc((size_t)GJB * Lc.nd);
-  col.alloc((size_t)GJB * Lc.nd);
-  cold.alloc((size_t)GJB * Lc.nd);
+  DBuf<double>& scl = Lc.gj_scale;
+  DBuf<double>& pbuf = Lc.gj_piv;
+  DBuf<double>& row = Lc.gj_row;
+  DBuf<double>& col = Lc.gj_col;
+  DBuf<double>& cold = Lc.gj_cold;
   const int64_t nd2 = (int64_t)Lc.nd * Lc.nd;
   // invert the equilibrated matrix s S s + eps I (s = diag^-1/2, eps = coarse_shift),
   // then scale back: inv = s (s S s + eps I)^-1 s
