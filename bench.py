@@ -41,7 +41,7 @@ def schur_bytes(n_obs, n_pt, n_cam, s):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("step_kernels.hip", "common.hpp"):
+    for f in ("schur_kernels.hip", "common.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2007_01941_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -72,6 +72,8 @@ def main():
     ap.add_argument("--scene", default="city2k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device-to-device 5 times (reference kernel for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
@@ -80,6 +82,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        src = torch.ones(2 ** 27, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read_per_launch": 2 ** 30, "copy_bytes_written_per_launch": 2 ** 30}),
+              flush=True)
+        return
 
     import paper_2007_01941_amd as bamg
     from scenes import make_scene

@@ -134,4 +134,34 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
+// One halving step of a wave reduce-scatter: lanes whose `off` bit is set keep
+// the upper half of v[0 .. 2H), the others the lower half, each adding the
+// partner lane's copy of the half it keeps.
+template <int H>
+__device__ __forceinline__ void reduce_scatter_step(double* v, int off, bool upper) {
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    const double send = upper ? v[k] : v[H + k];
+    const double keep = upper ? v[H + k] : v[k];
+    v[k] = keep + __shfl_xor(send, off, 64);
+  }
+}
+
+// Sums N = 32 m per-lane values over the 64 lanes of a wave with 63 m / 2
+// exchanges (instead of 6 N for N separate butterflies). On return lane l holds
+// in v[0 .. m) the wave totals of entries m (l >> 1) .. m (l >> 1) + m - 1
+// (both lanes of a pair hold the same totals).
+template <int N>
+__device__ __forceinline__ void wave_reduce_scatter(double (&v)[N]) {
+  static_assert(N % 32 == 0, "N must be a multiple of 32");
+  const int lane = threadIdx.x & 63;
+  reduce_scatter_step<N / 2>(v, 32, lane & 32);
+  reduce_scatter_step<N / 4>(v, 16, lane & 16);
+  reduce_scatter_step<N / 8>(v, 8, lane & 8);
+  reduce_scatter_step<N / 16>(v, 4, lane & 4);
+  reduce_scatter_step<N / 32>(v, 2, lane & 2);
+#pragma unroll
+  for (int k = 0; k < N / 32; ++k) v[k] += __shfl_xor(v[k], 1, 64);
+}
+
 }  // namespace bamg

@@ -137,6 +137,11 @@ static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
   P->pt_new.upload(pt_new, s);
   P->cam_off.upload(cam_off32, s);
   P->cam_obs.upload(P->h_cam_obs, s);
+  {
+    std::vector<int32_t> cq(n_obs);
+    for (int64_t i = 0; i < n_obs; ++i) cq[i] = P->h_obs_pt[P->h_cam_obs[i]];
+    P->cam_q.upload(cq, s);
+  }
   P->tile_obs.upload(t_obs, s);
   P->tile_pt.upload(t_pt, s);
   P->tile_coff.upload(t_coff, s);
@@ -207,9 +212,9 @@ static void build_covisibility(ba_plan* P, Level& L, LaunchPass launch, hipStrea
   L.h_col = L.col.download(s);
 }
 
-// Observation pairs of every upper off-diagonal block of the level-0 pattern:
-// for each point (in order) and each pair a < b of its camera-sorted
-// observations, the pair goes to block (camera(a), camera(b)).
+// Shared points of every upper off-diagonal block of the level-0 pattern: for
+// each point (in order) and each pair a < b of its camera-sorted observations,
+// the point goes to block (camera(a), camera(b)).
 static void build_s0_pairs(ba_plan* P, const Level& L0, hipStream_t s) {
   const int n_pt = P->n_pt;
   std::vector<int32_t> cnt(L0.nnz + 1, 0);
@@ -226,14 +231,14 @@ static void build_s0_pairs(ba_plan* P, const Level& L0, hipStream_t s) {
       }
   BA_CHECK(total < INT32_MAX, BA_ERR_LIMIT, "too many covisible observation pairs");
   for (int64_t e = 0; e < L0.nnz; ++e) cnt[e + 1] += cnt[e];
-  std::vector<int2> pairs(std::max<int64_t>(1, total));
+  std::vector<int32_t> pts(std::max<int64_t>(1, total));
   std::vector<int32_t> cur(cnt.begin(), cnt.end() - 1);
   for (int q = 0; q < n_pt; ++q)
     for (int64_t a = P->h_pt_off[q]; a < P->h_pt_off[q + 1]; ++a)
       for (int64_t b = a + 1; b < P->h_pt_off[q + 1]; ++b)
-        pairs[cur[entry(P->h_obs_cam[a], P->h_obs_cam[b])]++] = make_int2((int)a, (int)b);
+        pts[cur[entry(P->h_obs_cam[a], P->h_obs_cam[b])]++] = q;
   P->s0_ptr.upload(cnt, s);
-  P->s0_pairs.upload(pairs, s);
+  P->s0_q.upload(pts, s);
 }
 
 static void aggregate_level(ba_plan* P, Level& L, int cap, hipStream_t s) {

@@ -118,61 +118,71 @@ __global__ __launch_bounds__(64) void k_qr_aggregates(int bs, const int32_t* __r
 // ---------------------------------------------------------------- explicit level-0 S
 
 // Off-diagonal block (i, j), i < j, of S = A - W C^-1 W^T:
-//   S_ij = - sum_{p seen by i and j} F_{o_i}^T (E_{o_i} C_p^-1 E_{o_j}^T) F_{o_j},
-// over the block's observation pairs (built with the plan). One workgroup per
-// upper entry: pairs are staged in chunks of 128 (F_i, F_j and the 2 x 2 middle
-// factor), then 81 threads accumulate the block. Diagonal blocks are the
-// block-Jacobi blocks S_cc; both (i, j) and (j, i) are written.
-__global__ __launch_bounds__(128) void k_explicit_s0(
+//   S_ij = - sum_{p seen by i and j} F_ip^T (E_ip C_p^-1 E_jp^T) F_jp,
+// one wave per upper entry, one lane per shared point (the plan lists the
+// points of every block). Each lane recomputes both cameras' Jacobian blocks
+// from the camera data and the point record [X | C_p^-1], accumulates the 81
+// entries, and the wave sums them with a reduce-scatter. Diagonal blocks are
+// the block-Jacobi blocks S_cc; both (i, j) and (j, i) are written.
+__global__ __launch_bounds__(64) void k_explicit_s0(
     const int32_t* __restrict__ row_of, const int32_t* __restrict__ col,
     const int32_t* __restrict__ trans_pos, const int32_t* __restrict__ s0_ptr,
-    const int2* __restrict__ s0_pairs, const int32_t* __restrict__ obs_pt, int64_t stride,
-    const double* __restrict__ F, const double* __restrict__ E, const double* __restrict__ Cinv,
+    const int32_t* __restrict__ s0_q, const double* __restrict__ campre, const double* __restrict__ prec,
     const double* __restrict__ Scc, double* __restrict__ S) {
   const int e = blockIdx.x;
   const int i = row_of[e], j = col[e];
+  const int lane = threadIdx.x;
   if (i == j) {
-    if (threadIdx.x < 81) S[(size_t)e * 81 + threadIdx.x] = Scc[(size_t)i * 81 + threadIdx.x];
+    for (int k = lane; k < 81; k += 64) S[(size_t)e * 81 + k] = Scc[(size_t)i * 81 + k];
     return;
   }
   if (i > j) return;
-  __shared__ double Fi[128][18];
-  __shared__ double Fj[128][18];
-  __shared__ double Mm[128][4];
-  double acc = 0.0;
-  const int r = threadIdx.x / 9, c = threadIdx.x % 9;
-  const int beg = s0_ptr[e], end = s0_ptr[e + 1];
-  for (int base = beg; base < end; base += 128) {
-    const int h = base + threadIdx.x;
-    if (h < end) {
-      const int2 pr = s0_pairs[h];
-      const int oi = pr.x, oj = pr.y;
-      const double* ci = Cinv + (size_t)obs_pt[oi] * 6;
-      const double C[9] = {ci[0], ci[1], ci[2], ci[1], ci[3], ci[4], ci[2], ci[4], ci[5]};
-      double ei[6], ej[6];
-      for (int t = 0; t < 6; ++t) { ei[t] = E[t * stride + oi]; ej[t] = E[t * stride + oj]; }
-      for (int a = 0; a < 2; ++a) {
-        double ec[3];
-        for (int t = 0; t < 3; ++t) ec[t] = ei[a * 3] * C[t] + ei[a * 3 + 1] * C[3 + t] + ei[a * 3 + 2] * C[6 + t];
-        for (int b = 0; b < 2; ++b)
-          Mm[threadIdx.x][a * 2 + b] = ec[0] * ej[b * 3] + ec[1] * ej[b * 3 + 1] + ec[2] * ej[b * 3 + 2];
-      }
-      for (int t = 0; t < 18; ++t) { Fi[threadIdx.x][t] = F[t * stride + oi]; Fj[threadIdx.x][t] = F[t * stride + oj]; }
+  const double* ci = campre + (size_t)i * 24;
+  const double* cj = campre + (size_t)j * 24;
+  double acc[96];
+#pragma unroll
+  for (int k = 0; k < 96; ++k) acc[k] = 0.0;
+  const int end = s0_ptr[e + 1];
+  for (int h = s0_ptr[e] + lane; h < end; h += 64) {
+    const double* rec = prec + (size_t)s0_q[h] * PREC;
+    const double X[3] = {rec[0], rec[1], rec[2]};
+    const double C[9] = {rec[3], rec[4], rec[5], rec[4], rec[6], rec[7], rec[5], rec[7], rec[8]};
+    double pi[2], fi[18], ei[6], fj[18], ej[6], z;
+    project_jacobian(ci, X, pi, fi, ei, &z);
+    project_jacobian(cj, X, pi, fj, ej, &z);
+    double ec[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        ec[r * 3 + k] = ei[r * 3 + 0] * C[0 * 3 + k] + ei[r * 3 + 1] * C[1 * 3 + k] + ei[r * 3 + 2] * C[2 * 3 + k];
+    double m[4];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) m[r * 2 + t] = ec[r * 3 + 0] * ej[t * 3 + 0] + ec[r * 3 + 1] * ej[t * 3 + 1] + ec[r * 3 + 2] * ej[t * 3 + 2];
+    double mf[18];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      mf[k] = m[0] * fj[k] + m[1] * fj[9 + k];
+      mf[9 + k] = m[2] * fj[k] + m[3] * fj[9 + k];
     }
-    __syncthreads();
-    const int nh = end - base < 128 ? end - base : 128;
-    if (threadIdx.x < 81) {
-      for (int q = 0; q < nh; ++q) {
-        const double a0 = Mm[q][0] * Fj[q][c] + Mm[q][1] * Fj[q][9 + c];
-        const double a1 = Mm[q][2] * Fj[q][c] + Mm[q][3] * Fj[q][9 + c];
-        acc += Fi[q][r] * a0 + Fi[q][9 + r] * a1;
-      }
-    }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 9; ++r)
+#pragma unroll
+      for (int c = 0; c < 9; ++c) acc[r * 9 + c] += fi[r] * mf[c] + fi[9 + r] * mf[9 + c];
   }
-  if (threadIdx.x < 81) {
-    S[(size_t)e * 81 + r * 9 + c] = -acc;
-    S[(size_t)trans_pos[e] * 81 + c * 9 + r] = -acc;
+  wave_reduce_scatter<96>(acc);
+  if (!(lane & 1)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int idx = 3 * (lane >> 1) + k;
+      if (idx < 81) {
+        const int r = idx / 9, c = idx % 9;
+        S[(size_t)e * 81 + idx] = -acc[k];
+        S[(size_t)trans_pos[e] * 81 + c * 9 + r] = -acc[k];
+      }
+    }
   }
 }
 

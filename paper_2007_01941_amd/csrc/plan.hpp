@@ -79,6 +79,7 @@ struct ba_plan {
   bamg::DBuf<int32_t> pt_new;     // [n_pt] reordered index of each caller point
   bamg::DBuf<int32_t> cam_off;    // [n_cam + 1]
   bamg::DBuf<int32_t> cam_obs;    // [n_obs] point-major observation indices, camera-major
+  bamg::DBuf<int32_t> cam_q;      // [n_obs] reordered point of each camera-major entry
   bamg::DBuf<int32_t> obs_rank;   // [n_obs] point-major index of caller observation i
   // ---- tiles for the implicit Schur product
   int32_t n_tiles = 0;
@@ -89,9 +90,9 @@ struct ba_plan {
   bamg::DBuf<uint32_t> obs_slot;  // [n_obs] (point slot << 16) | camera slot
   int32_t max_tile_cams = 0;
   // ---- explicit level-0 S: for every upper off-diagonal block (i, j) of the
-  // level-0 pattern, the observation pairs (o_i, o_j) of the points i and j share
+  // level-0 pattern, the (reordered) points cameras i and j share
   bamg::DBuf<int32_t> s0_ptr;     // [nnz0 + 1]
-  bamg::DBuf<int2> s0_pairs;      // point-major observation indices (camera i, camera j)
+  bamg::DBuf<int32_t> s0_q;
   int32_t max_pt_obs = 0;
   // ---- multigrid hierarchy
   std::vector<bamg::Level> levels;
@@ -102,13 +103,13 @@ struct ba_plan {
   bamg::DBuf<double> Cinv;        // [n_pt][6] packed symmetric C^-1 (reordered points)
   bamg::DBuf<float> Cinv32;
   bamg::DBuf<double> vgp;         // [n_pt][3] C^-1 g_p
+  bamg::DBuf<double> prec;        // [n_pt][PREC] point records: X | C^-1 (packed) | C^-1 g_p
   bamg::DBuf<double> gp;          // [n_pt][3] g_p
   bamg::DBuf<double> Dp;          // [n_pt][3] damping of the point block
   bamg::DBuf<double> A;           // [n_cam][45] packed damped A
   bamg::DBuf<float> A32;
   bamg::DBuf<double> Dc;          // [n_cam][9] damping of the camera block
   bamg::DBuf<double> b;           // [n_cam][9]
-  bamg::DBuf<double> gc;          // [n_cam][9]
   bamg::DBuf<double> Scc;         // [n_cam][81] block-Jacobi blocks (before inversion)
   bamg::DBuf<double> Sinv;        // [n_cam][81] inverses
   bamg::DBuf<float> Sinv32;

@@ -14,10 +14,10 @@ static size_t plan_bytes(const ba_plan* P) {
   b += P->obs_cam.bytes() + P->obs_pt.bytes() + P->obs_orig.bytes() + P->pt_off.bytes() + P->pt_orig.bytes();
   b += P->pt_new.bytes() + P->cam_off.bytes() + P->cam_obs.bytes() + P->obs_rank.bytes();
   b += P->tile_obs.bytes() + P->tile_pt.bytes() + P->tile_coff.bytes() + P->tile_cams.bytes() + P->obs_slot.bytes();
-  b += P->s0_ptr.bytes() + P->s0_pairs.bytes();
+  b += P->s0_ptr.bytes() + P->s0_q.bytes() + P->cam_q.bytes();
   b += P->campre.bytes() + P->F.bytes() + P->E.bytes() + P->fres.bytes() + P->F32.bytes() + P->E32.bytes();
   b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
-  b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->gc.bytes() + P->Scc.bytes();
+  b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->Scc.bytes() + P->prec.bytes();
   b += P->Sinv.bytes() + P->Sinv32.bytes();
   for (const Level& L : P->levels) {
     b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
@@ -45,7 +45,7 @@ static void allocate_step(ba_plan* P) {
   P->A.alloc((size_t)P->n_cam * 45);
   P->Dc.alloc((size_t)P->n_cam * 9);
   P->b.alloc((size_t)P->n_cam * 9);
-  P->gc.alloc((size_t)P->n_cam * 9);
+  P->prec.alloc((size_t)P->n_pt * PREC);
   P->Scc.alloc((size_t)P->n_cam * 81);
   P->Sinv.alloc((size_t)P->n_cam * 81);
   P->scratch = new Scratch();
@@ -372,9 +372,8 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   Level& L0 = P->levels[0];
   // explicit level-0 S (Section 3.6): needed for the Galerkin product and, when
   // cheaper than the implicit form, for smoothing
-  hipLaunchKernelGGL(k_explicit_s0, dim3((unsigned)L0.nnz), dim3(128), 0, s, L0.row_of.p, L0.col.p, L0.trans_pos.p,
-                     P->s0_ptr.p, P->s0_pairs.p, P->obs_pt.p, P->n_obs_pad, P->F.p, P->E.p, P->Cinv.p,
-                     P->Scc.p, L0.S.p);
+  hipLaunchKernelGGL(k_explicit_s0, dim3((unsigned)L0.nnz), dim3(64), 0, s, L0.row_of.p, L0.col.p, L0.trans_pos.p,
+                     P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p, P->Scc.p, L0.S.p);
   L0.explicit_op = level0_explicit(P, o, mixed ? 4 : 8);
   hipLaunchKernelGGL(k_nullspace0, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
                      L0.K.p);
@@ -447,13 +446,18 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   P->inspectable_mg = false;
   P->lambda = o->lambda;
   Timer tj(s);
-  eval_jacobian(P, cams, pts, uv, mixed, s);
-  hipLaunchKernelGGL(k_point_blocks, dim3(grid_of<double>(P->n_pt)), dim3(256), 0, s, P->n_pt, P->pt_off.p,
-                     P->pt_orig.p, P->n_obs_pad, P->E.p, P->fres.p, o->lambda, D, P->n_cam, P->Cinv.p,
-                     mixed ? P->Cinv32.p : nullptr, P->vgp.p, P->gp.p, P->Dp.p, P->errflag.p);
-  hipLaunchKernelGGL(k_camera_blocks, dim3(P->n_cam), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->obs_pt.p,
-                     P->n_obs_pad, P->F.p, P->E.p, P->fres.p, P->Cinv.p, P->vgp.p, o->lambda, D, P->A.p,
-                     mixed ? P->A32.p : nullptr, P->Dc.p, P->b.p, P->gc.p, P->Scc.p, P->Sinv.p,
+  hipLaunchKernelGGL(k_campre, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
+                     P->errflag.p);
+  hipLaunchKernelGGL(k_jacobian_tiles, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
+                     P->obs_slot.p, P->obs_cam.p, P->obs_orig.p, P->pt_orig.p, P->campre.p, pts, uv, P->n_obs_pad,
+                     o->lambda, D, P->n_cam, P->F.p, P->E.p, P->fres.p, mixed ? P->F32.p : nullptr,
+                     mixed ? P->E32.p : nullptr, P->Cinv.p, mixed ? P->Cinv32.p : nullptr, P->vgp.p, P->gp.p,
+                     P->Dp.p, P->prec.p, P->errflag.p);
+  BA_LAUNCH_CHECK();
+  check_errflag(P, s);
+  hipLaunchKernelGGL(k_camera_blocks, dim3(P->n_cam), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->cam_q.p,
+                     P->n_obs_pad, P->campre.p, P->prec.p, P->fres.p, o->lambda, D, P->A.p,
+                     mixed ? P->A32.p : nullptr, P->Dc.p, P->b.p, P->Scc.p, P->Sinv.p,
                      mixed ? P->Sinv32.p : nullptr, P->errflag.p);
   BA_LAUNCH_CHECK();
   check_errflag(P, s, "normal blocks");
@@ -585,7 +589,7 @@ static ba_status solve(ba_plan* P, const ba_opts* o, double* delta_cam, double* 
   const ba_status status = solve_camera_system(P, o, P->b.p, st, s);
   BA_HIP(hipMemcpyAsync(delta_cam, W.x.p, (size_t)W.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // back-substitution delta_p = C^-1 (-g_p - W^T delta_c)
-  hipLaunchKernelGGL(k_recover_points, dim3(grid_of<double>(P->n_pt)), dim3(256), 0, s, P->n_pt, P->pt_off.p,
+  hipLaunchKernelGGL(k_recover_tiles, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
                      P->pt_orig.p, P->obs_cam.p, P->n_obs_pad, P->F.p, P->E.p, P->Cinv.p, P->gp.p, -1.0, W.x.p,
                      delta_pt);
   BA_LAUNCH_CHECK();

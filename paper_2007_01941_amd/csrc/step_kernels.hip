@@ -132,36 +132,19 @@ __global__ void k_scatter_jacobian(int n_obs, const int32_t* __restrict__ obs_or
   if (E_out) for (int k = 0; k < 6; ++k) E_out[oo * 6 + k] = E[k * stride + o];
 }
 
-// ---------------------------------------------------------------- point blocks
+// ---------------------------------------------------------------- Jacobian + point blocks
 
-// C_p = sum E_o^T E_o + D_p, g_p = sum E_o^T f_o; C_p^-1 (packed), v_p = C_p^-1 g_p.
-// D_p = lambda diag(sum E^T E), or the explicit diagonal Dexp (caller order).
-__global__ __launch_bounds__(256) void k_point_blocks(
-    int n_pt, const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_orig, int64_t stride,
-    const double* __restrict__ E, const double* __restrict__ fres, double lambda,
-    const double* __restrict__ Dexp, int n_cam, double* __restrict__ Cinv, float* __restrict__ Cinv32,
-    double* __restrict__ vgp, double* __restrict__ gp_out, double* __restrict__ Dp_out, uint32_t* err) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n_pt) return;
-  double C[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
-  for (int o = pt_off[q]; o < pt_off[q + 1]; ++o) {
-    double e[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) e[k] = E[k * stride + o];
-    const double f0 = fres[o], f1 = fres[stride + o];
-    C[0] += e[0] * e[0] + e[3] * e[3];
-    C[1] += e[0] * e[1] + e[3] * e[4];
-    C[2] += e[0] * e[2] + e[3] * e[5];
-    C[3] += e[1] * e[1] + e[4] * e[4];
-    C[4] += e[1] * e[2] + e[4] * e[5];
-    C[5] += e[2] * e[2] + e[5] * e[5];
-    g[0] += e[0] * f0 + e[3] * f1;
-    g[1] += e[1] * f0 + e[4] * f1;
-    g[2] += e[2] * f0 + e[5] * f1;
-  }
+// C_p^-1 and the derived point quantities from the sums C0 = sum E^T E (packed 6)
+// and g = sum E^T f of one point q (reordered index; qo = caller index).
+// D_p = lambda diag(C0), or the explicit diagonal Dexp (caller order).
+__device__ __forceinline__ void finish_point(int q, int qo, const double C[6], const double g[3], double lambda,
+                                             const double* __restrict__ Dexp, int n_cam,
+                                             const double* __restrict__ pts, double* __restrict__ Cinv,
+                                             float* __restrict__ Cinv32, double* __restrict__ vgp,
+                                             double* __restrict__ gp_out, double* __restrict__ Dp_out,
+                                             double* __restrict__ prec, uint32_t* err) {
   double d[3];
   if (Dexp) {
-    const int qo = pt_orig[q];
     for (int k = 0; k < 3; ++k) d[k] = Dexp[(size_t)9 * n_cam + 3 * qo + k];
   } else {
     d[0] = lambda * C[0];
@@ -177,14 +160,98 @@ __global__ __launch_bounds__(256) void k_point_blocks(
     cholesky_inverse<3>(a, inv);
   }
   const double ci[6] = {inv[0], inv[1], inv[2], inv[4], inv[5], inv[8]};
+  double v[3];
+  for (int k = 0; k < 3; ++k) v[k] = inv[k * 3 + 0] * g[0] + inv[k * 3 + 1] * g[1] + inv[k * 3 + 2] * g[2];
+  double* rec = prec + (size_t)q * PREC;
+  for (int k = 0; k < 3; ++k) rec[k] = pts[(size_t)qo * 3 + k];
   for (int k = 0; k < 6; ++k) {
     Cinv[(size_t)q * 6 + k] = ci[k];
+    rec[3 + k] = ci[k];
     if (Cinv32) Cinv32[(size_t)q * 6 + k] = (float)ci[k];
   }
   for (int k = 0; k < 3; ++k) {
-    vgp[(size_t)q * 3 + k] = inv[k * 3 + 0] * g[0] + inv[k * 3 + 1] * g[1] + inv[k * 3 + 2] * g[2];
+    vgp[(size_t)q * 3 + k] = v[k];
+    rec[9 + k] = v[k];
     gp_out[(size_t)q * 3 + k] = g[k];
     Dp_out[(size_t)q * 3 + k] = d[k];
+  }
+}
+
+// Residual, Jacobian blocks and the point side of the normal equations in one
+// pass, one workgroup per tile of whole points (one thread per observation):
+// writes f, F, E (and FP32 copies); sums C0 = sum E^T E and g_p = sum E^T f per
+// point in LDS; then per point C_p = C0 + D_p, C_p^-1 (packed), v_p = C_p^-1 g_p,
+// and the point record [X | C_p^-1 | v_p] read by the camera-side kernels.
+__global__ __launch_bounds__(256) void k_jacobian_tiles(
+    const int32_t* __restrict__ tile_obs, const int32_t* __restrict__ tile_pt,
+    const int32_t* __restrict__ pt_off, const uint32_t* __restrict__ obs_slot,
+    const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_orig,
+    const int32_t* __restrict__ pt_orig,
+    const double* __restrict__ campre, const double* __restrict__ pts, const double* __restrict__ uv,
+    int64_t stride, double lambda, const double* __restrict__ Dexp, int n_cam, double* __restrict__ F,
+    double* __restrict__ E, double* __restrict__ fres, float* __restrict__ F32, float* __restrict__ E32,
+    double* __restrict__ Cinv, float* __restrict__ Cinv32, double* __restrict__ vgp,
+    double* __restrict__ gp_out, double* __restrict__ Dp_out, double* __restrict__ prec, uint32_t* err) {
+  // per-observation contributions [E^T E (6) | E^T f (3)], summed per point in
+  // observation order afterwards (deterministic, no atomics)
+  __shared__ double part[9][TILE_OBS];
+  const int t = blockIdx.x;
+  const int o0 = tile_obs[t], o1 = tile_obs[t + 1];
+  const int q0 = tile_pt[t], np = tile_pt[t + 1] - q0;
+  double sum[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) sum[k] = 0.0;
+  // more than TILE_OBS observations only for a tile holding one point
+  for (int o = o0 + threadIdx.x; o < o1; o += TILE_OBS) {
+    const int c = obs_cam[o];
+    const int pl = (int)(obs_slot[o] >> 16);
+    const int qo = pt_orig[q0 + pl];
+    const int oo = obs_orig[o];
+    const double X[3] = {pts[(size_t)qo * 3 + 0], pts[(size_t)qo * 3 + 1], pts[(size_t)qo * 3 + 2]};
+    double pi[2], Fo[18], e[6], z;
+    project_jacobian(campre + (size_t)c * 24, X, pi, Fo, e, &z);
+    const double r0 = pi[0] - uv[(size_t)oo * 2 + 0];
+    const double r1 = pi[1] - uv[(size_t)oo * 2 + 1];
+    if (!(z < 0.0)) atomicOr(err, ERRF_GEOMETRY);
+    if (!isfinite(r0) || !isfinite(r1) || !isfinite(X[0] + X[1] + X[2])) atomicOr(err, ERRF_NONFINITE);
+    fres[o] = r0;
+    fres[stride + o] = r1;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) F[k * stride + o] = Fo[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) E[k * stride + o] = e[k];
+    if (F32) {
+#pragma unroll
+      for (int k = 0; k < 18; ++k) F32[k * stride + o] = (float)Fo[k];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) E32[k * stride + o] = (float)e[k];
+    }
+    sum[0] += e[0] * e[0] + e[3] * e[3];
+    sum[1] += e[0] * e[1] + e[3] * e[4];
+    sum[2] += e[0] * e[2] + e[3] * e[5];
+    sum[3] += e[1] * e[1] + e[4] * e[4];
+    sum[4] += e[1] * e[2] + e[4] * e[5];
+    sum[5] += e[2] * e[2] + e[5] * e[5];
+    sum[6] += e[0] * r0 + e[3] * r1;
+    sum[7] += e[1] * r0 + e[4] * r1;
+    sum[8] += e[2] * r0 + e[5] * r1;
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) part[k][threadIdx.x] = sum[k];
+  __syncthreads();
+  for (int i = threadIdx.x; i < np; i += 256) {
+    const int q = q0 + i;
+    int l0 = pt_off[q] - o0, l1 = pt_off[q + 1] - o0;
+    if (l1 - l0 > TILE_OBS) { l0 = 0; l1 = TILE_OBS; }
+    double C[6] = {0, 0, 0, 0, 0, 0}, g[3] = {0, 0, 0};
+    for (int l = l0; l < l1; ++l) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) C[k] += part[k][l];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) g[k] += part[6 + k][l];
+    }
+    finish_point(q, pt_orig[q], C, g, lambda, Dexp, n_cam, pts, Cinv, Cinv32, vgp, gp_out, Dp_out, prec,
+                 err);
   }
 }
 
@@ -203,44 +270,57 @@ __device__ __forceinline__ void block_reduce(double (&acc)[NV], double* red /*[4
   __syncthreads();
 }
 
-// One workgroup (256 threads) per camera c, over its observations (camera-major):
-//   A0 = sum F^T F, g_c = sum F^T f                                  (pass 1)
-//   A = A0 + D_c, D_c = lambda diag(A0) (or explicit)
-//   T = sum Y C_p^-1 Y^T, u = sum Y v_p, Y = F^T E                    (pass 2)
-//   b = -g_c + u   (reduced right-hand side -g_c + W C^-1 g_p)
-//   S_cc = A - T   (diagonal block of S) and its inverse (block Jacobi).
+// Workgroup (256 threads) sum of 64 per-thread values: wave reduce-scatter,
+// then the 4 waves' totals through LDS. On return red[0 .. 64) holds the sums.
+__device__ __forceinline__ void block_reduce64(double (&acc)[64], double* red /*[4][64]*/) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  wave_reduce_scatter<64>(acc);
+  if (!(lane & 1)) {
+    red[wid * 64 + (lane & ~1)] = acc[0];
+    red[wid * 64 + (lane & ~1) + 1] = acc[1];
+  }
+  __syncthreads();
+  if (threadIdx.x < 64)
+    red[threadIdx.x] = red[threadIdx.x] + red[64 + threadIdx.x] + red[128 + threadIdx.x] + red[192 + threadIdx.x];
+  __syncthreads();
+}
+
+// One workgroup (256 threads) per camera c over its observations (camera-major
+// list), recomputing F_o and E_o from the camera and the point record instead
+// of gathering them from the point-major planes:
+//   pass 1:  A0 = sum F^T F;  A = A0 + D_c, D_c = lambda diag(A0) (or explicit)
+//   pass 2:  T = sum F^T M F with M = E C_p^-1 E^T (2 x 2), the camera's share
+//            of W C^-1 W^T;  b = sum F^T (E v_p - f) = -g_c + W C^-1 g_p
+//   S_cc = A - T (diagonal block of S) and its inverse (block Jacobi).
 __global__ __launch_bounds__(256) void k_camera_blocks(
     const int32_t* __restrict__ cam_off, const int32_t* __restrict__ cam_obs,
-    const int32_t* __restrict__ obs_pt, int64_t stride, const double* __restrict__ F,
-    const double* __restrict__ E, const double* __restrict__ fres, const double* __restrict__ Cinv,
-    const double* __restrict__ vgp, double lambda, const double* __restrict__ Dexp,
-    double* __restrict__ A_out, float* __restrict__ A32, double* __restrict__ Dc_out,
-    double* __restrict__ b_out, double* __restrict__ gc_out, double* __restrict__ Scc_out,
+    const int32_t* __restrict__ cam_q, int64_t stride, const double* __restrict__ campre,
+    const double* __restrict__ prec, const double* __restrict__ fres, double lambda,
+    const double* __restrict__ Dexp, double* __restrict__ A_out, float* __restrict__ A32,
+    double* __restrict__ Dc_out, double* __restrict__ b_out, double* __restrict__ Scc_out,
     double* __restrict__ Sinv, float* __restrict__ Sinv32, uint32_t* err) {
-  __shared__ double red[4 * 54];
+  __shared__ double red[4 * 64];
   __shared__ double S[81];
   __shared__ double Adiag[9], Ad[45];
   const int c = blockIdx.x;
   const int beg = cam_off[c], end = cam_off[c + 1];
-  double acc[54];
-  // ---- pass 1: A0 (45 packed) and g_c (9)
+  const double* cp = campre + (size_t)c * 24;
+  double acc[64];
+  // ---- pass 1: A0 (45 packed)
 #pragma unroll
-  for (int k = 0; k < 54; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 64; ++k) acc[k] = 0.0;
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
-    const int o = cam_obs[i];
-    double f[18];
-#pragma unroll
-    for (int k = 0; k < 18; ++k) f[k] = F[k * stride + o];
-    const double r0 = fres[o], r1 = fres[stride + o];
+    const double* rec = prec + (size_t)cam_q[i] * PREC;
+    const double X[3] = {rec[0], rec[1], rec[2]};
+    double pi[2], f[18], e[6], z;
+    project_jacobian(cp, X, pi, f, e, &z);
     int idx = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a)
 #pragma unroll
       for (int bb = a; bb < 9; ++bb) acc[idx++] += f[a] * f[bb] + f[9 + a] * f[9 + bb];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) acc[45 + a] += f[a] * r0 + f[9 + a] * r1;
   }
-  block_reduce<54>(acc, red);
+  block_reduce64(acc, red);
   if (threadIdx.x < 45) Ad[threadIdx.x] = red[threadIdx.x];
   if (threadIdx.x < 9) {
     const int a = threadIdx.x;
@@ -248,10 +328,8 @@ __global__ __launch_bounds__(256) void k_camera_blocks(
     const double dd = Dexp ? Dexp[(size_t)c * 9 + a] : lambda * a0;
     Adiag[a] = dd;
     Dc_out[(size_t)c * 9 + a] = dd;
-    gc_out[(size_t)c * 9 + a] = red[45 + a];
   }
   __syncthreads();
-  double gcv = threadIdx.x < 9 ? red[45 + threadIdx.x] : 0.0;
   if (threadIdx.x < 45) {
     // add damping on the diagonal of the packed matrix
     int i = 0, rem = threadIdx.x;
@@ -263,41 +341,45 @@ __global__ __launch_bounds__(256) void k_camera_blocks(
     if (A32) A32[(size_t)c * 45 + threadIdx.x] = (float)v;
   }
   __syncthreads();
-  // ---- pass 2: T = sum Y C^-1 Y^T (45 packed) and u = sum Y v_p (9)
+  // ---- pass 2: T (45 packed) and b (9)
 #pragma unroll
-  for (int k = 0; k < 54; ++k) acc[k] = 0.0;
+  for (int k = 0; k < 64; ++k) acc[k] = 0.0;
   for (int i = beg + threadIdx.x; i < end; i += blockDim.x) {
     const int o = cam_obs[i];
-    const int q = obs_pt[o];
-    double f[18], e[6];
+    const double* rec = prec + (size_t)cam_q[i] * PREC;
+    const double X[3] = {rec[0], rec[1], rec[2]};
+    const double C[9] = {rec[3], rec[4], rec[5], rec[4], rec[6], rec[7], rec[5], rec[7], rec[8]};
+    const double v0 = rec[9], v1 = rec[10], v2 = rec[11];
+    const double f0 = fres[o], f1 = fres[stride + o];
+    double pi[2], f[18], e[6], z;
+    project_jacobian(cp, X, pi, f, e, &z);
+    double ec[6];
 #pragma unroll
-    for (int k = 0; k < 18; ++k) f[k] = F[k * stride + o];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) e[k] = E[k * stride + o];
-    const double* ci = Cinv + (size_t)q * 6;
-    const double C[9] = {ci[0], ci[1], ci[2], ci[1], ci[3], ci[4], ci[2], ci[4], ci[5]};
-    double Y[27], YC[27];
-#pragma unroll
-    for (int a = 0; a < 9; ++a)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) Y[a * 3 + k] = f[a] * e[k] + f[9 + a] * e[3 + k];
-#pragma unroll
-    for (int a = 0; a < 9; ++a)
+    for (int r = 0; r < 2; ++r)
 #pragma unroll
       for (int k = 0; k < 3; ++k)
-        YC[a * 3 + k] = Y[a * 3 + 0] * C[0 * 3 + k] + Y[a * 3 + 1] * C[1 * 3 + k] + Y[a * 3 + 2] * C[2 * 3 + k];
+        ec[r * 3 + k] = e[r * 3 + 0] * C[0 * 3 + k] + e[r * 3 + 1] * C[1 * 3 + k] + e[r * 3 + 2] * C[2 * 3 + k];
+    const double m00 = ec[0] * e[0] + ec[1] * e[1] + ec[2] * e[2];
+    const double m01 = ec[0] * e[3] + ec[1] * e[4] + ec[2] * e[5];
+    const double m11 = ec[3] * e[3] + ec[4] * e[4] + ec[5] * e[5];
+    double mf[18];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      mf[k] = m00 * f[k] + m01 * f[9 + k];
+      mf[9 + k] = m01 * f[k] + m11 * f[9 + k];
+    }
     int idx = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a)
 #pragma unroll
-      for (int bb = a; bb < 9; ++bb)
-        acc[idx++] += YC[a * 3 + 0] * Y[bb * 3 + 0] + YC[a * 3 + 1] * Y[bb * 3 + 1] + YC[a * 3 + 2] * Y[bb * 3 + 2];
-    const double v0 = vgp[(size_t)q * 3], v1 = vgp[(size_t)q * 3 + 1], v2 = vgp[(size_t)q * 3 + 2];
+      for (int bb = a; bb < 9; ++bb) acc[idx++] += f[a] * mf[bb] + f[9 + a] * mf[9 + bb];
+    const double w0 = e[0] * v0 + e[1] * v1 + e[2] * v2 - f0;
+    const double w1 = e[3] * v0 + e[4] * v1 + e[5] * v2 - f1;
 #pragma unroll
-    for (int a = 0; a < 9; ++a) acc[45 + a] += Y[a * 3 + 0] * v0 + Y[a * 3 + 1] * v1 + Y[a * 3 + 2] * v2;
+    for (int a = 0; a < 9; ++a) acc[45 + a] += f[a] * w0 + f[9 + a] * w1;
   }
-  block_reduce<54>(acc, red);
-  if (threadIdx.x < 9) b_out[(size_t)c * 9 + threadIdx.x] = -gcv + red[45 + threadIdx.x];
+  block_reduce64(acc, red);
+  if (threadIdx.x < 9) b_out[(size_t)c * 9 + threadIdx.x] = red[45 + threadIdx.x];
   if (threadIdx.x < 81) {
     const int i = threadIdx.x / 9, j = threadIdx.x % 9;
     const int a = i < j ? i : j, bb = i < j ? j : i;
@@ -324,131 +406,6 @@ __global__ __launch_bounds__(256) void k_camera_blocks(
     if (Sinv32) Sinv32[(size_t)c * 81 + threadIdx.x] = (float)S[threadIdx.x];
   }
 }
-
-// ---------------------------------------------------------------- implicit Schur product
-
-// y_c = A_c x_c (packed symmetric A), one thread per (camera, row).
-template <class T>
-__global__ __launch_bounds__(256) void k_apply_A(int n_cam, const T* __restrict__ A,
-                                                 const T* __restrict__ x, T* __restrict__ y) {
-  const int gid = blockIdx.x * 252 + threadIdx.x;
-  const int c = gid / 9, i = gid % 9;
-  if (threadIdx.x >= 252 || c >= n_cam) return;
-  const T* a = A + (size_t)c * 45;
-  const T* xv = x + (size_t)c * 9;
-  T s = 0;
-#pragma unroll
-  for (int j = 0; j < 9; ++j) s += a[i <= j ? sym_index(9, i, j) : sym_index(9, j, i)] * xv[j];
-  y[(size_t)c * 9 + i] = s;
-}
-
-// y -= F^T E C^-1 E^T F x, one workgroup per tile of <= TILE_OBS observations
-// belonging to whole points. Camera vectors of the tile's cameras are staged
-// in LDS (x) and accumulated in LDS (y) before one global atomic add per
-// (tile, camera, component); point sums E^T F x are accumulated in LDS.
-template <class T>
-__global__ __launch_bounds__(256) void k_schur_tiles(
-    const int32_t* __restrict__ tile_obs, const int32_t* __restrict__ tile_pt,
-    const int32_t* __restrict__ tile_coff, const int32_t* __restrict__ tile_cams,
-    const uint32_t* __restrict__ obs_slot, const T* __restrict__ F, const T* __restrict__ E,
-    int64_t stride, const T* __restrict__ Cinv, const T* __restrict__ x, T* __restrict__ y,
-    const int* __restrict__ done) {
-  if (done && *done) return;
-  __shared__ T xs[TILE_SLOTS * 9];
-  __shared__ T ys[TILE_SLOTS * 9];
-  __shared__ T zs[(TILE_OBS / 2) * 3];
-  const int t = blockIdx.x;
-  const int o0 = tile_obs[t], o1 = tile_obs[t + 1];
-  const int q0 = tile_pt[t], np = tile_pt[t + 1] - q0;
-  const int c0 = tile_coff[t], nc = tile_coff[t + 1] - c0;
-  const int ncs = nc < TILE_SLOTS ? nc : TILE_SLOTS;
-  for (int i = threadIdx.x; i < ncs * 9; i += 256) {
-    const int s = i / 9, k = i - s * 9;
-    xs[i] = x[(size_t)tile_cams[c0 + s] * 9 + k];
-    ys[i] = T(0);
-  }
-  for (int i = threadIdx.x; i < np * 3; i += 256) zs[i] = T(0);
-  __syncthreads();
-
-  const int o = o0 + threadIdx.x;
-  const bool act = o < o1;
-  T f[18], e[6];
-  int slot = 0, pl = 0;
-  if (act) {
-#pragma unroll
-    for (int k = 0; k < 18; ++k) f[k] = F[k * stride + o];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) e[k] = E[k * stride + o];
-    const uint32_t w = obs_slot[o];
-    slot = (int)(w & 0xffffu);
-    pl = (int)(w >> 16);
-    const T* xv = slot < TILE_SLOTS ? &xs[slot * 9] : &x[(size_t)tile_cams[c0 + slot] * 9];
-    T s0 = 0, s1 = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) { s0 += f[k] * xv[k]; s1 += f[9 + k] * xv[k]; }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) atomicAdd(&zs[pl * 3 + k], e[k] * s0 + e[3 + k] * s1);
-  }
-  // observations beyond one per thread (only a single point with > TILE_OBS views)
-  for (int oo = o0 + 256 + threadIdx.x; oo < o1; oo += 256) {
-    const uint32_t w = obs_slot[oo];
-    const int sl = (int)(w & 0xffffu), pq = (int)(w >> 16);
-    const T* xv = sl < TILE_SLOTS ? &xs[sl * 9] : &x[(size_t)tile_cams[c0 + sl] * 9];
-    T s0 = 0, s1 = 0;
-    for (int k = 0; k < 9; ++k) { s0 += F[k * stride + oo] * xv[k]; s1 += F[(9 + k) * stride + oo] * xv[k]; }
-    for (int k = 0; k < 3; ++k) atomicAdd(&zs[pq * 3 + k], E[k * stride + oo] * s0 + E[(3 + k) * stride + oo] * s1);
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < np; i += 256) {
-    const T* ci = Cinv + (size_t)(q0 + i) * 6;
-    const T z0 = zs[i * 3], z1 = zs[i * 3 + 1], z2 = zs[i * 3 + 2];
-    zs[i * 3 + 0] = ci[0] * z0 + ci[1] * z1 + ci[2] * z2;
-    zs[i * 3 + 1] = ci[1] * z0 + ci[3] * z1 + ci[4] * z2;
-    zs[i * 3 + 2] = ci[2] * z0 + ci[4] * z1 + ci[5] * z2;
-  }
-  __syncthreads();
-  if (act) {
-    const T u0 = zs[pl * 3], u1 = zs[pl * 3 + 1], u2 = zs[pl * 3 + 2];
-    const T w0 = e[0] * u0 + e[1] * u1 + e[2] * u2;
-    const T w1 = e[3] * u0 + e[4] * u1 + e[5] * u2;
-    if (slot < TILE_SLOTS) {
-#pragma unroll
-      for (int k = 0; k < 9; ++k) atomicAdd(&ys[slot * 9 + k], -(f[k] * w0 + f[9 + k] * w1));
-    } else {
-      T* yv = y + (size_t)tile_cams[c0 + slot] * 9;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) unsafeAtomicAdd(&yv[k], -(f[k] * w0 + f[9 + k] * w1));
-    }
-  }
-  for (int oo = o0 + 256 + threadIdx.x; oo < o1; oo += 256) {
-    const uint32_t w = obs_slot[oo];
-    const int sl = (int)(w & 0xffffu), pq = (int)(w >> 16);
-    const T u0 = zs[pq * 3], u1 = zs[pq * 3 + 1], u2 = zs[pq * 3 + 2];
-    const T w0 = E[0 * stride + oo] * u0 + E[1 * stride + oo] * u1 + E[2 * stride + oo] * u2;
-    const T w1 = E[3 * stride + oo] * u0 + E[4 * stride + oo] * u1 + E[5 * stride + oo] * u2;
-    for (int k = 0; k < 9; ++k) {
-      const T v = -(F[k * stride + oo] * w0 + F[(9 + k) * stride + oo] * w1);
-      if (sl < TILE_SLOTS) atomicAdd(&ys[sl * 9 + k], v);
-      else unsafeAtomicAdd(&y[(size_t)tile_cams[c0 + sl] * 9 + k], v);
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < ncs * 9; i += 256) {
-    const int s = i / 9, k = i - s * 9;
-    unsafeAtomicAdd(&y[(size_t)tile_cams[c0 + s] * 9 + k], ys[i]);
-  }
-}
-
-template __global__ void k_schur_tiles<double>(const int32_t*, const int32_t*, const int32_t*,
-                                               const int32_t*, const uint32_t*, const double*,
-                                               const double*, int64_t, const double*, const double*,
-                                               double*, const int*);
-template __global__ void k_schur_tiles<float>(const int32_t*, const int32_t*, const int32_t*,
-                                              const int32_t*, const uint32_t*, const float*,
-                                              const float*, int64_t, const float*, const float*,
-                                              float*, const int*);
-template __global__ void k_apply_A<double>(int, const double*, const double*, double*);
-template __global__ void k_apply_A<float>(int, const float*, const float*, float*);
 
 // ---------------------------------------------------------------- camera-side half products
 
@@ -481,17 +438,22 @@ __global__ __launch_bounds__(256) void k_cam_FtEv(const int32_t* __restrict__ ca
     out[(size_t)c * 9 + threadIdx.x] = (base ? base[(size_t)c * 9 + threadIdx.x] : 0.0) + scale * red[threadIdx.x];
 }
 
-// Point recovery: x_p = C_p^-1 (r_p - sum_{o in p} E_o^T F_o x_c(o)), written in caller order.
-// r_p is given in reordered point order (rp, may be NULL for 0) scaled by rscale.
-__global__ __launch_bounds__(256) void k_recover_points(
-    int n_pt, const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_orig,
+// Point recovery: x_p = C_p^-1 (rscale r_p - sum_{o in p} E_o^T F_o x_c(o)), written
+// in caller order; r_p is in reordered point order (rp may be NULL for 0). One
+// workgroup per tile of whole points, one thread per observation (coalesced
+// plane reads); per-observation terms are summed per point in order.
+__global__ __launch_bounds__(256) void k_recover_tiles(
+    const int32_t* __restrict__ tile_obs, const int32_t* __restrict__ tile_pt,
+    const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_orig,
     const int32_t* __restrict__ obs_cam, int64_t stride, const double* __restrict__ F,
     const double* __restrict__ E, const double* __restrict__ Cinv, const double* __restrict__ rp,
     double rscale, const double* __restrict__ xc, double* __restrict__ out) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n_pt) return;
+  __shared__ double part[3][TILE_OBS];
+  const int t = blockIdx.x;
+  const int o0 = tile_obs[t], o1 = tile_obs[t + 1];
+  const int q0 = tile_pt[t], np = tile_pt[t + 1] - q0;
   double z0 = 0, z1 = 0, z2 = 0;
-  for (int o = pt_off[q]; o < pt_off[q + 1]; ++o) {
+  for (int o = o0 + threadIdx.x; o < o1; o += TILE_OBS) {
     const double* xv = xc + (size_t)obs_cam[o] * 9;
     double s0 = 0, s1 = 0;
 #pragma unroll
@@ -500,14 +462,25 @@ __global__ __launch_bounds__(256) void k_recover_points(
     z1 += E[1 * stride + o] * s0 + E[4 * stride + o] * s1;
     z2 += E[2 * stride + o] * s0 + E[5 * stride + o] * s1;
   }
-  const double r0 = (rp ? rscale * rp[(size_t)q * 3] : 0.0) - z0;
-  const double r1 = (rp ? rscale * rp[(size_t)q * 3 + 1] : 0.0) - z1;
-  const double r2 = (rp ? rscale * rp[(size_t)q * 3 + 2] : 0.0) - z2;
-  const double* ci = Cinv + (size_t)q * 6;
-  const size_t qo = pt_orig[q];
-  out[qo * 3 + 0] = ci[0] * r0 + ci[1] * r1 + ci[2] * r2;
-  out[qo * 3 + 1] = ci[1] * r0 + ci[3] * r1 + ci[4] * r2;
-  out[qo * 3 + 2] = ci[2] * r0 + ci[4] * r1 + ci[5] * r2;
+  part[0][threadIdx.x] = z0;
+  part[1][threadIdx.x] = z1;
+  part[2][threadIdx.x] = z2;
+  __syncthreads();
+  for (int i = threadIdx.x; i < np; i += 256) {
+    const int q = q0 + i;
+    int l0 = pt_off[q] - o0, l1 = pt_off[q + 1] - o0;
+    if (l1 - l0 > TILE_OBS) { l0 = 0; l1 = TILE_OBS; }
+    double y0 = 0, y1 = 0, y2 = 0;
+    for (int l = l0; l < l1; ++l) { y0 += part[0][l]; y1 += part[1][l]; y2 += part[2][l]; }
+    const double r0 = (rp ? rscale * rp[(size_t)q * 3] : 0.0) - y0;
+    const double r1 = (rp ? rscale * rp[(size_t)q * 3 + 1] : 0.0) - y1;
+    const double r2 = (rp ? rscale * rp[(size_t)q * 3 + 2] : 0.0) - y2;
+    const double* ci = Cinv + (size_t)q * 6;
+    const size_t qo = pt_orig[q];
+    out[qo * 3 + 0] = ci[0] * r0 + ci[1] * r1 + ci[2] * r2;
+    out[qo * 3 + 1] = ci[1] * r0 + ci[3] * r1 + ci[4] * r2;
+    out[qo * 3 + 2] = ci[2] * r0 + ci[4] * r1 + ci[5] * r2;
+  }
 }
 
 // v_p = C_p^-1 r_p for a point vector given in caller order (gathered into reordered order).
