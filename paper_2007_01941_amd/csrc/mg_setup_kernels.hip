@@ -56,6 +56,9 @@ __global__ __launch_bounds__(64) void k_qr_aggregates(int bs, const int32_t* __r
   }
   __syncthreads();
   const int ncol = rows < NS ? rows : NS;
+  // lane = (row group g, column c): column sums over rows r = g (mod 4), then
+  // two exchanges combine the 4 groups
+  const int c = lane & 15, g = lane >> 4;
   for (int j = 0; j < ncol; ++j) {
     double s = 0.0;
     for (int r = j + 1 + lane; r < rows; r += 64) s += A[r * NS + j] * A[r * NS + j];
@@ -71,34 +74,38 @@ __global__ __launch_bounds__(64) void k_qr_aggregates(int bs, const int32_t* __r
     __syncthreads();
     if (s > 0.0)
       for (int r = j + 1 + lane; r < rows; r += 64) A[r * NS + j] *= scal;
-    if (lane == 0) { A[j * NS + j] = beta; tau[j] = t; }
+    if (lane == 0) tau[j] = t;
     __syncthreads();
     // apply H_j = I - t v v^T (v = [1; A[j+1:, j]]) to columns j+1..NS-1
-    for (int c = j + 1; c < NS; ++c) {
-      double w = 0.0;
-      for (int r = j + lane; r < rows; r += 64) w += (r == j ? 1.0 : A[r * NS + j]) * A[r * NS + c];
-      w = wave_sum(w) * t;
-      __syncthreads();
-      for (int r = j + lane; r < rows; r += 64) A[r * NS + c] -= w * (r == j ? 1.0 : A[r * NS + j]);
-      __syncthreads();
-    }
+    double w = 0.0;
+    if (c > j)
+      for (int r = j + g; r < rows; r += 4) w += (r == j ? 1.0 : A[r * NS + j]) * A[r * NS + c];
+    w += __shfl_xor(w, 16, 64);
+    w += __shfl_xor(w, 32, 64);
+    w *= t;
+    if (c > j)
+      for (int r = j + g; r < rows; r += 4) A[r * NS + c] -= w * (r == j ? 1.0 : A[r * NS + j]);
+    __syncthreads();
+    if (lane == 0) A[j * NS + j] = beta;
+    __syncthreads();
   }
   // Q = H_0 ... H_{ncol-1} [I; 0]
   for (int idx = lane; idx < rows * NS; idx += 64) {
-    const int r = idx / NS, c = idx % NS;
-    Q[idx] = (r == c) ? 1.0 : 0.0;
+    const int r = idx / NS, cc = idx % NS;
+    Q[idx] = (r == cc) ? 1.0 : 0.0;
   }
   __syncthreads();
   for (int j = ncol - 1; j >= 0; --j) {
     const double t = tau[j];
-    for (int c = j; c < NS; ++c) {
-      double w = 0.0;
-      for (int r = j + lane; r < rows; r += 64) w += (r == j ? 1.0 : A[r * NS + j]) * Q[r * NS + c];
-      w = wave_sum(w) * t;
-      __syncthreads();
-      for (int r = j + lane; r < rows; r += 64) Q[r * NS + c] -= w * (r == j ? 1.0 : A[r * NS + j]);
-      __syncthreads();
-    }
+    double w = 0.0;
+    if (c >= j)
+      for (int r = j + g; r < rows; r += 4) w += (r == j ? 1.0 : A[r * NS + j]) * Q[r * NS + c];
+    w += __shfl_xor(w, 16, 64);
+    w += __shfl_xor(w, 32, 64);
+    w *= t;
+    if (c >= j)
+      for (int r = j + g; r < rows; r += 4) Q[r * NS + c] -= w * (r == j ? 1.0 : A[r * NS + j]);
+    __syncthreads();
   }
   // sign convention diag(R) >= 0; R = upper triangle of A's first NS rows
   __shared__ double sgn[NS];
@@ -365,53 +372,93 @@ __global__ __launch_bounds__(64) void k_mfma_probe(const double* X, const double
 // Gauss-Jordan elimination with 64 x 64 pivot blocks. With P = A_kk^-1, one
 // pivot step maps
 //   A_kk <- P,  A_kj <- P A_kj,  A_ik <- -A_ik P,  A_ij <- A_ij - A_ik P A_kj,
-// and after every block has served as pivot A holds A^-1. Each step is three
-// launches: the 64 x 64 pivot inverse (one workgroup, in LDS), the new pivot
-// row and column (one workgroup per block), and the rank-64 update of all
-// other blocks (one workgroup per block, 16 waves, each wave one 16 x 16 tile
-// on the FP64 matrix cores). nd is a multiple of 64; pivots are the diagonal
-// blocks of successive Schur complements, positive definite for SPD A.
+// and after every block has served as pivot A holds A^-1. Each step is two
+// launches: the pivot inverse (one workgroup) and the update of every block
+// (one workgroup per block, reading one copy of A and writing the other). nd is a
+// multiple of 64; pivots are the diagonal blocks of successive Schur
+// complements, positive definite for SPD A.
 constexpr int GJB = 64;
 
-// P = A_kk^-1 by unblocked Gauss-Jordan: 1024 threads, each keeping 4 entries
-// of the block in registers (column j = t % 64, rows t / 64 + 16 m); the pivot
-// row and column of every step are exchanged through double-buffered LDS, so
-// each step costs one barrier.
-__global__ __launch_bounds__(1024) void k_gj_pivot(int nd, const double* __restrict__ A, int k,
-                                                   double* __restrict__ Pbuf, uint32_t* err) {
-  __shared__ double rowp[2][GJB], colp[2][GJB];
-  const size_t k0 = (size_t)k * GJB;
+// In-place inverse of a 4 x 4 SPD matrix (row-major) by Gauss-Jordan without
+// pivoting; false if a pivot is not positive.
+__device__ __forceinline__ bool inv4(double (&a)[16]) {
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    const double piv = a[p * 4 + p];
+    ok = ok && (piv > 0.0);
+    const double ip = 1.0 / piv;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (j != p) a[p * 4 + j] *= ip;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i == p) continue;
+      const double aip = a[i * 4 + p];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (j != p) a[i * 4 + j] -= aip * a[p * 4 + j];
+      a[i * 4 + p] = -aip * ip;
+    }
+    a[p * 4 + p] = ip;
+  }
+  return ok;
+}
+
+// v <- inverse of a 64 x 64 SPD block held by 256 threads (thread t keeps
+// column j = t % 64, rows t / 64 + 4 m, m < 16), by Gauss-Jordan on 4 x 4
+// pivot blocks: pivot block q is rows 4q .. 4q+3, i.e. register v[q] of the
+// threads with t / 64 = 0 .. 3. Pivot rows and columns go through
+// double-buffered LDS (one barrier per pivot block); every thread inverts the
+// 4 x 4 pivot itself.
+__device__ __forceinline__ bool pivot_inverse64(double (&v)[16], double (*rowK)[4][GJB], double (*colK)[GJB][4]) {
   const int t = threadIdx.x, j = t % GJB, i0 = t / GJB;
-  double v[4];
+  bool ok = true;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) v[m] = A[(k0 + i0 + 16 * m) * nd + k0 + j];
-  bool bad = false;
-  for (int p = 0; p < GJB; ++p) {
-    const int buf = p & 1;
-    if (i0 == (p & 15)) rowp[buf][j] = v[p >> 4];
-    if (j == p) {
+  for (int q = 0; q < GJB / 4; ++q) {
+    const int buf = q & 1;
+    rowK[buf][i0][j] = v[q];
+    if ((j >> 2) == q) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) colp[buf][i0 + 16 * m] = v[m];
+      for (int m = 0; m < 16; ++m) colK[buf][i0 + 4 * m][j & 3] = v[m];
     }
     __syncthreads();
-    const double piv = rowp[buf][p];
-    if (!(piv > 0.0)) { bad = true; break; }   // uniform: all threads read the same pivot
-    const double ip = 1.0 / piv;
-    const double rp = rowp[buf][j] * ip;
+    double p4[16];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int i = i0 + 16 * m;
-      const double cp = colp[buf][i];
-      if (i == p) v[m] = (j == p) ? ip : rp;
-      else v[m] = (j == p) ? -cp * ip : v[m] - cp * rp;
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) p4[a * 4 + bb] = rowK[buf][a][4 * q + bb];
+    ok = inv4(p4) && ok;
+    double tj[4];
+    {
+      const double r0 = rowK[buf][0][j], r1 = rowK[buf][1][j], r2 = rowK[buf][2][j], r3 = rowK[buf][3][j];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) tj[a] = p4[a * 4 + 0] * r0 + p4[a * 4 + 1] * r1 + p4[a * 4 + 2] * r2 + p4[a * 4 + 3] * r3;
+    }
+    const bool jin = (j >> 2) == q;
+    const int bj = j & 3;
+    double pc[4];   // column bj of the pivot inverse (used when j is a pivot column)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+      pc[a] = bj == 0 ? p4[a * 4 + 0] : bj == 1 ? p4[a * 4 + 1] : bj == 2 ? p4[a * 4 + 2] : p4[a * 4 + 3];
+    // the coefficients that multiply the pivot column entries of row i
+    double w[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) w[a] = jin ? pc[a] : tj[a];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      if (m == q) {
+        // row 4q + i0 of the pivot block row
+        v[m] = i0 == 0 ? w[0] : i0 == 1 ? w[1] : i0 == 2 ? w[2] : w[3];
+      } else {
+        const int i = i0 + 4 * m;
+        const double c0 = colK[buf][i][0], c1 = colK[buf][i][1], c2 = colK[buf][i][2], c3 = colK[buf][i][3];
+        const double d = c0 * w[0] + c1 * w[1] + c2 * w[2] + c3 * w[3];
+        v[m] = jin ? -d : v[m] - d;
+      }
     }
   }
-  if (bad) {
-    if (t == 0) atomicOr(err, ERRF_NOT_SPD);
-    return;
-  }
-#pragma unroll
-  for (int m = 0; m < 4; ++m) Pbuf[(i0 + 16 * m) * GJB + j] = v[m];
+  return ok;
 }
 
 // One 64 x 64 block product on 16 waves: wave w owns output tile (w/4, w%4);
@@ -430,49 +477,74 @@ __device__ __forceinline__ double* block_tile(double* B, int ld) {
   return B + (size_t)((w >> 2) * 16) * ld + (w & 3) * 16;
 }
 
-// New pivot row and column: for block b != k, Row_b = P A_kb and Col_b = -A_bk P,
-// and the old column block kept for the update (Cold_b = A_bk).
-__global__ __launch_bounds__(1024) void k_gj_panel(int nd, const double* __restrict__ A, int k,
-                                                   const double* __restrict__ Pbuf, double* __restrict__ Row,
-                                                   double* __restrict__ Col, double* __restrict__ Cold) {
-  const int b = blockIdx.x;
-  if (b == k) return;
-  const size_t k0 = (size_t)k * GJB, b0 = (size_t)b * GJB;
-  const double* Akb = A + k0 * nd + b0;   // row k, block b
-  const double* Abk = A + b0 * nd + k0;   // row b, block k
-  d4 r = {0, 0, 0, 0}, c = {0, 0, 0, 0};
-  r = block_mma(r, Pbuf, GJB, Akb, nd, 1.0);
-  c = block_mma(c, Abk, nd, Pbuf, GJB, -1.0);
-  tile_store(block_tile(Row + b0, nd), nd, r);          // Row: 64 x nd
-  tile_store(block_tile(Col + b0 * GJB, GJB), GJB, c);  // Col: nd x 64
-  // copy of the old column block
-  for (int idx = threadIdx.x; idx < GJB * GJB; idx += 1024)
-    Cold[(b0 + idx / GJB) * GJB + idx % GJB] = Abk[(size_t)(idx / GJB) * nd + idx % GJB];
+// P = A_kk^-1 for pivot step k (one workgroup of 256 threads).
+__global__ __launch_bounds__(256) void k_gj_pivot(int nd, const double* __restrict__ A, int k,
+                                                  double* __restrict__ Pbuf, uint32_t* err) {
+  __shared__ double rowK[2][4][GJB];
+  __shared__ double colK[2][GJB][4];
+  const size_t k0 = (size_t)k * GJB;
+  const int t = threadIdx.x, jj = t % GJB, ii = t / GJB;
+  double v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = A[(k0 + ii + 4 * m) * nd + k0 + jj];
+  if (!pivot_inverse64(v, rowK, colK)) {
+    if (t == 0) atomicOr(err, ERRF_NOT_SPD);
+  }
+#pragma unroll
+  for (int m = 0; m < 16; ++m) Pbuf[(ii + 4 * m) * GJB + jj] = v[m];
 }
 
-// Rank-64 update of every block (i, j), i, j != k: A_ij -= Cold_i Row_j; the
-// pivot row, column and block take their new values.
-__global__ __launch_bounds__(1024) void k_gj_update(int nd, double* __restrict__ A, int k,
-                                                    const double* __restrict__ Pbuf, const double* __restrict__ Row,
-                                                    const double* __restrict__ Col, const double* __restrict__ Cold) {
-  const int nb = nd / GJB;
-  const int i = blockIdx.x / nb, j = blockIdx.x % nb;
-  const size_t i0 = (size_t)i * GJB, j0 = (size_t)j * GJB;
-  double* Aij = A + i0 * nd + j0;
-  if (i == k && j == k) {
-    for (int idx = threadIdx.x; idx < GJB * GJB; idx += 1024) Aij[(size_t)(idx / GJB) * nd + idx % GJB] = Pbuf[idx];
-  } else if (i == k) {
-    for (int idx = threadIdx.x; idx < GJB * GJB; idx += 1024)
-      Aij[(size_t)(idx / GJB) * nd + idx % GJB] = Row[(size_t)(idx / GJB) * nd + j0 + idx % GJB];
-  } else if (j == k) {
-    for (int idx = threadIdx.x; idx < GJB * GJB; idx += 1024)
-      Aij[(size_t)(idx / GJB) * nd + idx % GJB] = Col[(i0 + idx / GJB) * GJB + idx % GJB];
-  } else {
-    double* t = block_tile(Aij, nd);
-    d4 acc = tile_load(t, nd);
-    acc = block_mma(acc, Cold + i0 * GJB, GJB, Row + j0, nd, -1.0);
-    tile_store(t, nd, acc);
+// 64 x 64 block (row stride ld) into LDS (row stride GJB + 1), coalesced.
+__device__ __forceinline__ void stage_block(double* __restrict__ dst, const double* __restrict__ src, size_t ld) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int idx = threadIdx.x + 1024 * r;
+    dst[(idx / GJB) * (GJB + 1) + idx % GJB] = src[(size_t)(idx / GJB) * ld + idx % GJB];
   }
+}
+
+// Pivot step k of blocked Gauss-Jordan from Ain to Aout, given P = A_kk^-1:
+// one workgroup (16 waves) per 64 x 64 block (i, j) writes
+//   (k, k): P;   (k, j): P A_kj;   (i, k): -A_ik P;   else A_ij - A_ik (P A_kj),
+// operands staged in LDS, products on the FP64 matrix cores.
+__global__ __launch_bounds__(1024) void k_gj_update(int nd, const double* __restrict__ Ain, double* __restrict__ Aout,
+                                                    int k, const double* __restrict__ Pbuf) {
+  constexpr int LD = GJB + 1;
+  __shared__ double X[GJB * LD];
+  __shared__ double Y[GJB * LD];
+  const int nb = nd / GJB;
+  const int bi = blockIdx.x / nb, bj = blockIdx.x % nb;
+  const size_t k0 = (size_t)k * GJB, i0 = (size_t)bi * GJB, j0 = (size_t)bj * GJB;
+  double* out = block_tile(Aout + i0 * nd + j0, nd);
+  d4 acc = {0, 0, 0, 0};
+  if (bi == k && bj == k) {
+    stage_block(X, Pbuf, GJB);
+    __syncthreads();
+    acc = tile_load(block_tile(X, LD), LD);
+  } else if (bi == k) {
+    stage_block(X, Pbuf, GJB);
+    stage_block(Y, Ain + k0 * nd + j0, nd);
+    __syncthreads();
+    acc = block_mma(acc, X, LD, Y, LD, 1.0);
+  } else if (bj == k) {
+    stage_block(X, Ain + i0 * nd + k0, nd);
+    stage_block(Y, Pbuf, GJB);
+    __syncthreads();
+    acc = block_mma(acc, X, LD, Y, LD, -1.0);
+  } else {
+    stage_block(X, Pbuf, GJB);
+    stage_block(Y, Ain + k0 * nd + j0, nd);
+    __syncthreads();
+    d4 tk = {0, 0, 0, 0};
+    tk = block_mma(tk, X, LD, Y, LD, 1.0);   // T = P A_kj
+    __syncthreads();                          // every wave is done with X and Y
+    tile_store(block_tile(Y, LD), LD, tk);
+    stage_block(X, Ain + i0 * nd + k0, nd);
+    __syncthreads();
+    acc = tile_load(block_tile(const_cast<double*>(Ain) + i0 * nd + j0, nd), nd);
+    acc = block_mma(acc, X, LD, Y, LD, -1.0);
+  }
+  tile_store(out, nd, acc);
 }
 
 }  // namespace bamg

@@ -53,7 +53,8 @@ struct Level {
   // V-cycle work vectors, FP64 and FP32 (n * bs each)
   DBuf<double> lz_u, lz_v, lz_up, lz_vp, lz_av, lz_dav, lz_w, lz_dw;   // Lanczos vectors
   DBuf<double> lz_s;         // Lanczos scalars: alpha[32], beta[32], norm, b2, count, stop
-  DBuf<double> gj_scale, gj_piv, gj_row, gj_col, gj_cold;   // coarsest level: Gauss-Jordan work
+  DBuf<double> gj_scale;     // coarsest level: equilibration scales
+  DBuf<double> gj_piv;       // coarsest level: inverse of the current 64 x 64 pivot block
   DBuf<double> vb, vx, vr, vd, vt, vpart;
   DBuf<float> fb, fx, fr, fd, ft, fpart;   // vpart/fpart: restriction partials (n * NS)
 };

@@ -68,9 +68,6 @@ static void allocate_step(ba_plan* P) {
       L.inv.alloc((size_t)L.nd * L.nd);
       L.gj_scale.alloc(L.nd);
       L.gj_piv.alloc(GJB * GJB);
-      L.gj_row.alloc((size_t)GJB * L.nd);
-      L.gj_col.alloc((size_t)GJB * L.nd);
-      L.gj_cold.alloc((size_t)GJB * L.nd);
     } else {
       for (DBuf<double>* v : {&L.lz_u, &L.lz_v, &L.lz_up, &L.lz_vp, &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw})
         v->alloc(nv);
@@ -400,10 +397,6 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(tot)), dim3(256), 0, s, Lc.n, Lc.bs, Lc.nd, Lc.row_of.p,
                      Lc.col.p, Lc.nnz, Lc.S.p, Lc.dense.p);
   DBuf<double>& scl = Lc.gj_scale;
-  DBuf<double>& pbuf = Lc.gj_piv;
-  DBuf<double>& row = Lc.gj_row;
-  DBuf<double>& col = Lc.gj_col;
-  DBuf<double>& cold = Lc.gj_cold;
   const int64_t nd2 = (int64_t)Lc.nd * Lc.nd;
   // invert the equilibrated matrix s S s + eps I (s = diag^-1/2, eps = coarse_shift),
   // then scale back: inv = s (s S s + eps I)^-1 s
@@ -413,10 +406,11 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
                      o->coarse_shift);
   const int nbk = Lc.nd / GJB;
   for (int k = 0; k < nbk; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(1024), 0, s, Lc.nd, Lc.dense.p, k, pbuf.p, P->errflag.p);
-    hipLaunchKernelGGL(k_gj_panel, dim3(nbk), dim3(1024), 0, s, Lc.nd, Lc.dense.p, k, pbuf.p, row.p, col.p, cold.p);
-    hipLaunchKernelGGL(k_gj_update, dim3(nbk * nbk), dim3(1024), 0, s, Lc.nd, Lc.dense.p, k, pbuf.p, row.p, col.p,
-                       cold.p);
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)Lc.dense.p, k, Lc.gj_piv.p,
+                       P->errflag.p);
+    hipLaunchKernelGGL(k_gj_update, dim3(nbk * nbk), dim3(1024), 0, s, Lc.nd, (const double*)Lc.dense.p, Lc.inv.p,
+                       k, (const double*)Lc.gj_piv.p);
+    std::swap(Lc.dense, Lc.inv);
   }
   std::swap(Lc.dense, Lc.inv);
   hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.inv.p, scl.p, 0.0);
