@@ -83,20 +83,34 @@ struct Timer {
 template <class T>
 static void schur_apply_dev(ba_plan* P, const T* x, T* y, const int* done, hipStream_t s);
 
+// y -= F^T E C^-1 E^T F x (the tile kernel alone; y already holds A x).
+template <class T>
+static void schur_tiles_dev(ba_plan* P, const T* x, T* y, const int* done, hipStream_t s);
+
+template <>
+void schur_tiles_dev<double>(ba_plan* P, const double* x, double* y, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_schur_tiles<double>, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
+                     P->tile_coff.p, P->tile_cams.p, P->tile_cseg.p, P->pt_off.p, P->obs_slot.p, P->F.p, P->E.p,
+                     P->n_obs_pad, P->Cinv.p, x, y, P->n_tiles, done);
+}
+
+template <>
+void schur_tiles_dev<float>(ba_plan* P, const float* x, float* y, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_schur_tiles<float>, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
+                     P->tile_coff.p, P->tile_cams.p, P->tile_cseg.p, P->pt_off.p, P->obs_slot.p, P->F32.p, P->E32.p,
+                     P->n_obs_pad, P->Cinv32.p, x, y, P->n_tiles, done);
+}
+
 template <>
 void schur_apply_dev<double>(ba_plan* P, const double* x, double* y, const int* done, hipStream_t s) {
   hipLaunchKernelGGL(k_apply_A<double>, dim3(ceil_div(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam, P->A.p, x, y);
-  hipLaunchKernelGGL(k_schur_tiles<double>, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
-                     P->tile_coff.p, P->tile_cams.p, P->obs_slot.p, P->F.p, P->E.p, P->n_obs_pad, P->Cinv.p,
-                     x, y, done);
+  schur_tiles_dev<double>(P, x, y, done, s);
 }
 
 template <>
 void schur_apply_dev<float>(ba_plan* P, const float* x, float* y, const int* done, hipStream_t s) {
   hipLaunchKernelGGL(k_apply_A<float>, dim3(ceil_div(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam, P->A32.p, x, y);
-  hipLaunchKernelGGL(k_schur_tiles<float>, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
-                     P->tile_coff.p, P->tile_cams.p, P->obs_slot.p, P->F32.p, P->E32.p, P->n_obs_pad,
-                     P->Cinv32.p, x, y, done);
+  schur_tiles_dev<float>(P, x, y, done, s);
 }
 
 }  // namespace bamg

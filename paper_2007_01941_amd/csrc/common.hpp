@@ -103,6 +103,7 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // Tile geometry of the point-major observation layout.
 constexpr int TILE_OBS = 256;     // observations per tile (one per thread)
+constexpr int S0_CHUNK = 128;    // shared points per wave in the explicit level-0 S
 constexpr int PREC = 16;         // doubles per point record (X 3, C^-1 6, C^-1 g_p 3, padding)
 constexpr int TILE_SLOTS = 96;    // cameras of a tile kept in LDS (others go to global atomics)
 

@@ -128,6 +128,16 @@ __device__ __forceinline__ void cholesky_inverse(T* a, T* out) {
 }
 
 // Wave-wide sum (64 lanes).
+// Workgroups are dealt round-robin to the 8 XCDs of the chip (each with its
+// own L2). For a grid of 8 ceil(n / 8) workgroups over n work items whose
+// neighbours share data, map workgroup b to item (b % 8) ceil(n / 8) + b / 8:
+// every XCD then works through one contiguous range. Items >= n are idle.
+__device__ __forceinline__ int xcd_block(int b, int n) {
+  const int per = (n + 7) / 8;
+  return (b % 8) * per + b / 8;
+}
+__host__ __device__ constexpr int xcd_grid(int n) { return (n + 7) / 8 * 8; }
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

@@ -103,7 +103,10 @@ static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
     t_pt.push_back(n_pt);
   }
   const int n_tiles = (int)t_obs.size() - 1;
-  std::vector<int32_t> t_coff{0}, t_cams;
+  // Per tile: its distinct cameras (ascending; an observation's camera slot is
+  // the index in this list), and the tile's observations sorted by slot: the
+  // rank of each observation in that order and the first rank of every slot.
+  std::vector<int32_t> t_coff{0}, t_cams, t_cseg;
   std::vector<uint32_t> slot(n_obs);
   std::vector<int32_t> mark(n_cam, -1), slot_of(n_cam, 0);
   int max_tc = 0;
@@ -116,8 +119,17 @@ static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
     std::sort(cams.begin(), cams.end());
     BA_CHECK(cams.size() <= 65535, BA_ERR_LIMIT, "tile with too many cameras");
     for (size_t i = 0; i < cams.size(); ++i) slot_of[cams[i]] = (int32_t)i;
-    for (int64_t o = t_obs[t]; o < t_obs[t + 1]; ++o)
-      slot[o] = (uint32_t)slot_of[P->h_obs_cam[o]] | ((uint32_t)(P->h_obs_pt[o] - t_pt[t]) << 16);
+    std::vector<int32_t> seg(cams.size() + 1, 0);
+    for (int64_t o = t_obs[t]; o < t_obs[t + 1]; ++o) ++seg[slot_of[P->h_obs_cam[o]] + 1];
+    for (size_t i = 0; i < cams.size(); ++i) seg[i + 1] += seg[i];
+    const bool small = t_obs[t + 1] - t_obs[t] <= TILE_OBS;   // else: a single point, no ranks
+    std::vector<int32_t> cur(seg.begin(), seg.end() - 1);
+    for (int64_t o = t_obs[t]; o < t_obs[t + 1]; ++o) {
+      const int sl = slot_of[P->h_obs_cam[o]];
+      const uint32_t rank = small ? (uint32_t)cur[sl]++ : 0u;
+      slot[o] = (uint32_t)sl | ((uint32_t)(P->h_obs_pt[o] - t_pt[t]) << 16) | (rank << 24);
+    }
+    t_cseg.insert(t_cseg.end(), seg.begin(), seg.end() - 1);
     t_cams.insert(t_cams.end(), cams.begin(), cams.end());
     t_coff.push_back((int32_t)t_cams.size());
     max_tc = std::max(max_tc, (int)cams.size());
@@ -146,6 +158,7 @@ static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
   P->tile_pt.upload(t_pt, s);
   P->tile_coff.upload(t_coff, s);
   P->tile_cams.upload(t_cams, s);
+  P->tile_cseg.upload(t_cseg, s);
   P->obs_slot.upload(slot, s);
   BA_HIP(hipStreamSynchronize(s));
 }
@@ -237,8 +250,17 @@ static void build_s0_pairs(ba_plan* P, const Level& L0, hipStream_t s) {
     for (int64_t a = P->h_pt_off[q]; a < P->h_pt_off[q + 1]; ++a)
       for (int64_t b = a + 1; b < P->h_pt_off[q + 1]; ++b)
         pts[cur[entry(P->h_obs_cam[a], P->h_obs_cam[b])]++] = q;
+  std::vector<int32_t> ce, cb;
+  for (int64_t e = 0; e < L0.nnz; ++e)
+    for (int32_t h = cnt[e]; h < cnt[e + 1]; h += S0_CHUNK) {
+      ce.push_back((int32_t)e);
+      cb.push_back(h);
+    }
+  P->s0_chunks = (int32_t)ce.size();
   P->s0_ptr.upload(cnt, s);
   P->s0_q.upload(pts, s);
+  P->s0_chunk_e.upload(ce, s);
+  P->s0_chunk_beg.upload(cb, s);
 }
 
 static void aggregate_level(ba_plan* P, Level& L, int cap, hipStream_t s) {

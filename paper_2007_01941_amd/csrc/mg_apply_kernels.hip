@@ -7,37 +7,73 @@
 
 namespace bamg {
 
-// y = S x for a block-sparse S (BS x BS blocks, CSR of blocks). One wave per
-// block row: lane (part, comp) accumulates component `comp` over the row's
-// blocks part, part + P, ... and the parts are summed through LDS.
-template <int BS, class T>
-__global__ __launch_bounds__(256) void k_bsr_spmv(int n, const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ col,
-                                                  const T* __restrict__ S, const T* __restrict__ x,
-                                                  T* __restrict__ y, const int* done) {
+// Epilogues of the block-row product t = (S v)_i (one node i per workgroup):
+enum RowEpilogue {
+  EP_STORE = 0,     // out_i = t
+  EP_RESID = 1,     // r_i -= t
+  EP_CHEB = 2,      // v = d_in:  r_i -= t;  d_out_i = c1 d_in_i + c2 D_i^-1 r_i;  x_out_i = x_in_i + d_out_i
+  EP_CHEB_POST = 3  // v = x_in:  r_i = b_i - t;  d_out_i = c2 D_i^-1 r_i;  x_out_i = x_in_i + d_out_i
+};
+
+// Block-sparse product with the explicit level operator (BS x BS blocks, CSR
+// of blocks), one workgroup of 256 threads per block row: thread (part, comp)
+// accumulates component comp over the row's blocks part, part + PARTS, ...
+// (PARTS = 256 / BS; consecutive threads read consecutive rows of a block),
+// the parts are summed in LDS, and the row's Chebyshev update (EP_CHEB,
+// EP_CHEB_POST) or residual update (EP_RESID) is applied in place: the
+// workgroup owns all of node i. The product's input v is never written here
+// (d_in, d_out and x_in, x_out are different buffers where v is one of them).
+template <int BS, class T, int EP>
+__global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restrict__ rowptr,
+                                                 const int32_t* __restrict__ col, const T* __restrict__ S,
+                                                 const T* __restrict__ v, T* __restrict__ out,
+                                                 const T* __restrict__ Dinv, const T* __restrict__ b,
+                                                 T* __restrict__ r, const T* __restrict__ d_in,
+                                                 T* __restrict__ d_out, const T* __restrict__ x_in,
+                                                 T* __restrict__ x_out, T c1, T c2, const int* done) {
   if (done && *done) return;
-  constexpr int PARTS = 64 / BS;
-  __shared__ T red[4][64];
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + wid;
-  const int part = lane / BS, comp = lane % BS;
+  constexpr int PARTS = 256 / BS;
+  __shared__ T red[256];
+  __shared__ T rs[BS];
+  const int row = blockIdx.x;
+  const int part = threadIdx.x / BS, comp = threadIdx.x % BS;
   T acc = 0;
-  if (row < n && part < PARTS) {
-    for (int e = rowptr[row] + part; e < rowptr[row + 1]; e += PARTS) {
+  if (part < PARTS) {
+    const int e1 = rowptr[row + 1];
+    for (int e = rowptr[row] + part; e < e1; e += PARTS) {
       const T* blk = S + (size_t)e * BS * BS + comp * BS;
-      const T* xv = x + (size_t)col[e] * BS;
+      const T* xv = v + (size_t)col[e] * BS;
 #pragma unroll
       for (int k = 0; k < BS; ++k) acc += blk[k] * xv[k];
     }
   }
-  red[wid][lane] = acc;
+  red[threadIdx.x] = acc;
   __syncthreads();
-  if (row < n && lane < BS) {
-    T s = 0;
-#pragma unroll
-    for (int p = 0; p < PARTS; ++p) s += red[wid][p * BS + lane];
-    y[(size_t)row * BS + lane] = s;
+  const bool own = threadIdx.x < BS;
+  const size_t k = (size_t)row * BS + comp;
+  T rv = 0;
+  if (own) {
+    T tsum = 0;
+#pragma unroll 4
+    for (int p = 0; p < PARTS; ++p) tsum += red[p * BS + comp];
+    if (EP == EP_STORE) {
+      out[k] = tsum;
+    } else {
+      rv = EP == EP_CHEB_POST ? b[k] - tsum : r[k] - tsum;
+      r[k] = rv;
+      rs[comp] = rv;
+    }
   }
+  if (EP == EP_STORE || EP == EP_RESID) return;
+  __syncthreads();
+  if (!own) return;
+  const T* m = Dinv + (size_t)row * BS * BS + comp * BS;
+  T z = 0;
+#pragma unroll
+  for (int k2 = 0; k2 < BS; ++k2) z += m[k2] * rs[k2];
+  const T dv = EP == EP_CHEB ? c1 * d_in[k] + c2 * z : c2 * z;
+  d_out[k] = dv;
+  x_out[k] = x_in[k] + dv;
 }
 
 // z = D^-1 r block by block (BS x BS inverse blocks), one thread per dof.

@@ -6,6 +6,9 @@
 
 namespace bamg {
 
+// Accumulator of one 16 x 16 FP64 MFMA tile (4 entries per lane).
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------- near-nullspace
 
 // K rows of camera c (9 x 16, row-major): columns 0..8 constant in each camera
@@ -124,71 +127,94 @@ __global__ __launch_bounds__(64) void k_qr_aggregates(int bs, const int32_t* __r
 
 // ---------------------------------------------------------------- explicit level-0 S
 
+// Level-0 S before the off-diagonal sums: diagonal blocks = the block-Jacobi
+// blocks S_cc, every other block 0.
+__global__ void k_s0_init(int64_t n, const int32_t* __restrict__ row_of, const int32_t* __restrict__ col,
+                          const double* __restrict__ Scc, double* __restrict__ S) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n) return;
+  const int64_t e = idx / 81;
+  const int k = (int)(idx - e * 81);
+  const int i = row_of[e];
+  S[idx] = i == col[e] ? Scc[(size_t)i * 81 + k] : 0.0;
+}
+
 // Off-diagonal block (i, j), i < j, of S = A - W C^-1 W^T:
-//   S_ij = - sum_{p seen by i and j} F_ip^T (E_ip C_p^-1 E_jp^T) F_jp,
-// one wave per upper entry, one lane per shared point (the plan lists the
-// points of every block). Each lane recomputes both cameras' Jacobian blocks
-// from the camera data and the point record [X | C_p^-1], accumulates the 81
-// entries, and the wave sums them with a reduce-scatter. Diagonal blocks are
-// the block-Jacobi blocks S_cc; both (i, j) and (j, i) are written.
+//   S_ij = - sum_{p seen by i and j} F_ip^T (E_ip C_p^-1 E_jp^T) F_jp = - U^T V,
+// with U stacking the 2 x 9 blocks F_ip and V the blocks M_p F_jp
+// (M_p = E_ip C_p^-1 E_jp^T, 2 x 2) over the shared points p (the plan lists
+// them per block and cuts every block's list into chunks of at most
+// S0_CHUNK points, so that heavy blocks spread over many waves). One wave per
+// chunk: in batches of 64 points each lane recomputes both cameras' Jacobian
+// blocks from the camera data and the point record [X | C_p^-1] and leaves
+// its 2 rows of U and V in LDS; then U^T V accumulates on the FP64 matrix
+// cores (16 x 16 x 4, 9 x 9 used), two points per instruction; the chunk's
+// sum is added to blocks (i, j) and (j, i) with global atomics.
 __global__ __launch_bounds__(64) void k_explicit_s0(
+    const int32_t* __restrict__ chunk_e, const int32_t* __restrict__ chunk_beg,
     const int32_t* __restrict__ row_of, const int32_t* __restrict__ col,
     const int32_t* __restrict__ trans_pos, const int32_t* __restrict__ s0_ptr,
     const int32_t* __restrict__ s0_q, const double* __restrict__ campre, const double* __restrict__ prec,
-    const double* __restrict__ Scc, double* __restrict__ S) {
-  const int e = blockIdx.x;
+    double* __restrict__ S) {
+  __shared__ double Us[128 * 9];
+  __shared__ double Vs[128 * 9];
+  const int ch = blockIdx.x;
+  const int e = chunk_e[ch];
   const int i = row_of[e], j = col[e];
   const int lane = threadIdx.x;
-  if (i == j) {
-    for (int k = lane; k < 81; k += 64) S[(size_t)e * 81 + k] = Scc[(size_t)i * 81 + k];
-    return;
-  }
-  if (i > j) return;
   const double* ci = campre + (size_t)i * 24;
   const double* cj = campre + (size_t)j * 24;
-  double acc[96];
+  const int kq = lane >> 4, cc = lane & 15;
+  d4 acc = {0, 0, 0, 0};
+  const int beg = chunk_beg[ch];
+  const int end = min(s0_ptr[e + 1], beg + S0_CHUNK);
+  for (int base = beg; base < end; base += 64) {
+    const int nh = end - base < 64 ? end - base : 64;
+    if (lane < nh) {
+      const double* rec = prec + (size_t)s0_q[base + lane] * PREC;
+      const double X[3] = {rec[0], rec[1], rec[2]};
+      const double C[9] = {rec[3], rec[4], rec[5], rec[4], rec[6], rec[7], rec[5], rec[7], rec[8]};
+      double pi[2], fi[18], ei[6], fj[18], ej[6], z;
+      project_jacobian(ci, X, pi, fi, ei, &z);
+      project_jacobian(cj, X, pi, fj, ej, &z);
+      double ec[6];
 #pragma unroll
-  for (int k = 0; k < 96; ++k) acc[k] = 0.0;
-  const int end = s0_ptr[e + 1];
-  for (int h = s0_ptr[e] + lane; h < end; h += 64) {
-    const double* rec = prec + (size_t)s0_q[h] * PREC;
-    const double X[3] = {rec[0], rec[1], rec[2]};
-    const double C[9] = {rec[3], rec[4], rec[5], rec[4], rec[6], rec[7], rec[5], rec[7], rec[8]};
-    double pi[2], fi[18], ei[6], fj[18], ej[6], z;
-    project_jacobian(ci, X, pi, fi, ei, &z);
-    project_jacobian(cj, X, pi, fj, ej, &z);
-    double ec[6];
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k)
+          ec[r * 3 + k] = ei[r * 3 + 0] * C[0 * 3 + k] + ei[r * 3 + 1] * C[1 * 3 + k] + ei[r * 3 + 2] * C[2 * 3 + k];
+      double m[4];
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
-        ec[r * 3 + k] = ei[r * 3 + 0] * C[0 * 3 + k] + ei[r * 3 + 1] * C[1 * 3 + k] + ei[r * 3 + 2] * C[2 * 3 + k];
-    double m[4];
+      for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int r = 0; r < 2; ++r)
+        for (int t = 0; t < 2; ++t)
+          m[r * 2 + t] = ec[r * 3 + 0] * ej[t * 3 + 0] + ec[r * 3 + 1] * ej[t * 3 + 1] + ec[r * 3 + 2] * ej[t * 3 + 2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) m[r * 2 + t] = ec[r * 3 + 0] * ej[t * 3 + 0] + ec[r * 3 + 1] * ej[t * 3 + 1] + ec[r * 3 + 2] * ej[t * 3 + 2];
-    double mf[18];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      mf[k] = m[0] * fj[k] + m[1] * fj[9 + k];
-      mf[9 + k] = m[2] * fj[k] + m[3] * fj[9 + k];
-    }
-#pragma unroll
-    for (int r = 0; r < 9; ++r)
-#pragma unroll
-      for (int c = 0; c < 9; ++c) acc[r * 9 + c] += fi[r] * mf[c] + fi[9 + r] * mf[9 + c];
-  }
-  wave_reduce_scatter<96>(acc);
-  if (!(lane & 1)) {
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const int idx = 3 * (lane >> 1) + k;
-      if (idx < 81) {
-        const int r = idx / 9, c = idx % 9;
-        S[(size_t)e * 81 + idx] = -acc[k];
-        S[(size_t)trans_pos[e] * 81 + c * 9 + r] = -acc[k];
+      for (int k = 0; k < 9; ++k) {
+        Us[(2 * lane) * 9 + k] = fi[k];
+        Us[(2 * lane + 1) * 9 + k] = fi[9 + k];
+        Vs[(2 * lane) * 9 + k] = m[0] * fj[k] + m[1] * fj[9 + k];
+        Vs[(2 * lane + 1) * 9 + k] = m[2] * fj[k] + m[3] * fj[9 + k];
       }
+    }
+    __syncthreads();
+    // rows 4 s .. 4 s + 3 of the stacked U, V (points 2 s, 2 s + 1)
+    for (int st = 0; st < (nh + 1) / 2; ++st) {
+      const int row = 4 * st + kq;
+      const bool ok = cc < 9 && row < 2 * nh;
+      const double a = ok ? Us[row * 9 + cc] : 0.0;
+      const double b = ok ? Vs[row * 9 + cc] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // accumulator element t of lane l holds (U^T V)[4 t + l / 16][l % 16]
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int r = 4 * t + kq;
+    if (r < 9 && cc < 9) {
+      unsafeAtomicAdd(&S[(size_t)e * 81 + r * 9 + cc], -acc[t]);
+      unsafeAtomicAdd(&S[(size_t)trans_pos[e] * 81 + cc * 9 + r], -acc[t]);
     }
   }
 }
@@ -299,7 +325,6 @@ __global__ void k_dense_scale(int nd, double* __restrict__ A, const double* __re
   A[idx] = A[idx] * s[r] * s[c] + (r == c ? shift : 0.0);
 }
 
-typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Orders the LDS/global accesses of the lanes of one wave (no block barrier).
 __device__ __forceinline__ void wave_sync() {

@@ -57,6 +57,8 @@ struct Level {
   DBuf<double> gj_piv;       // coarsest level: inverse of the current 64 x 64 pivot block
   DBuf<double> vb, vx, vr, vd, vt, vpart;
   DBuf<float> fb, fx, fr, fd, ft, fpart;   // vpart/fpart: restriction partials (n * NS)
+  DBuf<double> vd2, vx2;     // second Chebyshev direction and iterate (fused block-row products)
+  DBuf<float> fd2, fx2;
 };
 
 struct Scratch;   // defined in api.cpp
@@ -88,12 +90,16 @@ struct ba_plan {
   bamg::DBuf<int32_t> tile_pt;    // [n_tiles + 1]
   bamg::DBuf<int32_t> tile_coff;  // [n_tiles + 1] offsets into tile_cams
   bamg::DBuf<int32_t> tile_cams;  // distinct cameras of each tile, ascending
-  bamg::DBuf<uint32_t> obs_slot;  // [n_obs] (point slot << 16) | camera slot
+  bamg::DBuf<int32_t> tile_cseg;  // per tile_cams entry: first rank of that camera's observations
+  bamg::DBuf<uint32_t> obs_slot;  // [n_obs] camera slot | point slot << 16 | rank by camera << 24
   int32_t max_tile_cams = 0;
   // ---- explicit level-0 S: for every upper off-diagonal block (i, j) of the
   // level-0 pattern, the (reordered) points cameras i and j share
   bamg::DBuf<int32_t> s0_ptr;     // [nnz0 + 1]
   bamg::DBuf<int32_t> s0_q;
+  bamg::DBuf<int32_t> s0_chunk_e;    // chunks of <= S0_CHUNK points: block
+  bamg::DBuf<int32_t> s0_chunk_beg;  //   and first index into s0_q
+  int32_t s0_chunks = 0;
   int32_t max_pt_obs = 0;
   // ---- multigrid hierarchy
   std::vector<bamg::Level> levels;

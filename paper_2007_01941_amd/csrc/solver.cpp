@@ -13,8 +13,9 @@ static size_t plan_bytes(const ba_plan* P) {
   size_t b = 0;
   b += P->obs_cam.bytes() + P->obs_pt.bytes() + P->obs_orig.bytes() + P->pt_off.bytes() + P->pt_orig.bytes();
   b += P->pt_new.bytes() + P->cam_off.bytes() + P->cam_obs.bytes() + P->obs_rank.bytes();
-  b += P->tile_obs.bytes() + P->tile_pt.bytes() + P->tile_coff.bytes() + P->tile_cams.bytes() + P->obs_slot.bytes();
-  b += P->s0_ptr.bytes() + P->s0_q.bytes() + P->cam_q.bytes();
+  b += P->tile_obs.bytes() + P->tile_pt.bytes() + P->tile_coff.bytes() + P->tile_cams.bytes() + P->tile_cseg.bytes() + P->obs_slot.bytes();
+  b += P->s0_ptr.bytes() + P->s0_q.bytes() + P->cam_q.bytes() + P->s0_chunk_e.bytes() +
+       P->s0_chunk_beg.bytes();
   b += P->campre.bytes() + P->F.bytes() + P->E.bytes() + P->fres.bytes() + P->F32.bytes() + P->E32.bytes();
   b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
   b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->Scc.bytes() + P->prec.bytes();
@@ -26,7 +27,8 @@ static size_t plan_bytes(const ba_plan* P) {
     b += L.vpart.bytes() + L.fpart.bytes();
     b += L.S.bytes() + L.S32.bytes() + L.K.bytes() + L.P.bytes() + L.P32.bytes() + L.Dinv.bytes() + L.Dinv32.bytes();
     b += L.dense.bytes() + L.inv.bytes();
-    b += L.vb.bytes() + L.vx.bytes() + L.vr.bytes() + L.vd.bytes() + L.vt.bytes();
+    b += L.vb.bytes() + L.vx.bytes() + L.vr.bytes() + L.vd.bytes() + L.vt.bytes() + L.vd2.bytes() + L.vx2.bytes();
+    b += L.fd2.bytes() + L.fx2.bytes();
     b += L.fb.bytes() + L.fx.bytes() + L.fr.bytes() + L.fd.bytes() + L.ft.bytes();
   }
   return b;
@@ -61,7 +63,11 @@ static void allocate_step(ba_plan* P) {
       if (l > 0) L.Dinv.alloc((size_t)L.n * L.bs * L.bs);
     }
     for (DBuf<double>* v : {&L.vb, &L.vx, &L.vr, &L.vd, &L.vt}) v->alloc(nv);
-    if (l + 1 < nl) L.vpart.alloc((size_t)L.n * NS);
+    if (l + 1 < nl) {
+      L.vpart.alloc((size_t)L.n * NS);
+      L.vd2.alloc(nv);
+      L.vx2.alloc(nv);
+    }
     if (l + 1 == nl) {
       L.nd = (int)((nv + GJB - 1) / GJB * GJB);
       L.dense.alloc((size_t)L.nd * L.nd);
@@ -94,7 +100,11 @@ static void ensure_mixed(ba_plan* P) {
       if (l > 0) L.Dinv32.alloc((size_t)L.n * L.bs * L.bs);
     }
     for (DBuf<float>* v : {&L.fb, &L.fx, &L.fr, &L.fd, &L.ft}) v->alloc(nv);
-    if (l + 1 < nl) L.fpart.alloc((size_t)L.n * NS);
+    if (l + 1 < nl) {
+      L.fpart.alloc((size_t)L.n * NS);
+      L.fd2.alloc(nv);
+      L.fx2.alloc(nv);
+    }
   }
 }
 
@@ -143,6 +153,8 @@ template <> struct LvVec<double> {
   static double* d(Level& L) { return L.vd.p; }
   static double* t(Level& L) { return L.vt.p; }
   static double* part(Level& L) { return L.vpart.p; }
+  static double* d2(Level& L) { return L.vd2.p; }
+  static double* x2(Level& L) { return L.vx2.p; }
 };
 template <> struct LvVec<float> {
   static float* b(Level& L) { return L.fb.p; }
@@ -151,6 +163,8 @@ template <> struct LvVec<float> {
   static float* d(Level& L) { return L.fd.p; }
   static float* t(Level& L) { return L.ft.p; }
   static float* part(Level& L) { return L.fpart.p; }
+  static float* d2(Level& L) { return L.fd2.p; }
+  static float* x2(Level& L) { return L.fx2.p; }
 };
 
 template <class T>
@@ -161,11 +175,23 @@ static void op_apply(ba_plan* P, int l, const T* x, T* y, const int* done, hipSt
     return;
   }
   if (L.bs == 9)
-    hipLaunchKernelGGL((k_bsr_spmv<9, T>), dim3(grid_of<T>(L.n, 4)), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p,
-                       lvS<T>(L), x, y, done);
+    hipLaunchKernelGGL((k_bsr_row<9, T, EP_STORE>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p, lvS<T>(L),
+                       x, y, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr, (T*)nullptr,
+                       (const T*)nullptr, (T*)nullptr, T(0), T(0), done);
   else
-    hipLaunchKernelGGL((k_bsr_spmv<16, T>), dim3(grid_of<T>(L.n, 4)), dim3(256), 0, s, L.n, L.rowptr32.p,
-                       L.col.p, lvS<T>(L), x, y, done);
+    hipLaunchKernelGGL((k_bsr_row<16, T, EP_STORE>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p,
+                       lvS<T>(L), x, y, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr,
+                       (T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), done);
+}
+
+// Block-row product with the explicit operator of level l and a fused epilogue
+// (see k_bsr_row): v is the product's input.
+template <int BS, class T, int EP>
+static void row_op(ba_plan* P, int l, const T* v, const T* b, T* r, const T* d_in, T* d_out, const T* x_in,
+                   T* x_out, double c1, double c2, const int* done, hipStream_t s) {
+  Level& L = P->levels[l];
+  hipLaunchKernelGGL((k_bsr_row<BS, T, EP>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p, lvS<T>(L), v,
+                     (T*)nullptr, lvDinv<T>(P, l), b, r, d_in, d_out, x_in, x_out, (T)c1, (T)c2, done);
 }
 
 template <int BS, class T>
@@ -190,9 +216,76 @@ static void vcycle(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const 
   else vcycle_level<16, T>(P, o, l, b, x, done, s);
 }
 
+// One V-cycle level (Algorithm 1) with the explicit level operator: every
+// Chebyshev step after the first is one fused block-row launch (product and
+// update), with the direction d and, in post-smoothing, the iterate
+// ping-ponged between two buffers so that no launch writes its product's input.
+template <int BS, class T>
+static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done,
+                               hipStream_t s) {
+  Level& L = P->levels[l];
+  Level& C = P->levels[l + 1];
+  T* r = LvVec<T>::r(L);
+  T* dA = LvVec<T>::d(L);
+  T* dB = LvVec<T>::d2(L);
+  T* x2 = LvVec<T>::x2(L);
+  const T* Dinv = lvDinv<T>(P, l);
+  const double lmax = L.lmax;
+  const double theta = 0.5 * (o->cheb_hi + o->cheb_lo) * lmax;
+  const double delta = 0.5 * (o->cheb_hi - o->cheb_lo) * lmax;
+  const double sigma1 = theta / delta;
+  const int m = o->cheb_degree;
+  const int nb = std::max(1, ceil_div(L.n, 256 / BS));
+  // pre-smoothing from x = 0: r = b, d = D^-1 b / theta, x = d
+  double rho = 1.0 / sigma1;
+  hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, 0, Dinv, b, (const T*)nullptr, r, dA,
+                     x, (T)(1.0 / theta), done);
+  for (int k = 0; k < m; ++k) {
+    if (k == m - 1) {
+      // last pre-smoothing residual update r -= S d (the V-cycle residual)
+      row_op<BS, T, EP_RESID>(P, l, dA, nullptr, r, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, done, s);
+      break;
+    }
+    const double rn = 1.0 / (2.0 * sigma1 - rho);
+    row_op<BS, T, EP_CHEB>(P, l, dA, nullptr, r, dA, dB, x, x, rn * rho, 2.0 * rn / delta, done, s);
+    std::swap(dA, dB);
+    rho = rn;
+  }
+  // restriction of the residual
+  T* bc = LvVec<T>::b(C);
+  T* xc = LvVec<T>::x(C);
+  T* part = LvVec<T>::part(L);
+  hipLaunchKernelGGL((k_restrict_nodes<BS, T>), dim3(grid_of<T>((int64_t)L.n * NS)), dim3(256), 0, s, L.n,
+                     L.slot_of.p, lvP<T>(L), (const T*)r, (const T*)nullptr, part, done);
+  hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n, L.agg_ptr.p,
+                     (const T*)part, bc, done);
+  vcycle<T>(P, o, l + 1, bc, xc, done, s);
+  hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
+                     lvP<T>(L), (const T*)xc, x, done);
+  // post-smoothing from x: r = b - S x, d = D^-1 r / theta, iterate -> x2
+  rho = 1.0 / sigma1;
+  row_op<BS, T, EP_CHEB_POST>(P, l, x, b, r, nullptr, dA, x, x2, 0.0, 1.0 / theta, done, s);
+  if (m == 1) {
+    hipLaunchKernelGGL((k_convert<T, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n * BS,
+                       (const T*)x2, x);
+    return;
+  }
+  for (int k = 0; k < m - 1; ++k) {
+    const double rn = 1.0 / (2.0 * sigma1 - rho);
+    T* xo = k == m - 2 ? x : x2;
+    row_op<BS, T, EP_CHEB>(P, l, dA, nullptr, r, dA, dB, x2, xo, rn * rho, 2.0 * rn / delta, done, s);
+    std::swap(dA, dB);
+    rho = rn;
+  }
+}
+
 template <int BS, class T>
 static void vcycle_level(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done, hipStream_t s) {
   Level& L = P->levels[l];
+  if (l > 0 || L.explicit_op) {
+    vcycle_level_fused<BS, T>(P, o, l, b, x, done, s);
+    return;
+  }
   Level& C = P->levels[l + 1];
   T* r = LvVec<T>::r(L);
   T* d = LvVec<T>::d(L);
@@ -369,8 +462,12 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   Level& L0 = P->levels[0];
   // explicit level-0 S (Section 3.6): needed for the Galerkin product and, when
   // cheaper than the implicit form, for smoothing
-  hipLaunchKernelGGL(k_explicit_s0, dim3((unsigned)L0.nnz), dim3(64), 0, s, L0.row_of.p, L0.col.p, L0.trans_pos.p,
-                     P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p, P->Scc.p, L0.S.p);
+  hipLaunchKernelGGL(k_s0_init, dim3(grid_of<double>(L0.nnz * 81)), dim3(256), 0, s, (int64_t)L0.nnz * 81,
+                     L0.row_of.p, L0.col.p, P->Scc.p, L0.S.p);
+  if (P->s0_chunks > 0)
+    hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, P->s0_chunk_e.p, P->s0_chunk_beg.p,
+                       L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
+                       L0.S.p);
   L0.explicit_op = level0_explicit(P, o, mixed ? 4 : 8);
   hipLaunchKernelGGL(k_nullspace0, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
                      L0.K.p);
@@ -442,17 +539,17 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   Timer tj(s);
   hipLaunchKernelGGL(k_campre, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
                      P->errflag.p);
-  hipLaunchKernelGGL(k_jacobian_tiles, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
+  hipLaunchKernelGGL(k_jacobian_tiles, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
                      P->obs_slot.p, P->obs_cam.p, P->obs_orig.p, P->pt_orig.p, P->campre.p, pts, uv, P->n_obs_pad,
                      o->lambda, D, P->n_cam, P->F.p, P->E.p, P->fres.p, mixed ? P->F32.p : nullptr,
                      mixed ? P->E32.p : nullptr, P->Cinv.p, mixed ? P->Cinv32.p : nullptr, P->vgp.p, P->gp.p,
-                     P->Dp.p, P->prec.p, P->errflag.p);
+                     P->Dp.p, P->prec.p, P->n_tiles, P->errflag.p);
   BA_LAUNCH_CHECK();
   check_errflag(P, s);
-  hipLaunchKernelGGL(k_camera_blocks, dim3(P->n_cam), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->cam_q.p,
+  hipLaunchKernelGGL(k_camera_blocks, dim3(xcd_grid(P->n_cam)), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->cam_q.p,
                      P->n_obs_pad, P->campre.p, P->prec.p, P->fres.p, o->lambda, D, P->A.p,
                      mixed ? P->A32.p : nullptr, P->Dc.p, P->b.p, P->Scc.p, P->Sinv.p,
-                     mixed ? P->Sinv32.p : nullptr, P->errflag.p);
+                     mixed ? P->Sinv32.p : nullptr, P->n_cam, P->errflag.p);
   BA_LAUNCH_CHECK();
   check_errflag(P, s, "normal blocks");
   const double tjac = tj.ms();
@@ -498,14 +595,7 @@ static PcgOut pcg_run(ba_plan* P, const ba_opts* o, const T* b, PcgVecs<T> v, do
   for (int it = 0; it < max_iter; ++it) {
     hipLaunchKernelGGL((k_pcg_p_Ap<T>), dim3(grid_of<T>(9 * P->n_cam, 252 / 9 * 9)), dim3(256), 0, s, P->n_cam,
                        (const T*)v.z, v.p, A_of<T>(P), v.q, (const PcgScal*)sc);
-    if (sizeof(T) == 8)
-      hipLaunchKernelGGL(k_schur_tiles<double>, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
-                         P->tile_coff.p, P->tile_cams.p, P->obs_slot.p, P->F.p, P->E.p, P->n_obs_pad, P->Cinv.p,
-                         (const double*)v.p, (double*)v.q, done);
-    else
-      hipLaunchKernelGGL(k_schur_tiles<float>, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
-                         P->tile_coff.p, P->tile_cams.p, P->obs_slot.p, P->F32.p, P->E32.p, P->n_obs_pad,
-                         P->Cinv32.p, (const float*)v.p, (float*)v.q, done);
+    schur_tiles_dev<T>(P, v.p, v.q, done, s);
     hipLaunchKernelGGL((k_dot<DOT_ALPHA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, W.partial.p,
                        sc, (double*)nullptr);
     hipLaunchKernelGGL((k_pcg_xr<T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, v.x, v.r,
@@ -583,9 +673,9 @@ static ba_status solve(ba_plan* P, const ba_opts* o, double* delta_cam, double* 
   const ba_status status = solve_camera_system(P, o, P->b.p, st, s);
   BA_HIP(hipMemcpyAsync(delta_cam, W.x.p, (size_t)W.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // back-substitution delta_p = C^-1 (-g_p - W^T delta_c)
-  hipLaunchKernelGGL(k_recover_tiles, dim3(P->n_tiles), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
+  hipLaunchKernelGGL(k_recover_tiles, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
                      P->pt_orig.p, P->obs_cam.p, P->n_obs_pad, P->F.p, P->E.p, P->Cinv.p, P->gp.p, -1.0, W.x.p,
-                     delta_pt);
+                     delta_pt, P->n_tiles);
   BA_LAUNCH_CHECK();
   const double t = ts.ms();
   if (st) st->t_solve_ms = t;

@@ -191,11 +191,12 @@ __global__ __launch_bounds__(256) void k_jacobian_tiles(
     int64_t stride, double lambda, const double* __restrict__ Dexp, int n_cam, double* __restrict__ F,
     double* __restrict__ E, double* __restrict__ fres, float* __restrict__ F32, float* __restrict__ E32,
     double* __restrict__ Cinv, float* __restrict__ Cinv32, double* __restrict__ vgp,
-    double* __restrict__ gp_out, double* __restrict__ Dp_out, double* __restrict__ prec, uint32_t* err) {
+    double* __restrict__ gp_out, double* __restrict__ Dp_out, double* __restrict__ prec, int n_tiles, uint32_t* err) {
   // per-observation contributions [E^T E (6) | E^T f (3)], summed per point in
   // observation order afterwards (deterministic, no atomics)
   __shared__ double part[9][TILE_OBS];
-  const int t = blockIdx.x;
+  const int t = xcd_block(blockIdx.x, n_tiles);
+  if (t >= n_tiles) return;
   const int o0 = tile_obs[t], o1 = tile_obs[t + 1];
   const int q0 = tile_pt[t], np = tile_pt[t + 1] - q0;
   double sum[9];
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(256) void k_jacobian_tiles(
   // more than TILE_OBS observations only for a tile holding one point
   for (int o = o0 + threadIdx.x; o < o1; o += TILE_OBS) {
     const int c = obs_cam[o];
-    const int pl = (int)(obs_slot[o] >> 16);
+    const int pl = (int)((obs_slot[o] >> 16) & 0xffu);
     const int qo = pt_orig[q0 + pl];
     const int oo = obs_orig[o];
     const double X[3] = {pts[(size_t)qo * 3 + 0], pts[(size_t)qo * 3 + 1], pts[(size_t)qo * 3 + 2]};
@@ -298,11 +299,12 @@ __global__ __launch_bounds__(256) void k_camera_blocks(
     const double* __restrict__ prec, const double* __restrict__ fres, double lambda,
     const double* __restrict__ Dexp, double* __restrict__ A_out, float* __restrict__ A32,
     double* __restrict__ Dc_out, double* __restrict__ b_out, double* __restrict__ Scc_out,
-    double* __restrict__ Sinv, float* __restrict__ Sinv32, uint32_t* err) {
+    double* __restrict__ Sinv, float* __restrict__ Sinv32, int n_cam, uint32_t* err) {
   __shared__ double red[4 * 64];
   __shared__ double S[81];
   __shared__ double Adiag[9], Ad[45];
-  const int c = blockIdx.x;
+  const int c = xcd_block(blockIdx.x, n_cam);
+  if (c >= n_cam) return;
   const int beg = cam_off[c], end = cam_off[c + 1];
   const double* cp = campre + (size_t)c * 24;
   double acc[64];
@@ -447,9 +449,10 @@ __global__ __launch_bounds__(256) void k_recover_tiles(
     const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_orig,
     const int32_t* __restrict__ obs_cam, int64_t stride, const double* __restrict__ F,
     const double* __restrict__ E, const double* __restrict__ Cinv, const double* __restrict__ rp,
-    double rscale, const double* __restrict__ xc, double* __restrict__ out) {
+    double rscale, const double* __restrict__ xc, double* __restrict__ out, int n_tiles) {
   __shared__ double part[3][TILE_OBS];
-  const int t = blockIdx.x;
+  const int t = xcd_block(blockIdx.x, n_tiles);
+  if (t >= n_tiles) return;
   const int o0 = tile_obs[t], o1 = tile_obs[t + 1];
   const int q0 = tile_pt[t], np = tile_pt[t + 1] - q0;
   double z0 = 0, z1 = 0, z2 = 0;

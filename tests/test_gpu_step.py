@@ -60,10 +60,14 @@ SCENES = ["ring64", "city200"]
 def _sc(name):
     if name.startswith("tiny"):
         return tiny_scene(9, 120, seed=7, k_min=2, k_max=6)
+    if name == "wide":
+        # points seen by up to 300 cameras: tiles holding one point with more
+        # than 256 observations, and tiles with more cameras than LDS slots
+        return tiny_scene(300, 60, seed=5, k_min=2)
     return scene(name)
 
 
-@pytest.mark.parametrize("name", SCENES + ["tiny"])
+@pytest.mark.parametrize("name", SCENES + ["tiny", "wide"])
 def test_residual_and_jacobian(name):
     sc = _sc(name)
     plan, _ = plan_for(sc)
@@ -77,7 +81,7 @@ def test_residual_and_jacobian(name):
         assert (np.abs(got - ref) / scale).max() <= 1e-11
 
 
-@pytest.mark.parametrize("name", SCENES + ["tiny"])
+@pytest.mark.parametrize("name", SCENES + ["tiny", "wide"])
 def test_normal_blocks(name):
     sc = _sc(name)
     plan, opts = plan_for(sc, precond="bj")
@@ -96,7 +100,7 @@ def test_normal_blocks(name):
     assert np.all(np.abs(Scc - B) <= TOL_U * Babs)
 
 
-@pytest.mark.parametrize("name", SCENES + ["tiny"])
+@pytest.mark.parametrize("name", SCENES + ["tiny", "wide"])
 def test_implicit_schur_product(name):
     sc = _sc(name)
     plan, _ = plan_for(sc, precond="bj", precision="mixed")
