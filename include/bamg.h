@@ -12,7 +12,8 @@
  *   - `stream` is a hipStream_t passed as void*; all device work is enqueued on
  *     it. Calls that return step results block until those results are ready
  *     (the solver reads its convergence test back to the host); the two
- *     operator applications (ba_schur_apply, ba_precond_apply) do not block.
+ *     operator applications (ba_schur_apply, ba_schur_offdiag_apply,
+ *     ba_precond_apply) do not block.
  *   - A negative status means nothing was written to the outputs; a message is
  *     available from ba_last_error() on the calling thread. BA_NOT_CONVERGED
  *     means the outputs hold the last iterate and the statistics are valid.
@@ -169,6 +170,14 @@ ba_status ba_step_solve(ba_plan* p, const ba_opts* o, double* delta_cam, double*
  * x, y: [n_cam][9]. Enqueued on `stream`; returns without waiting. */
 ba_status ba_schur_apply(ba_plan* p, int32_t precision, const double* x, double* y,
                          void* stream);
+
+/* y <- y - W C^-1 W^T x with W = F^T E: the point-elimination term of the
+ * Schur complement S = A - W C^-1 W^T (Section 2.1) alone, as one kernel
+ * launch (the implicit product of Section 3.6 without its A x part).
+ * x [n_cam][9] is read, y [n_cam][9] is read and updated. precision as for
+ * ba_schur_apply. Enqueued on `stream`; returns without waiting. */
+ba_status ba_schur_offdiag_apply(ba_plan* p, int32_t precision, const double* x, double* y,
+                                 void* stream);
 
 /* z = M r: one preconditioner application of the prepared step (block Jacobi,
  * or one V-cycle of Algorithm 1 from a zero initial guess). [n_cam][9].

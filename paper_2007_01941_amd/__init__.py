@@ -156,6 +156,14 @@ class Plan:
                                            _ptr(x), _ptr(y), _stream()))
         return y
 
+    def schur_offdiag_apply(self, x, y, precision="fp64"):
+        """y -= W C^-1 W^T x in place (the point-elimination term of S)."""
+        x = x.contiguous()
+        assert y.is_contiguous() and y.dtype == torch.float64 and y.shape == x.shape
+        _lib.check(_lib.LIB.ba_schur_offdiag_apply(self._h, _lib.FP64 if precision == "fp64" else _lib.MIXED,
+                                                   _ptr(x), _ptr(y), _stream()))
+        return y
+
     def precond_apply(self, r, opts=None, precision="fp64"):
         r = r.contiguous()
         z = torch.empty_like(r)

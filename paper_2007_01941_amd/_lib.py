@@ -109,6 +109,7 @@ def _load():
         "ba_step_prepare": [P, P, P, P, P, P, P, P],
         "ba_step_solve": [P, P, P, P, P, P],
         "ba_schur_apply": [P, I32, P, P, P],
+        "ba_schur_offdiag_apply": [P, I32, P, P, P],
         "ba_precond_apply": [P, P, I32, P, P, P],
         "ba_step_blocks": [P, P, P, P, P],
         "ba_mg_levels": [P, P, P],
@@ -135,7 +136,7 @@ LIB = _load()
 # The C ABI's exported symbols, as declared in include/bamg.h.
 EXPORTED = ["ba_opts_default", "ba_plan_create", "ba_plan_destroy", "ba_plan_bytes", "ba_lm_step",
             "ba_lm_step_backward", "ba_eval_jacobian", "ba_step_prepare", "ba_step_solve",
-            "ba_schur_apply", "ba_precond_apply", "ba_step_blocks", "ba_mg_levels",
+            "ba_schur_apply", "ba_schur_offdiag_apply", "ba_precond_apply", "ba_step_blocks", "ba_mg_levels",
             "ba_mg_aggregates", "ba_mg_covisibility", "ba_mg_level_data", "ba_selftest_tile_mma",
             "ba_status_str", "ba_last_error"]
 

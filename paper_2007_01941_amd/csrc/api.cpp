@@ -286,6 +286,27 @@ ba_status ba_schur_apply(ba_plan* P, int32_t precision, const double* x, double*
   BA_API_END
 }
 
+ba_status ba_schur_offdiag_apply(ba_plan* P, int32_t precision, const double* x, double* y, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && x && y, BA_ERR_ARG, "null argument");
+  BA_CHECK(P->prepared, BA_ERR_ARG, "ba_step_prepare has not been called");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = 9 * P->n_cam;
+  if (precision == BA_MIXED) {
+    BA_CHECK(P->have_mixed, BA_ERR_ARG, "step was prepared without BA_MIXED");
+    Scratch& W = *P->scratch;
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, n, x, W.fx.p);
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(ceil_div(n, 256)), dim3(256), 0, s, n, (const double*)y,
+                       W.fq.p);
+    schur_tiles_dev<float>(P, W.fx.p, W.fq.p, nullptr, s);
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(ceil_div(n, 256)), dim3(256), 0, s, n, W.fq.p, y);
+  } else {
+    schur_tiles_dev<double>(P, x, y, nullptr, s);
+  }
+  BA_LAUNCH_CHECK();
+  BA_API_END
+}
+
 ba_status ba_precond_apply(ba_plan* P, const ba_opts* o, int32_t precision, const double* r,
                            double* z, void* stream) {
   BA_API_BEGIN

@@ -10,7 +10,7 @@ namespace bamg {
 // Epilogues of the block-row product t = (S v)_i (one node i per workgroup):
 enum RowEpilogue {
   EP_STORE = 0,     // out_i = t
-  EP_RESID = 1,     // r_i -= t
+  EP_RESID = 1,     // r_i -= t;  part_{slot(i)} = P_i^T r_i (restriction partial)
   EP_CHEB = 2,      // v = d_in:  r_i -= t;  d_out_i = c1 d_in_i + c2 D_i^-1 r_i;  x_out_i = x_in_i + d_out_i
   EP_CHEB_POST = 3  // v = x_in:  r_i = b_i - t;  d_out_i = c2 D_i^-1 r_i;  x_out_i = x_in_i + d_out_i
 };
@@ -30,17 +30,20 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
                                                  const T* __restrict__ Dinv, const T* __restrict__ b,
                                                  T* __restrict__ r, const T* __restrict__ d_in,
                                                  T* __restrict__ d_out, const T* __restrict__ x_in,
-                                                 T* __restrict__ x_out, T c1, T c2, const int* done) {
+                                                 T* __restrict__ x_out, T c1, T c2,
+                                                 const T* __restrict__ P, const int32_t* __restrict__ slot_of,
+                                                 T* __restrict__ rpart, const int* done) {
   if (done && *done) return;
   constexpr int PARTS = 256 / BS;
   __shared__ T red[256];
   __shared__ T rs[BS];
   const int row = blockIdx.x;
-  const int part = threadIdx.x / BS, comp = threadIdx.x % BS;
+  const int pidx = threadIdx.x / BS, comp = threadIdx.x % BS;
   T acc = 0;
-  if (part < PARTS) {
+  if (pidx < PARTS) {
     const int e1 = rowptr[row + 1];
-    for (int e = rowptr[row] + part; e < e1; e += PARTS) {
+#pragma unroll 2
+    for (int e = rowptr[row] + pidx; e < e1; e += PARTS) {
       const T* blk = S + (size_t)e * BS * BS + comp * BS;
       const T* xv = v + (size_t)col[e] * BS;
 #pragma unroll
@@ -64,8 +67,18 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
       rs[comp] = rv;
     }
   }
-  if (EP == EP_STORE || EP == EP_RESID) return;
+  if (EP == EP_STORE) return;
   __syncthreads();
+  if (EP == EP_RESID) {
+    if (threadIdx.x < NS) {
+      const T* Pi = P + (size_t)row * BS * NS + threadIdx.x;
+      T sacc = 0;
+#pragma unroll
+      for (int k2 = 0; k2 < BS; ++k2) sacc += Pi[k2 * NS] * rs[k2];
+      rpart[(size_t)slot_of[row] * NS + threadIdx.x] = sacc;
+    }
+    return;
+  }
   if (!own) return;
   const T* m = Dinv + (size_t)row * BS * BS + comp * BS;
   T z = 0;
@@ -96,22 +109,31 @@ __global__ __launch_bounds__(256) void k_blockdiag(int n, const T* __restrict__ 
 // First Chebyshev step. mode 0 (pre-smoothing from x = 0, r = b):
 //   d = D^-1 b / theta; x = d; r = b.
 // mode 1 (post-smoothing from x, t = S x): r = b - t; d = D^-1 r / theta; x += d.
+// mode 2: as mode 0, with b first formed (and stored) from the finer level's
+//   restriction partials: b_i = sum_{q in [agg_ptr[i], agg_ptr[i+1])} part_q.
 template <int BS, class T>
 __global__ __launch_bounds__(256) void k_cheb_first(int n, int mode, const T* __restrict__ Dinv,
-                                                    const T* __restrict__ b, const T* __restrict__ t,
+                                                    T* __restrict__ b, const T* __restrict__ t,
                                                     T* __restrict__ r, T* __restrict__ d,
-                                                    T* __restrict__ x, T inv_theta, const int* done) {
+                                                    T* __restrict__ x, T inv_theta,
+                                                    const int32_t* __restrict__ agg_ptr,
+                                                    const T* __restrict__ part, const int* done) {
   if (done && *done) return;
   __shared__ T rs[256];
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int nodes_per_block = 256 / BS;
   const int ln = threadIdx.x / BS, a = threadIdx.x % BS;
   const int i = blockIdx.x * nodes_per_block + ln;
   const bool act = ln < nodes_per_block && i < n;
-  (void)g;
   if (act) {
     const size_t k = (size_t)i * BS + a;
-    const T rv = mode == 0 ? b[k] : b[k] - t[k];
+    T rv;
+    if (mode == 2) {
+      rv = 0;
+      for (int q = agg_ptr[i]; q < agg_ptr[i + 1]; ++q) rv += part[(size_t)q * BS + a];
+      b[k] = rv;
+    } else {
+      rv = mode == 0 ? b[k] : b[k] - t[k];
+    }
     rs[ln * BS + a] = rv;
     r[k] = rv;
   }
@@ -124,7 +146,7 @@ __global__ __launch_bounds__(256) void k_cheb_first(int n, int mode, const T* __
   const size_t k = (size_t)i * BS + a;
   const T dv = s * inv_theta;
   d[k] = dv;
-  x[k] = mode == 0 ? dv : x[k] + dv;
+  x[k] = mode == 1 ? x[k] + dv : dv;
 }
 
 // Later Chebyshev steps: r -= t (t = S d); d = c1 d + c2 D^-1 r; x += d.
@@ -225,9 +247,15 @@ __global__ __launch_bounds__(256) void k_dense_solve(int nv, int nd, const doubl
   const int lane = threadIdx.x & 63;
   if (row >= nv) return;
   const double* m = inv + (size_t)row * nd;
-  double s = 0.0;
-  for (int k = lane; k < nv; k += 64) s += m[k] * (double)b[k];
-  s = wave_sum(s);
+  double s0 = 0.0, s1 = 0.0;
+  // nd is even and rows are 16-byte aligned: lane k reads entries 2k, 2k + 1 of each 128-wide chunk
+#pragma unroll 4
+  for (int k = 2 * lane; k < nv; k += 128) {
+    const double2 mv = *reinterpret_cast<const double2*>(m + k);
+    s0 += mv.x * (double)b[k];
+    if (k + 1 < nv) s1 += mv.y * (double)b[k + 1];
+  }
+  double s = wave_sum(s0 + s1);
   if (lane == 0) x[row] = (T)s;
 }
 

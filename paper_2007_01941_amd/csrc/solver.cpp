@@ -177,21 +177,25 @@ static void op_apply(ba_plan* P, int l, const T* x, T* y, const int* done, hipSt
   if (L.bs == 9)
     hipLaunchKernelGGL((k_bsr_row<9, T, EP_STORE>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p, lvS<T>(L),
                        x, y, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr, (T*)nullptr,
-                       (const T*)nullptr, (T*)nullptr, T(0), T(0), done);
+                       (const T*)nullptr, (T*)nullptr, T(0), T(0), (const T*)nullptr, (const int32_t*)nullptr,
+                       (T*)nullptr, done);
   else
     hipLaunchKernelGGL((k_bsr_row<16, T, EP_STORE>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p,
                        lvS<T>(L), x, y, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr,
-                       (T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), done);
+                       (T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), (const T*)nullptr,
+                       (const int32_t*)nullptr, (T*)nullptr, done);
 }
 
 // Block-row product with the explicit operator of level l and a fused epilogue
 // (see k_bsr_row): v is the product's input.
 template <int BS, class T, int EP>
 static void row_op(ba_plan* P, int l, const T* v, const T* b, T* r, const T* d_in, T* d_out, const T* x_in,
-                   T* x_out, double c1, double c2, const int* done, hipStream_t s) {
+                   T* x_out, double c1, double c2, T* part, const int* done, hipStream_t s) {
   Level& L = P->levels[l];
   hipLaunchKernelGGL((k_bsr_row<BS, T, EP>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p, lvS<T>(L), v,
-                     (T*)nullptr, lvDinv<T>(P, l), b, r, d_in, d_out, x_in, x_out, (T)c1, (T)c2, done);
+                     (T*)nullptr, lvDinv<T>(P, l), b, r, d_in, d_out, x_in, x_out, (T)c1, (T)c2,
+                     part ? lvP<T>(L) : (const T*)nullptr, part ? L.slot_of.p : (const int32_t*)nullptr, part,
+                     done);
 }
 
 template <int BS, class T>
@@ -201,19 +205,36 @@ static void blockdiag_apply(ba_plan* P, int l, const T* r, T* z, const int* done
                      lvDinv<T>(P, l), r, z, done);
 }
 
-template <int BS, class T>
-static void vcycle_level(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done, hipStream_t s);
-
+// The restriction of the finer level's residual, when it is still in the
+// form of per-node partials (fused into the finer level's residual update):
+// b_i = sum of part over [agg_ptr[i], agg_ptr[i+1]).
 template <class T>
-static void vcycle(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done, hipStream_t s) {
+struct Pending {
+  const int32_t* agg_ptr = nullptr;
+  const T* part = nullptr;
+};
+
+template <int BS, class T>
+static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> pend, const int* done,
+                         hipStream_t s);
+
+// x = M_l b: the V-cycle from level l (Algorithm 1), x overwritten. With
+// pend.part set, b is first formed from the finer level's partials.
+template <class T>
+static void vcycle(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> pend, const int* done,
+                   hipStream_t s) {
   Level& L = P->levels[l];
   if (l + 1 == (int)P->levels.size()) {
+    if (pend.part)
+      hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)L.n * NS)), dim3(256), 0, s, L.n,
+                         pend.agg_ptr, pend.part, b, done);
     const int nv = L.n * L.bs;
-    hipLaunchKernelGGL((k_dense_solve<T>), dim3(grid_of<T>(nv, 4)), dim3(256), 0, s, nv, L.nd, L.inv.p, b, x, done);
+    hipLaunchKernelGGL((k_dense_solve<T>), dim3(grid_of<T>(nv, 4)), dim3(256), 0, s, nv, L.nd, L.inv.p,
+                       (const T*)b, x, done);
     return;
   }
-  if (L.bs == 9) vcycle_level<9, T>(P, o, l, b, x, done, s);
-  else vcycle_level<16, T>(P, o, l, b, x, done, s);
+  if (L.bs == 9) vcycle_level<9, T>(P, o, l, b, x, pend, done, s);
+  else vcycle_level<16, T>(P, o, l, b, x, pend, done, s);
 }
 
 // One V-cycle level (Algorithm 1) with the explicit level operator: every
@@ -221,7 +242,7 @@ static void vcycle(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const 
 // update), with the direction d and, in post-smoothing, the iterate
 // ping-ponged between two buffers so that no launch writes its product's input.
 template <int BS, class T>
-static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done,
+static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> pend, const int* done,
                                hipStream_t s) {
   Level& L = P->levels[l];
   Level& C = P->levels[l + 1];
@@ -238,33 +259,33 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, const T* b, 
   const int nb = std::max(1, ceil_div(L.n, 256 / BS));
   // pre-smoothing from x = 0: r = b, d = D^-1 b / theta, x = d
   double rho = 1.0 / sigma1;
-  hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, 0, Dinv, b, (const T*)nullptr, r, dA,
-                     x, (T)(1.0 / theta), done);
+  hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, pend.part ? 2 : 0, Dinv, b,
+                     (const T*)nullptr, r, dA, x, (T)(1.0 / theta), pend.agg_ptr, pend.part, done);
+  T* part = LvVec<T>::part(L);
   for (int k = 0; k < m; ++k) {
     if (k == m - 1) {
-      // last pre-smoothing residual update r -= S d (the V-cycle residual)
-      row_op<BS, T, EP_RESID>(P, l, dA, nullptr, r, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, done, s);
+      // last pre-smoothing residual update r -= S d (the V-cycle residual),
+      // with each node's restriction partial P_i^T r_i
+      row_op<BS, T, EP_RESID>(P, l, dA, nullptr, r, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, part, done, s);
       break;
     }
     const double rn = 1.0 / (2.0 * sigma1 - rho);
-    row_op<BS, T, EP_CHEB>(P, l, dA, nullptr, r, dA, dB, x, x, rn * rho, 2.0 * rn / delta, done, s);
+    row_op<BS, T, EP_CHEB>(P, l, dA, nullptr, r, dA, dB, x, x, rn * rho, 2.0 * rn / delta, nullptr, done, s);
     std::swap(dA, dB);
     rho = rn;
   }
-  // restriction of the residual
+  // the coarse right-hand side is summed from the partials by the next level
   T* bc = LvVec<T>::b(C);
   T* xc = LvVec<T>::x(C);
-  T* part = LvVec<T>::part(L);
-  hipLaunchKernelGGL((k_restrict_nodes<BS, T>), dim3(grid_of<T>((int64_t)L.n * NS)), dim3(256), 0, s, L.n,
-                     L.slot_of.p, lvP<T>(L), (const T*)r, (const T*)nullptr, part, done);
-  hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n, L.agg_ptr.p,
-                     (const T*)part, bc, done);
-  vcycle<T>(P, o, l + 1, bc, xc, done, s);
+  Pending<T> next;
+  next.agg_ptr = L.agg_ptr.p;
+  next.part = part;
+  vcycle<T>(P, o, l + 1, bc, xc, next, done, s);
   hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
                      lvP<T>(L), (const T*)xc, x, done);
   // post-smoothing from x: r = b - S x, d = D^-1 r / theta, iterate -> x2
   rho = 1.0 / sigma1;
-  row_op<BS, T, EP_CHEB_POST>(P, l, x, b, r, nullptr, dA, x, x2, 0.0, 1.0 / theta, done, s);
+  row_op<BS, T, EP_CHEB_POST>(P, l, x, b, r, nullptr, dA, x, x2, 0.0, 1.0 / theta, nullptr, done, s);
   if (m == 1) {
     hipLaunchKernelGGL((k_convert<T, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n * BS,
                        (const T*)x2, x);
@@ -273,17 +294,18 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, const T* b, 
   for (int k = 0; k < m - 1; ++k) {
     const double rn = 1.0 / (2.0 * sigma1 - rho);
     T* xo = k == m - 2 ? x : x2;
-    row_op<BS, T, EP_CHEB>(P, l, dA, nullptr, r, dA, dB, x2, xo, rn * rho, 2.0 * rn / delta, done, s);
+    row_op<BS, T, EP_CHEB>(P, l, dA, nullptr, r, dA, dB, x2, xo, rn * rho, 2.0 * rn / delta, nullptr, done, s);
     std::swap(dA, dB);
     rho = rn;
   }
 }
 
 template <int BS, class T>
-static void vcycle_level(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, const int* done, hipStream_t s) {
+static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> pend, const int* done,
+                         hipStream_t s) {
   Level& L = P->levels[l];
   if (l > 0 || L.explicit_op) {
-    vcycle_level_fused<BS, T>(P, o, l, b, x, done, s);
+    vcycle_level_fused<BS, T>(P, o, l, b, x, pend, done, s);
     return;
   }
   Level& C = P->levels[l + 1];
@@ -300,7 +322,7 @@ static void vcycle_level(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, 
   // pre-smoothing from x = 0
   double rho = 1.0 / sigma1;
   hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, 0, Dinv, b, (const T*)nullptr, r, d, x,
-                     (T)(1.0 / theta), done);
+                     (T)(1.0 / theta), (const int32_t*)nullptr, (const T*)nullptr, done);
   for (int k = 0; k < m; ++k) {
     op_apply<T>(P, l, d, t, done, s);
     if (k == m - 1) break;
@@ -317,14 +339,14 @@ static void vcycle_level(ba_plan* P, const ba_opts* o, int l, const T* b, T* x, 
                      L.slot_of.p, lvP<T>(L), (const T*)r, (const T*)t, part, done);
   hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n, L.agg_ptr.p,
                      (const T*)part, bc, done);
-  vcycle<T>(P, o, l + 1, bc, xc, done, s);
+  vcycle<T>(P, o, l + 1, bc, xc, Pending<T>(), done, s);
   hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
                      lvP<T>(L), (const T*)xc, x, done);
   // post-smoothing from x
   op_apply<T>(P, l, x, t, done, s);
   rho = 1.0 / sigma1;
   hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, 1, Dinv, b, (const T*)t, r, d, x,
-                     (T)(1.0 / theta), done);
+                     (T)(1.0 / theta), (const int32_t*)nullptr, (const T*)nullptr, done);
   for (int k = 0; k < m - 1; ++k) {
     op_apply<T>(P, l, d, t, done, s);
     const double rn = 1.0 / (2.0 * sigma1 - rho);
@@ -348,7 +370,8 @@ static void precond_apply(ba_plan* P, const ba_opts* o, const T* r, T* z, const 
                        Sinv_of<T>(P), r, z, done);
   } else {
     BA_CHECK(P->prepared_mg, BA_ERR_ARG, "the step was prepared without the multigrid preconditioner");
-    vcycle<T>(P, o, 0, r, z, done, s);
+    // level 0 has no pending restriction, so r is only read
+    vcycle<T>(P, o, 0, const_cast<T*>(r), z, Pending<T>(), done, s);
   }
 }
 

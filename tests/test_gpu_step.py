@@ -119,6 +119,12 @@ def test_implicit_schur_product(name):
         # FP32 operands and accumulation: the same bound with u = 2^-24
         assert np.all(np.abs(y64 - ref) <= TOL_U * bound)
         assert np.all(np.abs(y32 - ref) <= 1e-4 * bound)
+        # the point-elimination term alone: y0 - W C^-1 W^T x = y0 - (A x - S x)
+        y0 = rng.normal(size=(sc.n_cam, 9))
+        Ax = np.einsum("cij,cj->ci", nrm.A, x)
+        ref_off = y0 - (Ax - ref)
+        got = host(plan.schur_offdiag_apply(xt, torch.as_tensor(y0, device="cuda")))
+        assert np.all(np.abs(got - ref_off) <= TOL_U * (bound + np.abs(y0) + np.abs(Ax)))
 
 
 @pytest.mark.parametrize("name", SCENES)
