@@ -10,7 +10,9 @@
  *     caller memory. A plan owns the device memory it allocates for itself
  *     (layout, per-step buffers, hierarchy) until ba_plan_destroy.
  *   - `stream` is a hipStream_t passed as void*; all device work is enqueued on
- *     it. Calls that return step results block until those results are ready
+ *     it (the multigrid setup also uses a side stream of the plan, forked from
+ *     and joined back into `stream` with events, so ordering on `stream` is
+ *     kept). Calls that return step results block until those results are ready
  *     (the solver reads its convergence test back to the host); the two
  *     operator applications (ba_schur_apply, ba_schur_offdiag_apply,
  *     ba_precond_apply) do not block.

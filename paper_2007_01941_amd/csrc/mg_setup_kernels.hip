@@ -261,25 +261,49 @@ __global__ __launch_bounds__(256) void k_galerkin(int bs, const int32_t* __restr
 
 // ---------------------------------------------------------------- block inverses
 
-// Inverse of the diagonal 16 x 16 block of every node (one wave per node).
+// Inverse of the diagonal 16 x 16 (SPD) block of every node, one wave per
+// node, by Gauss-Jordan without pivoting: lane l keeps column l % 16 of rows
+// l / 16 + 4 m (m < 4); the pivot row and column of every step are exchanged
+// through double-buffered LDS.
 __global__ __launch_bounds__(64) void k_diag_inverse16(const int32_t* __restrict__ diag_pos,
                                                        const double* __restrict__ S,
                                                        double* __restrict__ Dinv, uint32_t* err) {
-  __shared__ double a[NS * NS], inv[NS * NS];
+  __shared__ double rowb[2][NS], colb[2][NS];
   const int i = blockIdx.x;
+  const int l = threadIdx.x, c = l % NS, r0 = l / NS;
   const double* blk = S + (size_t)diag_pos[i] * NS * NS;
-  for (int k = threadIdx.x; k < NS * NS; k += 64) a[k] = blk[k];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (!cholesky<NS>(a)) {
-      atomicOr(err, ERRF_NOT_SPD);
-      for (int k = 0; k < NS * NS; ++k) inv[k] = 0.0;
-    } else {
-      cholesky_inverse<NS>(a, inv);
+  double v[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) v[m] = blk[(r0 + 4 * m) * NS + c];
+  bool ok = true;
+#pragma unroll
+  for (int p = 0; p < NS; ++p) {
+    const int buf = p & 1;
+    if (r0 == (p & 3)) rowb[buf][c] = v[p >> 2];
+    if (c == p) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) colb[buf][r0 + 4 * m] = v[m];
+    }
+    __syncthreads();
+    const double piv = rowb[buf][p];
+    ok = ok && piv > 0.0;
+    const double ip = 1.0 / piv;
+    const double rp = rowb[buf][c] * ip;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int ii = r0 + 4 * m;
+      const double cp = colb[buf][ii];
+      if (ii == p) v[m] = (c == p) ? ip : rp;
+      else v[m] = (c == p) ? -cp * ip : v[m] - cp * rp;
     }
   }
-  __syncthreads();
-  for (int k = threadIdx.x; k < NS * NS; k += 64) Dinv[(size_t)i * NS * NS + k] = inv[k];
+  if (!ok) {
+    if (l == 0) atomicOr(err, ERRF_NOT_SPD);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = 0.0;
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) Dinv[(size_t)i * NS * NS + (r0 + 4 * m) * NS + c] = v[m];
 }
 
 // ---------------------------------------------------------------- coarse level

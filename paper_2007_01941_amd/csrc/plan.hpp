@@ -127,5 +127,9 @@ struct ba_plan {
   bool have_mixed = false;
   double lambda = 1e-4;
   bamg::Scratch* scratch = nullptr;
+  // side stream of the multigrid setup (default priority), forked from and
+  // joined back into the caller's stream with these events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bamg::Backward* bwd = nullptr;
 };

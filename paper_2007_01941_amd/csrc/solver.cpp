@@ -52,6 +52,9 @@ static void allocate_step(ba_plan* P) {
   P->Sinv.alloc((size_t)P->n_cam * 81);
   P->scratch = new Scratch();
   P->scratch->init(P->n_cam, P->n_pt);
+  BA_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+  BA_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
+  BA_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
   const int nl = (int)P->levels.size();
   for (int l = 0; l < nl; ++l) {
     Level& L = P->levels[l];
@@ -431,8 +434,10 @@ static double tridiag_max_eig(const std::vector<double>& a, const std::vector<do
 }
 
 // lambda_max of D^-1 S on one level: `lanczos_steps` steps of generalized
-// Lanczos in the D inner product (scalars stay on the device; one readback).
-static double lanczos_lmax(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
+// Lanczos in the D inner product. The scalars stay on the device (L.lz_s);
+// lanczos_launch enqueues the process, lanczos_finish turns the scalars read
+// back to the host into the estimate.
+static void lanczos_launch(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
   Level& L = P->levels[l];
   const int n = L.n * L.bs;
   Scratch& W = *P->scratch;
@@ -468,9 +473,9 @@ static double lanczos_lmax(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
                        (const double*)L.lz_w.p, (const double*)L.lz_dw.p, (const double*)lz);
   }
   BA_LAUNCH_CHECK();
-  double h[68];
-  BA_HIP(hipMemcpyAsync(h, lz, sizeof(h), hipMemcpyDeviceToHost, s));
-  BA_HIP(hipStreamSynchronize(s));
+}
+
+static double lanczos_finish(const double* h, int steps) {
   BA_CHECK(h[LZ_NRM] > 0.0 && std::isfinite(h[LZ_NRM]), BA_ERR_NOT_SPD, "smoother blocks are not positive definite");
   // steps whose alpha is valid: all of them unless a breakdown stopped the process
   const int na = h[LZ_STOP] != 0.0 ? (int)h[LZ_COUNT] : steps;
@@ -479,6 +484,35 @@ static double lanczos_lmax(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- multigrid setup
+
+// Dense FP64 inverse of the coarsest level's operator: the equilibrated
+// s S s + eps I (s = diag^-1/2, eps = coarse_shift) by blocked Gauss-Jordan,
+// scaled back: inv = s (s S s + eps I)^-1 s.
+static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
+  Level& Lc = P->levels.back();
+  BA_HIP(hipMemsetAsync(Lc.dense.p, 0, (size_t)Lc.nd * Lc.nd * sizeof(double), s));
+  const int64_t tot = Lc.nnz * Lc.bs * Lc.bs + Lc.nd;
+  hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(tot)), dim3(256), 0, s, Lc.n, Lc.bs, Lc.nd, Lc.row_of.p,
+                     Lc.col.p, Lc.nnz, Lc.S.p, Lc.dense.p);
+  DBuf<double>& scl = Lc.gj_scale;
+  const int64_t nd2 = (int64_t)Lc.nd * Lc.nd;
+  hipLaunchKernelGGL(k_dense_diag, dim3(grid_of<double>(Lc.nd)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
+                     P->errflag.p);
+  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
+                     o->coarse_shift);
+  const int nbk = Lc.nd / GJB;
+  for (int k = 0; k < nbk; ++k) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)Lc.dense.p, k, Lc.gj_piv.p,
+                       P->errflag.p);
+    hipLaunchKernelGGL(k_gj_update, dim3(nbk * nbk), dim3(1024), 0, s, Lc.nd, (const double*)Lc.dense.p, Lc.inv.p,
+                       k, (const double*)Lc.gj_piv.p);
+    std::swap(Lc.dense, Lc.inv);
+  }
+  std::swap(Lc.dense, Lc.inv);
+  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.inv.p, scl.p, 0.0);
+  BA_LAUNCH_CHECK();
+}
+
 
 static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixed, hipStream_t s) {
   const int nl = (int)P->levels.size();
@@ -508,34 +542,22 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   }
   BA_LAUNCH_CHECK();
   P->inspectable_mg = true;
-  check_errflag(P, s, "multigrid setup (QR, Galerkin, smoother blocks)");
-  for (int l = 0; l + 1 < nl; ++l) P->levels[l].lmax = lanczos_lmax(P, o, l, s);
-  // coarsest level: dense FP64 inverse
-  Level& Lc = P->levels[nl - 1];
-  BA_HIP(hipMemsetAsync(Lc.dense.p, 0, (size_t)Lc.nd * Lc.nd * sizeof(double), s));
-  const int64_t tot = Lc.nnz * Lc.bs * Lc.bs + Lc.nd;
-  hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(tot)), dim3(256), 0, s, Lc.n, Lc.bs, Lc.nd, Lc.row_of.p,
-                     Lc.col.p, Lc.nnz, Lc.S.p, Lc.dense.p);
-  DBuf<double>& scl = Lc.gj_scale;
-  const int64_t nd2 = (int64_t)Lc.nd * Lc.nd;
-  // invert the equilibrated matrix s S s + eps I (s = diag^-1/2, eps = coarse_shift),
-  // then scale back: inv = s (s S s + eps I)^-1 s
-  hipLaunchKernelGGL(k_dense_diag, dim3(grid_of<double>(Lc.nd)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
-                     P->errflag.p);
-  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
-                     o->coarse_shift);
-  const int nbk = Lc.nd / GJB;
-  for (int k = 0; k < nbk; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)Lc.dense.p, k, Lc.gj_piv.p,
-                       P->errflag.p);
-    hipLaunchKernelGGL(k_gj_update, dim3(nbk * nbk), dim3(1024), 0, s, Lc.nd, (const double*)Lc.dense.p, Lc.inv.p,
-                       k, (const double*)Lc.gj_piv.p);
-    std::swap(Lc.dense, Lc.inv);
-  }
-  std::swap(Lc.dense, Lc.inv);
-  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.inv.p, scl.p, 0.0);
-  BA_LAUNCH_CHECK();
-  check_errflag(P, s, "coarse inverse");
+  // The coarsest level's dense inverse and the smoothers' Lanczos estimates
+  // are independent: the inverse runs on the plan's side stream (forked from
+  // and joined back into s), the Lanczos processes on s.
+  BA_HIP(hipEventRecord(P->ev_fork, s));
+  BA_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+  coarse_inverse(P, o, P->side);
+  BA_HIP(hipEventRecord(P->ev_join, P->side));
+  for (int l = 0; l + 1 < nl; ++l) lanczos_launch(P, o, l, s);
+  BA_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
+  // one readback: Lanczos scalars of every level and the error flags
+  std::vector<double> h((size_t)std::max(1, nl - 1) * 68);
+  for (int l = 0; l + 1 < nl; ++l)
+    BA_HIP(hipMemcpyAsync(h.data() + (size_t)l * 68, P->levels[l].lz_s.p, 68 * sizeof(double),
+                          hipMemcpyDeviceToHost, s));
+  check_errflag(P, s, "multigrid setup (QR, Galerkin, smoother blocks, coarse inverse)");
+  for (int l = 0; l + 1 < nl; ++l) P->levels[l].lmax = lanczos_finish(h.data() + (size_t)l * 68, o->lanczos_steps);
   if (mixed) {
     for (int l = 0; l < nl; ++l) {
       Level& L = P->levels[l];
@@ -567,8 +589,6 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
                      o->lambda, D, P->n_cam, P->F.p, P->E.p, P->fres.p, mixed ? P->F32.p : nullptr,
                      mixed ? P->E32.p : nullptr, P->Cinv.p, mixed ? P->Cinv32.p : nullptr, P->vgp.p, P->gp.p,
                      P->Dp.p, P->prec.p, P->n_tiles, P->errflag.p);
-  BA_LAUNCH_CHECK();
-  check_errflag(P, s);
   hipLaunchKernelGGL(k_camera_blocks, dim3(xcd_grid(P->n_cam)), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->cam_q.p,
                      P->n_obs_pad, P->campre.p, P->prec.p, P->fres.p, o->lambda, D, P->A.p,
                      mixed ? P->A32.p : nullptr, P->Dc.p, P->b.p, P->Scc.p, P->Sinv.p,
