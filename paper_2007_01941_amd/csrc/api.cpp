@@ -212,10 +212,13 @@ ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32
 
 void ba_plan_destroy(ba_plan* p) {
   if (!p) return;
-  if (p->side) {
-    (void)hipStreamSynchronize(p->side);
-    (void)hipStreamDestroy(p->side);
+  for (hipStream_t st : {p->side, p->side2}) {
+    if (!st) continue;
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
   }
+  for (hipEvent_t e : p->ev_qr) if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : p->ev_lvl) if (e) (void)hipEventDestroy(e);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   delete p->scratch;

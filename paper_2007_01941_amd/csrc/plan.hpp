@@ -129,7 +129,8 @@ struct ba_plan {
   bamg::Scratch* scratch = nullptr;
   // side stream of the multigrid setup (default priority), forked from and
   // joined back into the caller's stream with these events
-  hipStream_t side = nullptr;
+  hipStream_t side = nullptr, side2 = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  std::vector<hipEvent_t> ev_qr, ev_lvl;   // per level: QR done; operator and block inverses ready
   bamg::Backward* bwd = nullptr;
 };

@@ -53,8 +53,13 @@ static void allocate_step(ba_plan* P) {
   P->scratch = new Scratch();
   P->scratch->init(P->n_cam, P->n_pt);
   BA_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+  BA_HIP(hipStreamCreateWithFlags(&P->side2, hipStreamNonBlocking));
   BA_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
   BA_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+  P->ev_qr.assign(P->levels.size(), nullptr);
+  P->ev_lvl.assign(P->levels.size(), nullptr);
+  for (hipEvent_t& e : P->ev_qr) BA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (hipEvent_t& e : P->ev_lvl) BA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   const int nl = (int)P->levels.size();
   for (int l = 0; l < nl; ++l) {
     Level& L = P->levels[l];
@@ -514,11 +519,34 @@ static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
 }
 
 
+// Numeric multigrid setup as a small task graph on three streams (forked from
+// and joined back into s with events):
+//   side : near-nullspace, then QR of every level in turn (QR(l+1) needs only
+//          the coarse K of QR(l));
+//   s    : explicit level-0 S, then per level the Galerkin product (after
+//          QR(l)) and the next level's block inverses, then the coarsest
+//          level's dense inverse;
+//   side2: the Lanczos estimate of every level once its operator and block
+//          inverses are ready.
 static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixed, hipStream_t s) {
   const int nl = (int)P->levels.size();
   Level& L0 = P->levels[0];
-  // explicit level-0 S (Section 3.6): needed for the Galerkin product and, when
-  // cheaper than the implicit form, for smoothing
+  BA_HIP(hipEventRecord(P->ev_fork, s));
+  // ---- side: near-nullspace and the QR chain
+  BA_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+  hipLaunchKernelGGL(k_nullspace0, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, P->side, P->n_cam, cams,
+                     P->campre.p, L0.K.p);
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level& F = P->levels[l];
+    Level& C = P->levels[l + 1];
+    const size_t lds = (size_t)2 * F.max_agg * F.bs * NS * sizeof(double);
+    BA_CHECK(lds <= 160 * 1024, BA_ERR_LIMIT, "aggregate with %d nodes exceeds the QR kernel's LDS", F.max_agg);
+    hipLaunchKernelGGL(k_qr_aggregates, dim3(F.n_agg), dim3(64), lds, P->side, F.bs, F.agg_ptr.p, F.agg_mem.p,
+                       F.K.p, F.P.p, C.K.p);
+    BA_HIP(hipEventRecord(P->ev_qr[l], P->side));
+  }
+  // ---- s: explicit level-0 S (Section 3.6), needed for the Galerkin product
+  // and, when cheaper than the implicit form, for smoothing
   hipLaunchKernelGGL(k_s0_init, dim3(grid_of<double>(L0.nnz * 81)), dim3(256), 0, s, (int64_t)L0.nnz * 81,
                      L0.row_of.p, L0.col.p, P->Scc.p, L0.S.p);
   if (P->s0_chunks > 0)
@@ -526,30 +554,27 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
                        L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
                        L0.S.p);
   L0.explicit_op = level0_explicit(P, o, mixed ? 4 : 8);
-  hipLaunchKernelGGL(k_nullspace0, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
-                     L0.K.p);
+  BA_HIP(hipEventRecord(P->ev_lvl[0], s));
   for (int l = 0; l + 1 < nl; ++l) {
     Level& F = P->levels[l];
     Level& C = P->levels[l + 1];
-    const size_t lds = (size_t)2 * F.max_agg * F.bs * NS * sizeof(double);
-    BA_CHECK(lds <= 160 * 1024, BA_ERR_LIMIT, "aggregate with %d nodes exceeds the QR kernel's LDS", F.max_agg);
-    hipLaunchKernelGGL(k_qr_aggregates, dim3(F.n_agg), dim3(64), lds, s, F.bs, F.agg_ptr.p, F.agg_mem.p, F.K.p, F.P.p,
-                       C.K.p);
+    BA_HIP(hipStreamWaitEvent(s, P->ev_qr[l], 0));
     hipLaunchKernelGGL(k_galerkin, dim3((unsigned)C.nnz), dim3(256), 0, s, F.bs, F.gal_ptr.p, F.gal_fine.p,
                        F.row_of.p, F.col.p, F.S.p, F.P.p, C.S.p);
     if (l + 1 < nl - 1)
       hipLaunchKernelGGL(k_diag_inverse16, dim3(C.n), dim3(64), 0, s, C.diag_pos.p, C.S.p, C.Dinv.p, P->errflag.p);
+    BA_HIP(hipEventRecord(P->ev_lvl[l + 1], s));
   }
+  // ---- side2: Lanczos per level
+  for (int l = 0; l + 1 < nl; ++l) {
+    BA_HIP(hipStreamWaitEvent(P->side2, P->ev_lvl[l], 0));
+    lanczos_launch(P, o, l, P->side2);
+  }
+  BA_HIP(hipEventRecord(P->ev_join, P->side2));
+  // ---- s: coarsest level's dense inverse
+  coarse_inverse(P, o, s);
   BA_LAUNCH_CHECK();
   P->inspectable_mg = true;
-  // The coarsest level's dense inverse and the smoothers' Lanczos estimates
-  // are independent: the inverse runs on the plan's side stream (forked from
-  // and joined back into s), the Lanczos processes on s.
-  BA_HIP(hipEventRecord(P->ev_fork, s));
-  BA_HIP(hipStreamWaitEvent(P->side, P->ev_fork, 0));
-  coarse_inverse(P, o, P->side);
-  BA_HIP(hipEventRecord(P->ev_join, P->side));
-  for (int l = 0; l + 1 < nl; ++l) lanczos_launch(P, o, l, s);
   BA_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
   // one readback: Lanczos scalars of every level and the error flags
   std::vector<double> h((size_t)std::max(1, nl - 1) * 68);
