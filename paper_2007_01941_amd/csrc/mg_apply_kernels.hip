@@ -39,6 +39,18 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
   __shared__ T rs[BS];
   const int row = blockIdx.x;
   const int pidx = threadIdx.x / BS, comp = threadIdx.x % BS;
+  const bool own = threadIdx.x < BS;
+  const size_t k = (size_t)row * BS + comp;
+  // the epilogue's operands are loaded first, so that their latency overlaps
+  // the row product's
+  T r0 = 0, d0 = 0, x0 = 0;
+  if (own && EP != EP_STORE) {
+    r0 = EP == EP_CHEB_POST ? b[k] : r[k];
+    if (EP == EP_CHEB) d0 = d_in[k];
+    if (EP == EP_CHEB || EP == EP_CHEB_POST) x0 = x_in[k];
+  }
+  int slot = 0;
+  if (EP == EP_RESID && threadIdx.x < NS) slot = slot_of[row];
   T acc = 0;
   if (pidx < PARTS) {
     const int e1 = rowptr[row + 1];
@@ -47,14 +59,11 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
       const T* blk = S + (size_t)e * BS * BS + comp * BS;
       const T* xv = v + (size_t)col[e] * BS;
 #pragma unroll
-      for (int k = 0; k < BS; ++k) acc += blk[k] * xv[k];
+      for (int k2 = 0; k2 < BS; ++k2) acc += blk[k2] * xv[k2];
     }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
-  const bool own = threadIdx.x < BS;
-  const size_t k = (size_t)row * BS + comp;
-  T rv = 0;
   if (own) {
     T tsum = 0;
 #pragma unroll 4
@@ -62,7 +71,7 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
     if (EP == EP_STORE) {
       out[k] = tsum;
     } else {
-      rv = EP == EP_CHEB_POST ? b[k] - tsum : r[k] - tsum;
+      const T rv = r0 - tsum;
       r[k] = rv;
       rs[comp] = rv;
     }
@@ -75,7 +84,7 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
       T sacc = 0;
 #pragma unroll
       for (int k2 = 0; k2 < BS; ++k2) sacc += Pi[k2 * NS] * rs[k2];
-      rpart[(size_t)slot_of[row] * NS + threadIdx.x] = sacc;
+      rpart[(size_t)slot * NS + threadIdx.x] = sacc;
     }
     return;
   }
@@ -84,9 +93,9 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
   T z = 0;
 #pragma unroll
   for (int k2 = 0; k2 < BS; ++k2) z += m[k2] * rs[k2];
-  const T dv = EP == EP_CHEB ? c1 * d_in[k] + c2 * z : c2 * z;
+  const T dv = EP == EP_CHEB ? c1 * d0 + c2 * z : c2 * z;
   d_out[k] = dv;
-  x_out[k] = x_in[k] + dv;
+  x_out[k] = x0 + dv;
 }
 
 // z = D^-1 r block by block (BS x BS inverse blocks), one thread per dof.

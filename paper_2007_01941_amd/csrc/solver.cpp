@@ -3,6 +3,8 @@
 // (Included by api.cpp inside namespace-level scope.)
 #include <algorithm>
 #include <cmath>
+#include <string>
+#include <thread>
 
 namespace bamg {
 
@@ -505,6 +507,7 @@ static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
                      P->errflag.p);
   hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
                      o->coarse_shift);
+  // Pivot step k: P_k = A_kk^-1 (one workgroup), then the update of every block.
   const int nbk = Lc.nd / GJB;
   for (int k = 0; k < nbk; ++k) {
     hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)Lc.dense.p, k, Lc.gj_piv.p,
@@ -565,14 +568,39 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
       hipLaunchKernelGGL(k_diag_inverse16, dim3(C.n), dim3(64), 0, s, C.diag_pos.p, C.S.p, C.Dinv.p, P->errflag.p);
     BA_HIP(hipEventRecord(P->ev_lvl[l + 1], s));
   }
-  // ---- side2: Lanczos per level
-  for (int l = 0; l + 1 < nl; ++l) {
-    BA_HIP(hipStreamWaitEvent(P->side2, P->ev_lvl[l], 0));
-    lanczos_launch(P, o, l, P->side2);
-  }
-  BA_HIP(hipEventRecord(P->ev_join, P->side2));
+  // ---- side2: Lanczos per level, enqueued from a second host thread (its
+  // many small launches would otherwise hold back the coarse inverse's)
+  // (the error message is thread-local: a failure there is re-raised here
+  // with its message)
+  bool lz_failed = false;
+  ba_status lz_status = BA_OK;
+  std::string lz_msg;
+  std::thread lz([&]() {
+    try {
+      for (int l = 0; l + 1 < nl; ++l) {
+        BA_HIP(hipStreamWaitEvent(P->side2, P->ev_lvl[l], 0));
+        lanczos_launch(P, o, l, P->side2);
+      }
+      BA_HIP(hipEventRecord(P->ev_join, P->side2));
+    } catch (const Fail& f) {
+      lz_failed = true;
+      lz_status = f.st;
+      lz_msg = ba_last_error();
+    } catch (...) {
+      lz_failed = true;
+      lz_status = BA_ERR_HIP;
+      lz_msg = "Lanczos enqueue failed";
+    }
+  });
   // ---- s: coarsest level's dense inverse
-  coarse_inverse(P, o, s);
+  try {
+    coarse_inverse(P, o, s);
+  } catch (...) {
+    lz.join();
+    throw;
+  }
+  lz.join();
+  BA_CHECK(!lz_failed, lz_status, "%s", lz_msg.c_str());
   BA_LAUNCH_CHECK();
   P->inspectable_mg = true;
   BA_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
@@ -711,7 +739,11 @@ static ba_status solve_camera_system(ba_plan* P, const ba_opts* o, const double*
     bool conv = bb == 0.0;
     for (; ref < o->max_refine && !conv; ++ref) {
       convert(n, W.t.p, W.fb.p, s);
-      PcgOut r = pcg_run<float>(P, o, W.fb.p, PcgVecs<float>{W.fx.p, W.fr.p, W.fz.p, W.fp.p, W.fq.p}, o->inner_rtol,
+      // the inner solve needs to reduce the current residual only to the outer
+      // target (with a factor 2 margin), never by less than inner_rtol
+      const double need = 0.5 * o->rtol * std::sqrt(bb / rr);
+      const double tol = std::min(0.5, std::max(o->inner_rtol, need));
+      PcgOut r = pcg_run<float>(P, o, W.fb.p, PcgVecs<float>{W.fx.p, W.fr.p, W.fz.p, W.fp.p, W.fq.p}, tol,
                                 o->max_iter, s);
       BA_CHECK(!r.breakdown, BA_ERR_NOT_SPD, "PCG breakdown in an FP32 inner solve");
       iters += r.iters;
