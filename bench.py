@@ -211,6 +211,7 @@ def main():
             vms, _, vst, vdc, _ = run(opts, max(2, args.steps // 2), 1)
             s2 = vst[-1]
             var[name] = {"s_per_step": vms / 1e3, "pcg_iters": s2.iters, "refine_steps": s2.refine_steps,
+                         "fp64_fallback": s2.fallback_fp64,
                          "rel_res": s2.rel_res, "phases_ms": {"jacobian_and_blocks": s2.t_jacobian_ms,
                                                               "setup": s2.t_setup_ms,
                                                               "solve": s2.t_solve_ms},

@@ -93,6 +93,10 @@ typedef struct {            /* (host) */
   double t_jacobian_ms;     /* residual + Jacobian + normal blocks */
   double t_setup_ms;        /* preconditioner numeric setup */
   double t_solve_ms;        /* PCG (and refinement) + back-substitution */
+  int32_t fallback_fp64;    /* BA_MIXED: 1 if an FP32 inner solve broke down (FP32 rounding of S
+                               exceeded its smallest eigenvalues) and the solve was finished by
+                               FP64 PCG on the FP64 residual */
+  int32_t reserved_stats;
 } ba_stats;
 
 /* Defaults listed above. (host) o. */

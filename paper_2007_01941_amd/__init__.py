@@ -32,12 +32,13 @@ class Stats:
     t_setup_ms: float
     t_solve_ms: float
     converged: bool = True
+    fallback_fp64: bool = False
 
 
 def _stats(st: _lib._Stats, status) -> Stats:
     return Stats(st.iters, st.refine_steps, st.levels, list(st.nodes[: max(st.levels, 0)]),
                  st.rel_res, st.t_jacobian_ms, st.t_setup_ms, st.t_solve_ms,
-                 status == _lib.BA_OK)
+                 status == _lib.BA_OK, bool(st.fallback_fp64))
 
 
 def _ptr(t):

@@ -49,7 +49,8 @@ class _Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
                 ("levels", ctypes.c_int32), ("nodes", ctypes.c_int32 * 16),
                 ("rel_res", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
-                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double)]
+                ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
+                ("fallback_fp64", ctypes.c_int32), ("reserved_stats", ctypes.c_int32)]
 
 
 @dataclasses.dataclass

@@ -19,7 +19,7 @@ void set_error(const char* fmt, ...) {
 // PCG and refinement workspace of a plan.
 struct Scratch {
   int n = 0;  // 9 * n_cam
-  DBuf<double> x, r, z, p, q, t, bref;
+  DBuf<double> x, r, z, p, q, t, bref, e;
   DBuf<float> fx, fr, fz, fp, fq, fb;
   DBuf<double> partial;
   DBuf<PcgScal> scal;
@@ -28,7 +28,7 @@ struct Scratch {
   PcgScal* h_scal = nullptr;
   void init(int ncam, int npt) {
     n = 9 * ncam;
-    for (DBuf<double>* b : {&x, &r, &z, &p, &q, &t, &bref}) b->alloc(n);
+    for (DBuf<double>* b : {&x, &r, &z, &p, &q, &t, &bref, &e}) b->alloc(n);
     for (DBuf<float>* b : {&fx, &fr, &fz, &fp, &fq, &fb}) b->alloc(n);
     partial.alloc(RED_BLOCKS);
     scal.alloc(2);

@@ -195,6 +195,12 @@ __global__ void k_axpby(int n, const double* __restrict__ a, double s, const dou
   if (i < n) y[i] = a[i] + s * b[i];
 }
 
+// x += e (FP64 correction)
+__global__ void k_add_f64(int n, const double* __restrict__ e, double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += e[i];
+}
+
 // x += (double) e (refinement update)
 __global__ void k_add_f32(int n, const float* __restrict__ e, double* __restrict__ x) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -745,13 +745,35 @@ static ba_status solve_camera_system(ba_plan* P, const ba_opts* o, const double*
       const double tol = std::min(0.5, std::max(o->inner_rtol, need));
       PcgOut r = pcg_run<float>(P, o, W.fb.p, PcgVecs<float>{W.fx.p, W.fr.p, W.fz.p, W.fp.p, W.fq.p}, tol,
                                 o->max_iter, s);
-      BA_CHECK(!r.breakdown, BA_ERR_NOT_SPD, "PCG breakdown in an FP32 inner solve");
       iters += r.iters;
-      hipLaunchKernelGGL(k_add_f32, dim3(grid_of<double>(n)), dim3(256), 0, s, n, W.fx.p, W.x.p);
+      if (r.breakdown) {
+        // The FP32 operator or preconditioner lost definiteness (S's smallest
+        // eigenvalues below FP32 rounding of its terms): keep the iterate
+        // reached, and finish with an FP64 PCG on the FP64 residual.
+        if (r.iters > 0) {
+          hipLaunchKernelGGL(k_add_f32, dim3(grid_of<double>(n)), dim3(256), 0, s, n, W.fx.p, W.x.p);
+          schur_apply_dev<double>(P, W.x.p, W.q.p, nullptr, s);
+          hipLaunchKernelGGL(k_axpby, dim3(grid_of<double>(n)), dim3(256), 0, s, n, b, -1.0, W.q.p, W.t.p);
+          rr = plain_dot(P, n, W.t.p, W.t.p, s);
+        }
+        const double tol64 = std::min(0.5, o->rtol * std::sqrt(bb / std::max(rr, 1e-300)));
+        PcgOut r64 = pcg_run<double>(P, o, W.t.p, PcgVecs<double>{W.e.p, W.r.p, W.z.p, W.p.p, W.q.p}, tol64,
+                                     o->max_iter, s);
+        BA_CHECK(!r64.breakdown, BA_ERR_NOT_SPD, "PCG breakdown: the operator or preconditioner is not SPD");
+        iters += r64.iters;
+        hipLaunchKernelGGL(k_add_f64, dim3(grid_of<double>(n)), dim3(256), 0, s, n, (const double*)W.e.p, W.x.p);
+        if (st) st->fallback_fp64 = 1;
+      } else {
+        hipLaunchKernelGGL(k_add_f32, dim3(grid_of<double>(n)), dim3(256), 0, s, n, W.fx.p, W.x.p);
+      }
       schur_apply_dev<double>(P, W.x.p, W.q.p, nullptr, s);
       hipLaunchKernelGGL(k_axpby, dim3(grid_of<double>(n)), dim3(256), 0, s, n, b, -1.0, W.q.p, W.t.p);
       rr = plain_dot(P, n, W.t.p, W.t.p, s);
       conv = rr <= o->rtol * o->rtol * bb;
+      if (r.breakdown) {
+        ++ref;
+        break;
+      }
     }
     if (st) {
       st->iters = iters;
