@@ -219,6 +219,23 @@ def main():
             log(f"[bench] {name}: {vms:.2f} ms/step, iters {s2.iters}, rel_res {s2.rel_res:.2e}")
         result["variants"] = var
 
+    # ---- differentiation form: the adjoint of the step (loss |delta|^2, so dL/d delta = 2 delta)
+    if not args.no_variants:
+        bw = []
+        for i in range(3):
+            torch.cuda.synchronize()
+            t0 = time.time()
+            g = plan.backward(cams, pts, uv, dc, dp, 2 * dc, 2 * dp, opts=mg64)
+            torch.cuda.synchronize()
+            if i > 0:
+                bw.append(time.time() - t0)
+        gst = g[3]
+        result["adjoint"] = {"s_per_backward": sum(bw) / len(bw), "pcg_iters": gst.iters,
+                             "phases_ms": {"jacobian_and_blocks": gst.t_jacobian_ms, "setup": gst.t_setup_ms,
+                                           "adjoint_solve_and_gradients": gst.t_solve_ms}}
+        log(f"[bench] adjoint (backward of the step): {result['adjoint']['s_per_backward'] * 1e3:.2f} ms, "
+            f"iters {gst.iters}")
+
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(sc, st.iters)

@@ -553,18 +553,23 @@ __device__ __forceinline__ void stage_block(double* __restrict__ dst, const doub
 }
 
 // Pivot step k of blocked Gauss-Jordan from Ain to Aout, given P = A_kk^-1:
-// one workgroup (16 waves) per 64 x 64 block (i, j) writes
+// one workgroup (16 waves) per 64 x 64 block (i, j), i <= j, writes
 //   (k, k): P;   (k, j): P A_kj;   (i, k): -A_ik P;   else A_ij - A_ik (P A_kj),
-// operands staged in LDS, products on the FP64 matrix cores.
+// operands staged in LDS, products on the FP64 matrix cores. The iterate
+// keeps a fixed symmetry: A_ji = s A_ij^T with s = -1 when exactly one of
+// i, j has already served as pivot (i, j <= k) and +1 otherwise, so each
+// workgroup also writes block (j, i) and only the upper blocks are computed.
 __global__ __launch_bounds__(1024) void k_gj_update(int nd, const double* __restrict__ Ain, double* __restrict__ Aout,
                                                     int k, const double* __restrict__ Pbuf) {
   constexpr int LD = GJB + 1;
   __shared__ double X[GJB * LD];
   __shared__ double Y[GJB * LD];
   const int nb = nd / GJB;
-  const int bi = blockIdx.x / nb, bj = blockIdx.x % nb;
+  // upper block number -> (bi, bj), bi <= bj, row by row
+  int bi = 0, rem = blockIdx.x;
+  while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
+  const int bj = bi + rem;
   const size_t k0 = (size_t)k * GJB, i0 = (size_t)bi * GJB, j0 = (size_t)bj * GJB;
-  double* out = block_tile(Aout + i0 * nd + j0, nd);
   d4 acc = {0, 0, 0, 0};
   if (bi == k && bj == k) {
     stage_block(X, Pbuf, GJB);
@@ -593,7 +598,17 @@ __global__ __launch_bounds__(1024) void k_gj_update(int nd, const double* __rest
     acc = tile_load(block_tile(const_cast<double*>(Ain) + i0 * nd + j0, nd), nd);
     acc = block_mma(acc, X, LD, Y, LD, -1.0);
   }
-  tile_store(out, nd, acc);
+  tile_store(block_tile(Aout + i0 * nd + j0, nd), nd, acc);
+  if (bi != bj) {
+    // block (j, i) = s (block (i, j))^T: this wave's tile (tr, tc) goes to
+    // tile (tc, tr) of block (j, i), transposed
+    const double sgn = ((bi <= k) != (bj <= k)) ? -1.0 : 1.0;
+    const int w = threadIdx.x >> 6, tr = w >> 2, tc = w & 3;
+    const int l = threadIdx.x & 63;
+    double* T = Aout + (j0 + tc * 16) * nd + i0 + tr * 16;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) T[(size_t)(l & 15) * nd + 4 * t + (l >> 4)] = sgn * acc[t];
+  }
 }
 
 }  // namespace bamg

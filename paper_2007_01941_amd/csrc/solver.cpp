@@ -512,8 +512,8 @@ static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
   for (int k = 0; k < nbk; ++k) {
     hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)Lc.dense.p, k, Lc.gj_piv.p,
                        P->errflag.p);
-    hipLaunchKernelGGL(k_gj_update, dim3(nbk * nbk), dim3(1024), 0, s, Lc.nd, (const double*)Lc.dense.p, Lc.inv.p,
-                       k, (const double*)Lc.gj_piv.p);
+    hipLaunchKernelGGL(k_gj_update, dim3(nbk * (nbk + 1) / 2), dim3(1024), 0, s, Lc.nd, (const double*)Lc.dense.p,
+                       Lc.inv.p, k, (const double*)Lc.gj_piv.p);
     std::swap(Lc.dense, Lc.inv);
   }
   std::swap(Lc.dense, Lc.inv);
