@@ -207,10 +207,4 @@ __global__ void k_add_f32(int n, const float* __restrict__ e, double* __restrict
   if (i < n) x[i] += (double)e[i];
 }
 
-template <class T>
-__global__ void k_fill(size_t n, T* __restrict__ a, T v) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = v;
-}
-
 }  // namespace bamg
