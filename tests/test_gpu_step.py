@@ -6,7 +6,7 @@ import pytest
 from oracle import camera, multigrid as omg, step as ostep
 from scenes import tiny_scene
 from tests._fixtures import scene
-from tests._gpu import host, inputs, plan_for, rel
+from tests._gpu import dev, host, inputs, plan_for, rel
 
 # Forward-error bounds: a sum of products computed in FP64 in any order differs
 # from the exact value by at most n u sum|terms| (u = 2^-53, n = terms in the
@@ -148,6 +148,41 @@ def test_step_fp64(name, pc):
     slack = TOL_U * np.linalg.norm(schur_abs(nrm, host(dc)) + rhs_abs(nrm))
     assert np.linalg.norm(r) <= 2e-10 * np.linalg.norm(nrm.rhs()) + slack
     assert abs(st.iters - ref.iters) <= 2
+    assert rel(host(dc), ref.delta_c) <= 1e-6
+    assert rel(host(dp), ref.delta_p) <= 1e-6
+
+
+@pytest.mark.parametrize("name", SCENES)
+def test_step_mg_implicit_level0(name):
+    """The V-cycle with the implicit product as the level-0 operator (smoothing
+    and Lanczos) reaches the same step as the oracle's explicit-operator MG."""
+    sc = _sc(name)
+    plan, opts = plan_for(sc, precond="mg", rtol=1e-10, coarse_max_nodes=16, level0_op="implicit")
+    dc, dp, st = plan.lm_step(*inputs(sc))
+    ref = ostep.lm_step(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv, method="mg", rtol=1e-10,
+                        opts=omg.MGOptions(coarse_max_nodes=16))
+    print(f"[gpu] {name} mg implicit level 0: iters {st.iters} (oracle {ref.iters}) "
+          f"err_vs_oracle {rel(host(dc), ref.delta_c):.2e}", flush=True)
+    assert st.converged and st.rel_res <= 1e-10
+    assert abs(st.iters - ref.iters) <= 2
+    assert rel(host(dc), ref.delta_c) <= 1e-6
+    assert rel(host(dp), ref.delta_p) <= 1e-6
+
+
+@pytest.mark.parametrize("pc", ["bj", "mg"])
+def test_step_explicit_damping(pc):
+    """An explicit damping diagonal D (camera entries first, caller order)
+    replaces lambda diag(J^T J) in A and C."""
+    sc = _sc("ring64")
+    rng = np.random.default_rng(9)
+    nrm0 = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    # a positive diagonal of the scale of the Marquardt one, varied per entry
+    D = np.concatenate([nrm0.Dc.ravel(), nrm0.Dp.ravel()]) * rng.uniform(0.5, 20.0, 9 * sc.n_cam + 3 * sc.n_pt)
+    plan, opts = plan_for(sc, precond=pc, rtol=1e-10, coarse_max_nodes=16)
+    dc, dp, st = plan.lm_step(*inputs(sc), D=dev(D))
+    ref = ostep.lm_step(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv, method="full", D=D)
+    print(f"[gpu] ring64 {pc} explicit D: iters {st.iters} err {rel(host(dc), ref.delta_c):.2e}", flush=True)
+    assert st.converged
     assert rel(host(dc), ref.delta_c) <= 1e-6
     assert rel(host(dp), ref.delta_p) <= 1e-6
 
