@@ -247,6 +247,39 @@ static void vcycle(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> p
   else vcycle_level<16, T>(P, o, l, b, x, pend, done, s);
 }
 
+// Coarse-grid correction of level l: xc = V-cycle of level l+1 on the restricted
+// residual (given as the pending partials `pend`, or, with pend.part null, as
+// bc). Coarse levels always run in FP64: their 16 x 16 diagonal blocks are
+// nearly singular along the aggregates' rigid motions (held only by the
+// damping), so FP32 block inverses there are meaningless; in the FP32 V-cycle
+// the level-0 partials (or bc) are widened and the correction narrowed back.
+template <class T>
+static void coarse_correction(ba_plan* P, const ba_opts* o, int l, T* bc, T* xc, Pending<T> pend, const int* done,
+                              hipStream_t s);
+
+template <>
+void coarse_correction<double>(ba_plan* P, const ba_opts* o, int l, double* bc, double* xc, Pending<double> pend,
+                               const int* done, hipStream_t s) {
+  vcycle<double>(P, o, l + 1, bc, xc, pend, done, s);
+}
+
+template <>
+void coarse_correction<float>(ba_plan* P, const ba_opts* o, int l, float* bc, float* xc, Pending<float> pend,
+                              const int* done, hipStream_t s) {
+  Level& L = P->levels[l];
+  Level& C = P->levels[l + 1];
+  Pending<double> wide;
+  if (pend.part) {
+    convert((size_t)L.n * NS, pend.part, L.vpart.p, s);
+    wide.agg_ptr = pend.agg_ptr;
+    wide.part = L.vpart.p;
+  } else {
+    convert((size_t)C.n * C.bs, (const float*)bc, C.vb.p, s);
+  }
+  vcycle<double>(P, o, l + 1, C.vb.p, C.vx.p, wide, done, s);
+  convert((size_t)C.n * C.bs, (const double*)C.vx.p, xc, s);
+}
+
 // One V-cycle level (Algorithm 1) with the explicit level operator: every
 // Chebyshev step after the first is one fused block-row launch (product and
 // update), with the direction d and, in post-smoothing, the iterate
@@ -290,7 +323,7 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, 
   Pending<T> next;
   next.agg_ptr = L.agg_ptr.p;
   next.part = part;
-  vcycle<T>(P, o, l + 1, bc, xc, next, done, s);
+  coarse_correction<T>(P, o, l, bc, xc, next, done, s);
   hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
                      lvP<T>(L), (const T*)xc, x, done);
   // post-smoothing from x: r = b - S x, d = D^-1 r / theta, iterate -> x2
@@ -349,7 +382,7 @@ static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pendin
                      L.slot_of.p, lvP<T>(L), (const T*)r, (const T*)t, part, done);
   hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n, L.agg_ptr.p,
                      (const T*)part, bc, done);
-  vcycle<T>(P, o, l + 1, bc, xc, Pending<T>(), done, s);
+  coarse_correction<T>(P, o, l, bc, xc, Pending<T>(), done, s);
   hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
                      lvP<T>(L), (const T*)xc, x, done);
   // post-smoothing from x
@@ -612,14 +645,9 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   check_errflag(P, s, "multigrid setup (QR, Galerkin, smoother blocks, coarse inverse)");
   for (int l = 0; l + 1 < nl; ++l) P->levels[l].lmax = lanczos_finish(h.data() + (size_t)l * 68, o->lanczos_steps);
   if (mixed) {
-    for (int l = 0; l < nl; ++l) {
-      Level& L = P->levels[l];
-      convert((size_t)L.nnz * L.bs * L.bs, L.S.p, L.S32.p, s);
-      if (l + 1 < nl) {
-        convert((size_t)L.n * L.bs * NS, L.P.p, L.P32.p, s);
-        if (l > 0) convert((size_t)L.n * L.bs * L.bs, L.Dinv.p, L.Dinv32.p, s);
-      }
-    }
+    // FP32 copies of level 0 (the coarse levels of the FP32 V-cycle run in FP64)
+    convert((size_t)L0.nnz * L0.bs * L0.bs, L0.S.p, L0.S32.p, s);
+    if (nl > 1) convert((size_t)L0.n * L0.bs * NS, L0.P.p, L0.P32.p, s);
   }
   P->prepared_mg = true;
 }
