@@ -279,8 +279,13 @@ class PCGResult:
     history: list
 
 
-def pcg(apply_A, apply_M, b, rtol, max_iter=10000):
-    """Saad Algorithm 9.1, x0 = 0, stop on ||r|| <= rtol ||b||."""
+def pcg(apply_A, apply_M, b, rtol, max_iter=10000, forcing=None):
+    """Saad Algorithm 9.1, x0 = 0, stop on ||r|| <= rtol ||b||.
+
+    forcing = tau additionally stops on the Nash-Sofer rule of Section 2.1
+    (a constant forcing sequence, Section 4): with the quadratic model
+    Q_i = 1/2 x_i^T A x_i - x_i^T b of iterate i (Q_0 = 0), stop once
+    i (Q_i - Q_{i-1}) / Q_i <= tau. Q_i is evaluated from its definition."""
     x = np.zeros_like(b)
     r = b.copy()
     bn = np.linalg.norm(b)
@@ -290,6 +295,7 @@ def pcg(apply_A, apply_M, b, rtol, max_iter=10000):
     p = z.copy()
     rz = r @ z
     hist = []
+    q_prev = 0.0
     for it in range(1, max_iter + 1):
         Ap = apply_A(p)
         pAp = p @ Ap
@@ -302,6 +308,11 @@ def pcg(apply_A, apply_M, b, rtol, max_iter=10000):
         hist.append(rn / bn)
         if rn <= rtol * bn:
             return PCGResult(x, it, rn / bn, True, hist)
+        if forcing is not None:
+            q = 0.5 * (x @ apply_A(x)) - x @ b
+            if it * (q - q_prev) / q <= forcing:
+                return PCGResult(x, it, rn / bn, True, hist)
+            q_prev = q
         z = apply_M(r)
         rz_new = r @ z
         p = z + (rz_new / rz) * p

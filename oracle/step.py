@@ -36,9 +36,10 @@ def normal_for(cams, pts, obs_cam, obs_pt, uv, lam=1e-4, D=None):
 
 
 def lm_step(cams, pts, obs_cam, obs_pt, uv, lam=1e-4, method="mg", rtol=1e-8,
-            max_iter=10000, opts: mg.MGOptions = mg.MGOptions(), D=None):
+            max_iter=10000, opts: mg.MGOptions = mg.MGOptions(), D=None, forcing=None):
     """method: 'full' (sparse LU of J^T J + D), 'schur' (dense Cholesky of S),
-    'bj' (PCG, point-block-Jacobi), 'mg' (PCG, multigrid V-cycle)."""
+    'bj' (PCG, point-block-Jacobi), 'mg' (PCG, multigrid V-cycle).
+    forcing: Nash-Sofer tolerance tau for the PCG methods (None: residual rule only)."""
     nrm = normal_for(cams, pts, obs_cam, obs_pt, uv, lam, D)
     n_cam = cams.shape[0]
     if method == "full":
@@ -58,7 +59,7 @@ def lm_step(cams, pts, obs_cam, obs_pt, uv, lam=1e-4, method="mg", rtol=1e-8,
         M = lambda r: mg.vcycle(levels, r, opts)
     else:
         raise ValueError(method)
-    res = mg.pcg(nrm.S_apply, M, b, rtol, max_iter)
+    res = mg.pcg(nrm.S_apply, M, b, rtol, max_iter, forcing)
     dp = nrm.recover_points(res.x, -nrm.g_p.ravel())
     return StepResult(res.x.reshape(n_cam, 9), dp, res.iters, res.rel_res, res.converged,
                       levels, nrm, b)
