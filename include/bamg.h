@@ -56,6 +56,7 @@ typedef enum {
 enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_MULTIGRID = 1 };
 enum { BA_FP64 = 0, BA_MIXED = 1 };
 enum { BA_OP_AUTO = 0, BA_OP_IMPLICIT = 1, BA_OP_EXPLICIT = 2 };
+enum { BA_STOP_RESIDUAL = 0, BA_STOP_NASH_SOFER = 1 };
 
 typedef struct {
   int32_t precond;          /* BA_PC_BLOCK_JACOBI (point block Jacobi, Section 2.2) or BA_PC_MULTIGRID */
@@ -81,7 +82,15 @@ typedef struct {
   double coarse_shift;      /* coarsest direct solve factors s S s + coarse_shift I with
                                s = diag(S)^-1/2, default 1e-10 (keeps it SPD where the
                                coarsest operator is singular to FP64 rounding) */
-  int32_t reserved[8];
+  int32_t stop_rule;        /* PCG stop rule. BA_STOP_RESIDUAL (default): the rtol test above.
+                               BA_STOP_NASH_SOFER: also stop once i (Q_i - Q_{i-1}) / Q_i <= forcing,
+                               Q_i = 1/2 dc_i^T S dc_i - dc_i^T b at PCG iteration i (the forcing rule
+                               of Section 2.1 with a constant forcing sequence, Section 4). FP64 only:
+                               BA_MIXED with BA_STOP_NASH_SOFER is BA_ERR_ARG. The backward pass
+                               always uses the rtol test. */
+  int32_t reserved0;
+  double forcing;           /* tau of BA_STOP_NASH_SOFER, >= 0, default 0.1 */
+  int32_t reserved[4];
 } ba_opts;
 
 typedef struct {            /* (host) */
@@ -223,6 +232,77 @@ ba_status ba_mg_covisibility(const ba_plan* p, int32_t level, int64_t* nnz, int6
  *   what = 5: coarsest level only: inverse of its operator, dense [n][n]. */
 ba_status ba_mg_level_data(const ba_plan* p, int32_t level, int32_t what, double* out,
                            void* stream);
+
+/* ------------------------------------------------------------------------
+ * The Levenberg-Marquardt outer loop around the step (Section 2.1), with the
+ * solver settings of Section 4: a trust region whose radius starts at 1e4
+ * (damping D = diag(J^T J) / radius) and, with ba_opts.stop_rule =
+ * BA_STOP_NASH_SOFER, a constant forcing sequence for the inner PCG. The paper
+ * leaves the radius update to its nonlinear solver; this loop takes the update
+ * of Madsen, Nielsen and Tingleff (2004), Section 3.2, in radius form.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t max_iters;              /* LM iterations, default 100 (Section 4) */
+  int32_t reserved0;
+  double radius0;                 /* initial trust-region radius, default 1e4 (Section 4) */
+  double min_relative_decrease;   /* accept a step when rho exceeds this, default 1e-3 */
+  double function_tol;            /* stop after an accepted step that lowers the cost by at most
+                                     function_tol times the previous cost, default 1e-6 */
+  double parameter_tol;           /* stop (before evaluating the candidate) when
+                                     |delta| <= parameter_tol (|x| + parameter_tol), default 1e-8 */
+  double min_radius;              /* stop when a rejection takes the radius below this, default 1e-32 */
+  double max_radius;              /* cap of the radius, default 1e16 */
+  double reserved[2];
+} ba_lm_opts;
+
+enum { BA_TERM_MAX_ITERS = 0, BA_TERM_FUNCTION = 1, BA_TERM_PARAMETER = 2, BA_TERM_RADIUS = 3 };
+
+typedef struct {                  /* (host) one LM iteration */
+  double cost;                    /* 1/2 sum_o |f_o|^2 at the start of the iteration */
+  double cost_candidate;          /* at x + delta; +inf if the candidate puts a point at or behind an
+                                     observing camera, or its cost is not finite */
+  double model_decrease;          /* 1/2 |f|^2 - 1/2 |f + J delta|^2 */
+  double rho;                     /* (cost - cost_candidate) / model_decrease; -inf if the candidate is
+                                     invalid or model_decrease <= 0 */
+  double radius;                  /* trust-region radius of this step (lambda = 1 / radius) */
+  double step_norm;               /* |delta| over all camera and point parameters */
+  int32_t accepted;
+  int32_t pcg_iters;              /* PCG iterations of this step's linear solve */
+  double t_ms;                    /* time of the iteration */
+} ba_lm_iter;
+
+typedef struct {                  /* (host) */
+  int32_t iters;                  /* iterations recorded in the history */
+  int32_t accepted;               /* accepted steps */
+  int32_t termination;            /* BA_TERM_* */
+  int32_t pcg_iters;              /* summed over all iterations */
+  double cost0, cost;             /* initial and final cost */
+  double t_ms;                    /* total time */
+} ba_lm_summary;
+
+/* Defaults listed above. (host) lo. */
+ba_status ba_lm_opts_default(ba_lm_opts* lo);
+
+/* Cost 1/2 sum_o |pi_o - u_o|^2 at (cams, pts) and the number of observations
+ * whose point is at or behind the camera (x_cam.z >= 0) or whose residual is
+ * not finite (those are left out of the sum). cost, n_invalid (host);
+ * n_invalid may be NULL. Blocks until the values are ready. */
+ba_status ba_cost(ba_plan* p, const double* cams, const double* pts, const double* uv, double* cost,
+                  int64_t* n_invalid, void* stream);
+
+/* Levenberg-Marquardt from (cams, pts), updated in place [n_cam][9], [n_pt][3].
+ * Each iteration solves one step (as ba_lm_step, with lambda = 1 / radius; the
+ * lambda of o is ignored and D = lambda diag(J^T J)), evaluates the model
+ * decrease and the candidate's cost, accepts or rejects the candidate and
+ * updates the radius. Updates are additive on every parameter. An inner solve
+ * that reaches max_iter is used as it stands. o: the linear solver's options;
+ * lo: the loop's. history (host) holds lo->max_iters entries or is NULL;
+ * summary (host) may be NULL. Returns BA_OK whatever the termination rule.
+ * Errors: BA_ERR_GEOMETRY if the initial parameters put a point at or behind
+ * an observing camera or are not finite; the errors of ba_lm_step. After an
+ * error cams and pts hold the last accepted parameters. Blocks. */
+ba_status ba_lm_solve(ba_plan* p, const ba_opts* o, const ba_lm_opts* lo, double* cams, double* pts,
+                      const double* uv, ba_lm_iter* history, ba_lm_summary* summary, void* stream);
 
 /* Self-test of the FP64 matrix-core tile products the coarse factorization is
  * built from: C += X Y^T (mode 0), C += X^T Y (mode 1), C += X Y (mode 2), with

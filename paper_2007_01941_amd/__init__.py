@@ -16,9 +16,10 @@ import warnings
 import torch
 
 from . import _lib
-from ._lib import BAError, NotConverged, Options
+from ._lib import BAError, LMOptions, NotConverged, Options
 
-__all__ = ["Plan", "Options", "Stats", "lm_step", "LMStep", "BAError", "NotConverged"]
+__all__ = ["Plan", "Options", "LMOptions", "LMIteration", "LMSummary", "Stats", "lm_step", "LMStep",
+           "BAError", "NotConverged"]
 
 
 @dataclasses.dataclass
@@ -39,6 +40,35 @@ def _stats(st: _lib._Stats, status) -> Stats:
     return Stats(st.iters, st.refine_steps, st.levels, list(st.nodes[: max(st.levels, 0)]),
                  st.rel_res, st.t_jacobian_ms, st.t_setup_ms, st.t_solve_ms,
                  status == _lib.BA_OK, bool(st.fallback_fp64))
+
+
+@dataclasses.dataclass
+class LMIteration:
+    cost: float
+    cost_candidate: float
+    model_decrease: float
+    rho: float
+    radius: float
+    step_norm: float
+    accepted: bool
+    pcg_iters: int
+    t_ms: float
+
+
+@dataclasses.dataclass
+class LMSummary:
+    iters: int
+    accepted: int
+    termination: str
+    pcg_iters: int
+    cost0: float
+    cost: float
+    t_ms: float
+    history: list
+
+
+_TERM = {_lib.TERM_MAX_ITERS: "max_iters", _lib.TERM_FUNCTION: "function_tol",
+         _lib.TERM_PARAMETER: "parameter_tol", _lib.TERM_RADIUS: "min_radius"}
 
 
 def _ptr(t):
@@ -121,6 +151,32 @@ class Plan:
         if status == _lib.BA_NOT_CONVERGED:
             warnings.warn("adjoint PCG did not reach rtol within max_iter", NotConverged)
         return g_c, g_p, g_u, _stats(st, status)
+
+    # ---- the Levenberg-Marquardt loop
+    def cost(self, cams, pts, uv):
+        """(1/2 sum |f_o|^2, number of observations with the point at or behind
+        the camera or a non-finite residual)."""
+        self._check_inputs(cams, pts, uv)
+        c = ctypes.c_double()
+        bad = ctypes.c_int64()
+        _lib.check(_lib.LIB.ba_cost(self._h, _ptr(cams), _ptr(pts), _ptr(uv), ctypes.byref(c),
+                                    ctypes.byref(bad), _stream()))
+        return c.value, bad.value
+
+    def lm_solve(self, cams, pts, uv, opts: Options | None = None, lm_opts: LMOptions | None = None):
+        """Levenberg-Marquardt from (cams, pts), which are updated in place.
+        Returns an LMSummary with the per-iteration history."""
+        self._check_inputs(cams, pts, uv)
+        lo = (lm_opts or LMOptions()).to_c()
+        o = self._opts(opts)
+        hist = (_lib._LMIter * max(lo.max_iters, 1))()
+        sm = _lib._LMSummary()
+        _lib.check(_lib.LIB.ba_lm_solve(self._h, ctypes.byref(o), ctypes.byref(lo), _ptr(cams), _ptr(pts),
+                                        _ptr(uv), hist, ctypes.byref(sm), _stream()), allow_not_converged=False)
+        h = [LMIteration(r.cost, r.cost_candidate, r.model_decrease, r.rho, r.radius, r.step_norm,
+                         bool(r.accepted), r.pcg_iters, r.t_ms) for r in hist[: sm.iters]]
+        return LMSummary(sm.iters, sm.accepted, _TERM[sm.termination], sm.pcg_iters, sm.cost0, sm.cost,
+                         sm.t_ms, h)
 
     # ---- stages
     def eval_jacobian(self, cams, pts, uv):

@@ -17,6 +17,8 @@ BA_OK, BA_NOT_CONVERGED = 0, 1
 PC_BLOCK_JACOBI, PC_MULTIGRID = 0, 1
 FP64, MIXED = 0, 1
 OP_AUTO, OP_IMPLICIT, OP_EXPLICIT = 0, 1, 2
+STOP_RESIDUAL, STOP_NASH_SOFER = 0, 1
+TERM_MAX_ITERS, TERM_FUNCTION, TERM_PARAMETER, TERM_RADIUS = 0, 1, 2, 3
 
 
 class BAError(RuntimeError):
@@ -42,7 +44,8 @@ class _Opts(ctypes.Structure):
                 ("min_coarsen_ratio", ctypes.c_double),
                 ("level0_op", ctypes.c_int32), ("freeze_damping_in_grad", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("coarse_shift", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("stop_rule", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("forcing", ctypes.c_double), ("reserved", ctypes.c_int32 * 4)]
 
 
 class _Stats(ctypes.Structure):
@@ -51,6 +54,46 @@ class _Stats(ctypes.Structure):
                 ("rel_res", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
                 ("fallback_fp64", ctypes.c_int32), ("reserved_stats", ctypes.c_int32)]
+
+
+class _LMOpts(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("radius0", ctypes.c_double), ("min_relative_decrease", ctypes.c_double),
+                ("function_tol", ctypes.c_double), ("parameter_tol", ctypes.c_double),
+                ("min_radius", ctypes.c_double), ("max_radius", ctypes.c_double),
+                ("reserved", ctypes.c_double * 2)]
+
+
+class _LMIter(ctypes.Structure):
+    _fields_ = [("cost", ctypes.c_double), ("cost_candidate", ctypes.c_double),
+                ("model_decrease", ctypes.c_double), ("rho", ctypes.c_double),
+                ("radius", ctypes.c_double), ("step_norm", ctypes.c_double),
+                ("accepted", ctypes.c_int32), ("pcg_iters", ctypes.c_int32), ("t_ms", ctypes.c_double)]
+
+
+class _LMSummary(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("accepted", ctypes.c_int32),
+                ("termination", ctypes.c_int32), ("pcg_iters", ctypes.c_int32),
+                ("cost0", ctypes.c_double), ("cost", ctypes.c_double), ("t_ms", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class LMOptions:
+    """Mirror of ba_lm_opts (defaults as in ba_lm_opts_default)."""
+    max_iters: int = 100
+    radius0: float = 1e4
+    min_relative_decrease: float = 1e-3
+    function_tol: float = 1e-6
+    parameter_tol: float = 1e-8
+    min_radius: float = 1e-32
+    max_radius: float = 1e16
+
+    def to_c(self) -> _LMOpts:
+        o = _LMOpts()
+        o.max_iters, o.radius0 = self.max_iters, self.radius0
+        o.min_relative_decrease, o.function_tol = self.min_relative_decrease, self.function_tol
+        o.parameter_tol, o.min_radius, o.max_radius = self.parameter_tol, self.min_radius, self.max_radius
+        return o
 
 
 @dataclasses.dataclass
@@ -75,6 +118,8 @@ class Options:
     freeze_damping_in_grad: bool = False
     check_every: int = 4
     coarse_shift: float = 1e-10
+    stop_rule: str = "residual"      # "residual" | "nash_sofer"
+    forcing: float = 0.1
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -89,6 +134,8 @@ class Options:
         o.freeze_damping_in_grad = int(self.freeze_damping_in_grad)
         o.check_every = self.check_every
         o.coarse_shift = self.coarse_shift
+        o.stop_rule = {"residual": STOP_RESIDUAL, "nash_sofer": STOP_NASH_SOFER}[self.stop_rule]
+        o.forcing = self.forcing
         return o
 
 
@@ -118,6 +165,9 @@ def _load():
         "ba_mg_covisibility": [P, I32, P, P, P, P],
         "ba_mg_level_data": [P, I32, I32, P, P],
         "ba_selftest_tile_mma": [P, P, P, I32, P],
+        "ba_lm_opts_default": [P],
+        "ba_cost": [P, P, P, P, P, P, P],
+        "ba_lm_solve": [P, P, P, P, P, P, P, P, P],
         "ba_status_str": [I32],
         "ba_last_error": [],
     }
@@ -139,7 +189,7 @@ EXPORTED = ["ba_opts_default", "ba_plan_create", "ba_plan_destroy", "ba_plan_byt
             "ba_lm_step_backward", "ba_eval_jacobian", "ba_step_prepare", "ba_step_solve",
             "ba_schur_apply", "ba_schur_offdiag_apply", "ba_precond_apply", "ba_step_blocks", "ba_mg_levels",
             "ba_mg_aggregates", "ba_mg_covisibility", "ba_mg_level_data", "ba_selftest_tile_mma",
-            "ba_status_str", "ba_last_error"]
+            "ba_lm_opts_default", "ba_cost", "ba_lm_solve", "ba_status_str", "ba_last_error"]
 
 
 def check(status: int, allow_not_converged=True):

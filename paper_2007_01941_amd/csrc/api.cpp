@@ -155,6 +155,8 @@ ba_status ba_opts_default(ba_opts* o) {
   o->freeze_damping_in_grad = 0;
   o->check_every = 4;
   o->coarse_shift = 1e-10;
+  o->stop_rule = BA_STOP_RESIDUAL;
+  o->forcing = 0.1;
   return BA_OK;
 }
 
@@ -173,6 +175,9 @@ static void validate_opts(const ba_opts* o) {
   BA_CHECK(o->cheb_hi > o->cheb_lo && o->cheb_lo > 0.0, BA_ERR_ARG, "bad Chebyshev interval");
   BA_CHECK(o->check_every >= 1, BA_ERR_ARG, "check_every must be >= 1");
   BA_CHECK(o->coarse_shift >= 0.0 && o->coarse_shift < 1.0, BA_ERR_ARG, "coarse_shift must be in [0, 1)");
+  BA_CHECK(o->stop_rule == BA_STOP_RESIDUAL || o->stop_rule == BA_STOP_NASH_SOFER, BA_ERR_ARG, "bad stop_rule");
+  BA_CHECK(o->stop_rule != BA_STOP_NASH_SOFER || (o->forcing >= 0.0 && o->precision == BA_FP64), BA_ERR_ARG,
+           "the Nash-Sofer rule needs forcing >= 0 and BA_FP64");
   BA_CHECK(o->precision != BA_MIXED || (o->max_refine >= 1 && o->inner_rtol > 0.0 && o->inner_rtol < 1.0),
            BA_ERR_ARG, "bad refinement options");
 }
@@ -223,6 +228,7 @@ void ba_plan_destroy(ba_plan* p) {
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   delete p->scratch;
   delete p->bwd;
+  delete p->lm;
   delete p;
 }
 
@@ -391,6 +397,44 @@ ba_status ba_lm_step_backward(ba_plan* P, const ba_opts* o, const double* cams, 
   validate_opts(o);
   return backward(P, o, cams, pts, uv, delta_cam, delta_pt, gd_cam, gd_pt, g_cams, g_pts, g_uv, st,
                   (hipStream_t)stream);
+  BA_API_END
+}
+
+ba_status ba_lm_opts_default(ba_lm_opts* lo) {
+  if (!lo) return BA_ERR_ARG;
+  std::memset(lo, 0, sizeof(*lo));
+  lo->max_iters = 100;
+  lo->radius0 = 1e4;
+  lo->min_relative_decrease = 1e-3;
+  lo->function_tol = 1e-6;
+  lo->parameter_tol = 1e-8;
+  lo->min_radius = 1e-32;
+  lo->max_radius = 1e16;
+  return BA_OK;
+}
+
+ba_status ba_cost(ba_plan* P, const double* cams, const double* pts, const double* uv, double* cost,
+                  int64_t* n_invalid, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && cams && pts && uv && cost, BA_ERR_ARG, "null argument");
+  hipStream_t s = (hipStream_t)stream;
+  LmWork& L = lm_work(P);
+  enqueue_cost(P, L, cams, pts, uv, s);
+  read_scalars(L, nullptr, s);
+  *cost = L.h_scal->cost;
+  if (n_invalid) *n_invalid = (int64_t)L.h_scal->invalid;
+  BA_API_END
+}
+
+ba_status ba_lm_solve(ba_plan* P, const ba_opts* o, const ba_lm_opts* lo, double* cams, double* pts,
+                      const double* uv, ba_lm_iter* history, ba_lm_summary* summary, void* stream) {
+  BA_API_BEGIN
+  BA_CHECK(P && lo && cams && pts && uv, BA_ERR_ARG, "null argument");
+  validate_opts(o);
+  BA_CHECK(lo->max_iters >= 0 && lo->radius0 > 0.0 && lo->max_radius >= lo->radius0 && lo->min_radius >= 0.0 &&
+               lo->function_tol >= 0.0 && lo->parameter_tol >= 0.0 && lo->min_relative_decrease >= 0.0,
+           BA_ERR_ARG, "bad LM options");
+  return lm_solve(P, o, lo, cams, pts, uv, history, summary, (hipStream_t)stream);
   BA_API_END
 }
 

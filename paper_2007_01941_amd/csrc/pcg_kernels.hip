@@ -16,6 +16,7 @@ struct PcgScal {
   double bb;      // b . b
   double rr;      // r . r after the latest update
   double pq;
+  double q;       // quadratic model 1/2 x^T S x - x^T b of the current iterate
   int done;       // converged or broke down
   int iters;      // completed iterations
   int flag;       // ERRF_BREAKDOWN on breakdown
@@ -108,6 +109,7 @@ __global__ __launch_bounds__(256) void k_pcg_start(int n, const T* __restrict__ 
   if (!last_block_sum(v, partial, &s->count[3], &tot)) return;
   s->bb = tot;
   s->rr = tot;
+  s->q = 0.0;
   s->done = 0;
   s->iters = 0;
   s->flag = 0;
@@ -139,12 +141,15 @@ __global__ __launch_bounds__(256) void k_pcg_p_Ap(int n_cam, const T* __restrict
   q[(size_t)c * 9 + i] = acc;
 }
 
-// x += alpha p; r -= alpha q; convergence test on r . r.
+// x += alpha p; r -= alpha q; convergence test on r . r. With forcing >= 0
+// the Nash-Sofer rule of Section 2.1 also stops the iteration: the quadratic
+// model falls by alpha_i r_{i-1}.z_{i-1} / 2 in iteration i (Q_0 = 0), and the
+// solve ends once i (Q_i - Q_{i-1}) / Q_i <= forcing.
 template <class T>
 __global__ __launch_bounds__(256) void k_pcg_xr(int n, const T* __restrict__ p, const T* __restrict__ q,
                                                 T* __restrict__ x, T* __restrict__ r,
                                                 double* __restrict__ partial, PcgScal* s,
-                                                double rtol2) {
+                                                double rtol2, double forcing) {
   if (s->done) return;
   const T alpha = (T)s->alpha;
   double v = 0.0;
@@ -158,7 +163,13 @@ __global__ __launch_bounds__(256) void k_pcg_xr(int n, const T* __restrict__ p, 
   if (!last_block_sum(v, partial, &s->count[2], &tot)) return;
   s->rr = tot;
   s->iters += 1;
-  if (tot <= rtol2 * s->bb) s->done = 1;
+  if (tot <= rtol2 * s->bb) {
+    s->done = 1;
+  } else if (forcing >= 0.0) {
+    const double qn = s->q - 0.5 * s->alpha * s->rz;
+    if ((double)s->iters * (qn - s->q) / qn <= forcing) s->done = 1;
+    s->q = qn;
+  }
 }
 
 // z = Sinv r (block Jacobi, 9x9 per camera); one thread per (camera, row).

@@ -63,6 +63,7 @@ struct Level {
 
 struct Scratch;   // defined in api.cpp
 struct Backward;  // defined in backward.cpp
+struct LmWork;    // defined in lm.cpp
 
 }  // namespace bamg
 
@@ -133,4 +134,5 @@ struct ba_plan {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::vector<hipEvent_t> ev_qr, ev_lvl;   // per level: QR done; operator and block inverses ready
   bamg::Backward* bwd = nullptr;
+  bamg::LmWork* lm = nullptr;
 };

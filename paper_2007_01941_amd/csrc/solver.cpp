@@ -704,7 +704,7 @@ struct PcgOut {
 
 template <class T>
 static PcgOut pcg_run(ba_plan* P, const ba_opts* o, const T* b, PcgVecs<T> v, double rtol, int max_iter,
-                      hipStream_t s) {
+                      hipStream_t s, double forcing = -1.0) {
   Scratch& W = *P->scratch;
   PcgScal* sc = W.scal.p;
   const int* done = &sc->done;
@@ -723,7 +723,7 @@ static PcgOut pcg_run(ba_plan* P, const ba_opts* o, const T* b, PcgVecs<T> v, do
     hipLaunchKernelGGL((k_dot<DOT_ALPHA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, W.partial.p,
                        sc, (double*)nullptr);
     hipLaunchKernelGGL((k_pcg_xr<T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, v.x, v.r,
-                       W.partial.p, sc, rtol2);
+                       W.partial.p, sc, rtol2, forcing);
     precond_apply<T>(P, o, v.r, v.z, done, s);
     hipLaunchKernelGGL((k_dot<DOT_BETA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.r, (const T*)v.z, W.partial.p,
                        sc, (double*)nullptr);
@@ -745,12 +745,16 @@ static PcgOut pcg_run(ba_plan* P, const ba_opts* o, const T* b, PcgVecs<T> v, do
 }
 
 // Solve S x = b (b: FP64 device [n_cam*9]) into W.x; returns status and fills stats.
-static ba_status solve_camera_system(ba_plan* P, const ba_opts* o, const double* b, ba_stats* st, hipStream_t s) {
+// forcing >= 0 adds the Nash-Sofer stop rule to the FP64 PCG (the mixed form
+// keeps the residual rule: its inner solves have their own tolerances).
+static ba_status solve_camera_system(ba_plan* P, const ba_opts* o, const double* b, ba_stats* st, hipStream_t s,
+                                     double forcing = -1.0) {
   Scratch& W = *P->scratch;
   const int n = W.n;
   ba_status status = BA_OK;
   if (o->precision == BA_FP64) {
-    PcgOut r = pcg_run<double>(P, o, b, PcgVecs<double>{W.x.p, W.r.p, W.z.p, W.p.p, W.q.p}, o->rtol, o->max_iter, s);
+    PcgOut r = pcg_run<double>(P, o, b, PcgVecs<double>{W.x.p, W.r.p, W.z.p, W.p.p, W.q.p}, o->rtol, o->max_iter, s,
+                               forcing);
     BA_CHECK(!r.breakdown, BA_ERR_NOT_SPD, "PCG breakdown: the operator or preconditioner is not SPD");
     if (st) {
       st->iters = r.iters;
@@ -820,7 +824,8 @@ static ba_status solve(ba_plan* P, const ba_opts* o, double* delta_cam, double* 
   BA_CHECK(o->precision == BA_FP64 || P->have_mixed, BA_ERR_ARG, "the step was prepared without BA_MIXED");
   Timer ts(s);
   Scratch& W = *P->scratch;
-  const ba_status status = solve_camera_system(P, o, P->b.p, st, s);
+  const ba_status status =
+      solve_camera_system(P, o, P->b.p, st, s, o->stop_rule == BA_STOP_NASH_SOFER ? o->forcing : -1.0);
   BA_HIP(hipMemcpyAsync(delta_cam, W.x.p, (size_t)W.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // back-substitution delta_p = C^-1 (-g_p - W^T delta_c)
   hipLaunchKernelGGL(k_recover_tiles, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
@@ -877,3 +882,4 @@ static void level_data(const ba_plan* Pc, int l, int what, double* out, hipStrea
 }  // namespace bamg
 
 #include "backward.cpp"
+#include "lm.cpp"

@@ -48,3 +48,53 @@ def test_host_side_calls_without_gpu():
     h = ctypes.c_void_p()
     st = _lib.LIB.ba_plan_create(0, 0, 0, None, None, ctypes.byref(o), None, ctypes.byref(h))
     assert st == -1 and b"n_cam" in _lib.LIB.ba_last_error()
+
+
+def _c_layout(tmp_path, types):
+    """sizeof and field offsets of header structs, from a C compiler."""
+    import subprocess
+    src = tmp_path / "layout.c"
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "bamg.h"', "int main(void) {"]
+    for t, fields in types.items():
+        lines.append(f'  printf("{t} %zu\\n", sizeof({t}));')
+        for f in fields:
+            lines.append(f'  printf("{t}.{f} %zu\\n", offsetof({t}, {f}));')
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    return {k: int(v) for k, v in (l.split() for l in out.splitlines())}
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbamg.so not built")
+def test_binding_structs_match_header(tmp_path):
+    from paper_2007_01941_amd import _lib
+    pairs = {"ba_opts": _lib._Opts, "ba_stats": _lib._Stats, "ba_lm_opts": _lib._LMOpts,
+             "ba_lm_iter": _lib._LMIter, "ba_lm_summary": _lib._LMSummary}
+    rename = {"lam": "lambda"}
+    types = {t: [rename.get(f[0], f[0]) for f in py._fields_] for t, py in pairs.items()}
+    c = _c_layout(tmp_path, types)
+    for t, py in pairs.items():
+        assert c[t] == ctypes.sizeof(py), t
+        for f in py._fields_:
+            assert c[f"{t}.{rename.get(f[0], f[0])}"] == getattr(py, f[0]).offset, (t, f[0])
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libbamg.so not built")
+def test_lm_host_side_without_gpu():
+    from paper_2007_01941_amd import _lib
+    lo = _lib._LMOpts()
+    assert _lib.LIB.ba_lm_opts_default(ctypes.byref(lo)) == 0
+    assert lo.max_iters == 100 and lo.radius0 == 1e4 and lo.min_relative_decrease == 1e-3
+    py = _lib.LMOptions().to_c()
+    for f, _ in _lib._LMOpts._fields_:
+        if f.startswith("reserved"):
+            continue
+        assert getattr(py, f) == getattr(lo, f), f
+    o = _lib._Opts()
+    _lib.LIB.ba_opts_default(ctypes.byref(o))
+    assert o.stop_rule == _lib.STOP_RESIDUAL and o.forcing == _lib.Options().forcing
+    # null plan: rejected before any device work
+    assert _lib.LIB.ba_lm_solve(None, ctypes.byref(o), ctypes.byref(lo), None, None, None, None, None, None) == -1
+    assert _lib.LIB.ba_cost(None, None, None, None, None, None, None) == -1
