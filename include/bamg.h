@@ -85,7 +85,7 @@ typedef struct {
   int32_t stop_rule;        /* PCG stop rule. BA_STOP_RESIDUAL (default): the rtol test above.
                                BA_STOP_NASH_SOFER: also stop once i (Q_i - Q_{i-1}) / Q_i <= forcing,
                                Q_i = 1/2 dc_i^T S dc_i - dc_i^T b at PCG iteration i (the forcing rule
-                               of Section 2.1 with a constant forcing sequence, Section 4). FP64 only:
+                               of Section 2.1 with a constant forcing sequence, Section 5). FP64 only:
                                BA_MIXED with BA_STOP_NASH_SOFER is BA_ERR_ARG. The backward pass
                                always uses the rtol test. */
   int32_t reserved0;
@@ -235,16 +235,16 @@ ba_status ba_mg_level_data(const ba_plan* p, int32_t level, int32_t what, double
 
 /* ------------------------------------------------------------------------
  * The Levenberg-Marquardt outer loop around the step (Section 2.1), with the
- * solver settings of Section 4: a trust region whose radius starts at 1e4
+ * solver settings of Section 5: a trust region whose radius starts at 1e4
  * (damping D = diag(J^T J) / radius) and, with ba_opts.stop_rule =
  * BA_STOP_NASH_SOFER, a constant forcing sequence for the inner PCG. The paper
  * leaves the radius update to its nonlinear solver; this loop takes the update
  * of Madsen, Nielsen and Tingleff (2004), Section 3.2, in radius form.
  * ---------------------------------------------------------------------- */
 typedef struct {
-  int32_t max_iters;              /* LM iterations, default 100 (Section 4) */
+  int32_t max_iters;              /* LM iterations, default 100 (Section 5) */
   int32_t reserved0;
-  double radius0;                 /* initial trust-region radius, default 1e4 (Section 4) */
+  double radius0;                 /* initial trust-region radius, default 1e4 (Section 5) */
   double min_relative_decrease;   /* accept a step when rho exceeds this, default 1e-3 */
   double function_tol;            /* stop after an accepted step that lowers the cost by at most
                                      function_tol times the previous cost, default 1e-6 */

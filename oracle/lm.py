@@ -1,5 +1,5 @@
 """Oracle: the Levenberg-Marquardt outer loop around the linear solve
-(Section 2.1; the solver settings of Section 4).
+(Section 2.1; the solver settings of Section 5).
 
 Test infrastructure only. The paper runs Ceres' trust-region
 Levenberg-Marquardt with an initial trust-region radius of 1e4 and a constant
@@ -18,6 +18,8 @@ write the outer loop out. Readings taken here:
     angle-axis rotation, and the 3 point coordinates);
   * a candidate with a point at or behind an observing camera, or a non-finite
     cost, counts as a rejected step;
+  * with the Huber loss (oracle.robust) the cost is 1/2 sum rho(|f_o|^2) and the
+    model is that of the reweighted step, 1/2 |f~ + J~ delta|^2;
   * stopping: max_iters iterations; |delta| <= parameter_tol (|x| +
     parameter_tol) before the candidate is evaluated; an accepted step whose
     cost decrease is <= function_tol times the previous cost; radius below
@@ -32,6 +34,7 @@ import numpy as np
 from . import multigrid as mg
 from .camera import project
 from .normal import assemble_J
+from .robust import objective as robust_objective
 from .step import lm_step
 
 TERM_MAX_ITERS, TERM_FUNCTION, TERM_PARAMETER, TERM_RADIUS = 0, 1, 2, 3
@@ -70,12 +73,13 @@ class LMResult:
     history: list
 
 
-def cost_and_valid(cams, pts, obs_cam, obs_pt, uv):
-    """1/2 sum |pi_o - u_o|^2 and whether every point is in front of its observers."""
+def cost_and_valid(cams, pts, obs_cam, obs_pt, uv, loss=None, loss_scale=1.0):
+    """1/2 sum rho(|pi_o - u_o|^2) (rho(s) = s for the squared loss) and whether
+    every point is in front of its observers."""
     pi, xc = project(cams, pts, obs_cam, obs_pt)
     f = pi - uv
     valid = bool(np.all(xc[:, 2] < 0.0))
-    c = 0.5 * float(np.sum(f * f))
+    c = robust_objective(f, loss, loss_scale)
     return c, valid and np.isfinite(c)
 
 
@@ -95,10 +99,11 @@ def radius_update(radius, nu, rho, accepted, o: LMOptions):
 
 
 def solve(cams, pts, obs_cam, obs_pt, uv, o: LMOptions = LMOptions(), method="bj", rtol=1e-8,
-          forcing=None, max_pcg=10000, mg_opts: mg.MGOptions = mg.MGOptions()) -> LMResult:
+          forcing=None, max_pcg=10000, mg_opts: mg.MGOptions = mg.MGOptions(), loss=None,
+          loss_scale=1.0) -> LMResult:
     cams = np.array(cams, dtype=np.float64)
     pts = np.array(pts, dtype=np.float64)
-    cost, valid = cost_and_valid(cams, pts, obs_cam, obs_pt, uv)
+    cost, valid = cost_and_valid(cams, pts, obs_cam, obs_pt, uv, loss, loss_scale)
     if not valid:
         raise ValueError("initial parameters put a point at or behind an observing camera")
     cost0 = cost
@@ -107,7 +112,7 @@ def solve(cams, pts, obs_cam, obs_pt, uv, o: LMOptions = LMOptions(), method="bj
     term = TERM_MAX_ITERS
     for _ in range(o.max_iters):
         st = lm_step(cams, pts, obs_cam, obs_pt, uv, lam=1.0 / radius, method=method, rtol=rtol,
-                     max_iter=max_pcg, opts=mg_opts, forcing=forcing)
+                     max_iter=max_pcg, opts=mg_opts, forcing=forcing, loss=loss, loss_scale=loss_scale)
         dc, dp = st.delta_c, st.delta_p
         step_norm = float(np.sqrt(np.sum(dc * dc) + np.sum(dp * dp)))
         x_norm = float(np.sqrt(np.sum(cams * cams) + np.sum(pts * pts)))
@@ -116,7 +121,7 @@ def solve(cams, pts, obs_cam, obs_pt, uv, o: LMOptions = LMOptions(), method="bj
             break
         md = model_decrease(st.normal, dc, dp)
         cams_new, pts_new = cams + dc, pts + dp
-        cost_new, valid = cost_and_valid(cams_new, pts_new, obs_cam, obs_pt, uv)
+        cost_new, valid = cost_and_valid(cams_new, pts_new, obs_cam, obs_pt, uv, loss, loss_scale)
         if not valid:
             cost_new = np.inf
         rho = (cost - cost_new) / md if (md > 0.0 and valid) else -np.inf

@@ -283,7 +283,7 @@ def pcg(apply_A, apply_M, b, rtol, max_iter=10000, forcing=None):
     """Saad Algorithm 9.1, x0 = 0, stop on ||r|| <= rtol ||b||.
 
     forcing = tau additionally stops on the Nash-Sofer rule of Section 2.1
-    (a constant forcing sequence, Section 4): with the quadratic model
+    (a constant forcing sequence, Section 5): with the quadratic model
     Q_i = 1/2 x_i^T A x_i - x_i^T b of iterate i (Q_0 = 0), stop once
     i (Q_i - Q_{i-1}) / Q_i <= tau. Q_i is evaluated from its definition."""
     x = np.zeros_like(b)

@@ -15,6 +15,7 @@ from . import multigrid as mg
 from .camera import jacobian_blocks, residuals
 from .normal import Normal, cholesky_solve, solve_full
 from .nullspace import camera_nullspace
+from .robust import weights as robust_weights
 
 
 @dataclasses.dataclass
@@ -29,18 +30,24 @@ class StepResult:
     b: np.ndarray = None
 
 
-def normal_for(cams, pts, obs_cam, obs_pt, uv, lam=1e-4, D=None):
+def normal_for(cams, pts, obs_cam, obs_pt, uv, lam=1e-4, D=None, loss=None, loss_scale=1.0):
+    """Normal blocks of the step; with loss="huber" every observation's residual
+    and Jacobian rows are weighted by sqrt(rho'(|f_o|^2)) (oracle.robust)."""
     F, E = jacobian_blocks(cams, pts, obs_cam, obs_pt)
     f = residuals(cams, pts, obs_cam, obs_pt, uv)
+    w = robust_weights(f, loss, loss_scale)
+    F, E, f = F * w[:, None, None], E * w[:, None, None], f * w[:, None]
     return Normal(F, E, f, obs_cam, obs_pt, cams.shape[0], pts.shape[0], lam=lam, D=D)
 
 
 def lm_step(cams, pts, obs_cam, obs_pt, uv, lam=1e-4, method="mg", rtol=1e-8,
-            max_iter=10000, opts: mg.MGOptions = mg.MGOptions(), D=None, forcing=None):
+            max_iter=10000, opts: mg.MGOptions = mg.MGOptions(), D=None, forcing=None, loss=None,
+            loss_scale=1.0):
     """method: 'full' (sparse LU of J^T J + D), 'schur' (dense Cholesky of S),
     'bj' (PCG, point-block-Jacobi), 'mg' (PCG, multigrid V-cycle).
-    forcing: Nash-Sofer tolerance tau for the PCG methods (None: residual rule only)."""
-    nrm = normal_for(cams, pts, obs_cam, obs_pt, uv, lam, D)
+    forcing: Nash-Sofer tolerance tau for the PCG methods (None: residual rule only).
+    loss: None (squared) or "huber" with scale loss_scale (oracle.robust)."""
+    nrm = normal_for(cams, pts, obs_cam, obs_pt, uv, lam, D, loss, loss_scale)
     n_cam = cams.shape[0]
     if method == "full":
         dc, dp = solve_full(nrm)

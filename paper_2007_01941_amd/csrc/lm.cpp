@@ -1,5 +1,5 @@
 // The Levenberg-Marquardt outer loop (Section 2.1) with the solver settings of
-// Section 4: a trust region whose radius starts at 1e4 (damping
+// Section 5: a trust region whose radius starts at 1e4 (damping
 // D = diag(J^T J) / radius) and, optionally, the Nash-Sofer forcing rule for
 // the inner PCG. The paper leaves the radius update to its nonlinear solver;
 // this loop uses the update of Madsen, Nielsen and Tingleff, "Methods for

@@ -1,5 +1,5 @@
 """GPU parity of the Levenberg-Marquardt outer loop and of the Nash-Sofer
-forcing rule (Section 2.1; solver settings of Section 4) against the oracle."""
+forcing rule (Section 2.1; solver settings of Section 5) against the oracle."""
 import numpy as np
 import pytest
 

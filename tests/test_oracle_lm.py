@@ -1,5 +1,5 @@
 """Pins of the oracle's Levenberg-Marquardt outer loop and of the Nash-Sofer
-forcing rule (Section 2.1; solver settings of Section 4)."""
+forcing rule (Section 2.1; solver settings of Section 5)."""
 import os
 
 import numpy as np
