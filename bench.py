@@ -248,22 +248,22 @@ def main():
     # of every nonlinear iteration, as in the paper's timing)
     if not args.no_variants:
         lmres = {}
-        for pc in ("mg", "bj"):
-            for tau in (0.1, 0.01):
-                o = bamg.Options(precond=pc, precision="fp64", rtol=1e-10, max_iter=5000,
-                                 stop_rule="nash_sofer", forcing=tau)
-                c2, p2 = cams.clone(), pts.clone()
-                torch.cuda.synchronize()
-                t0 = time.time()
-                out = plan.lm_solve(c2, p2, uv, opts=o, lm_opts=bamg.LMOptions(max_iters=args.lm_iters))
-                torch.cuda.synchronize()
-                wall = time.time() - t0
-                lmres[f"{pc}_tau{tau}"] = {"s": wall, "lm_iters": out.iters, "accepted": out.accepted,
-                                           "pcg_iters": out.pcg_iters, "termination": out.termination,
-                                           "cost0": out.cost0, "cost": out.cost}
-                log(f"[bench] LM {pc} tau {tau}: {wall * 1e3:.1f} ms, {out.iters} iterations "
-                    f"({out.accepted} accepted, {out.pcg_iters} PCG), cost {out.cost0:.4e} -> {out.cost:.6e}, "
-                    f"stop: {out.termination}")
+        for pc, tau, loss in (("mg", 0.1, "squared"), ("bj", 0.1, "squared"), ("mg", 0.01, "squared"),
+                              ("bj", 0.01, "squared"), ("mg", 0.01, "huber"), ("bj", 0.01, "huber")):
+            o = bamg.Options(precond=pc, precision="fp64", rtol=1e-10, max_iter=5000,
+                             stop_rule="nash_sofer", forcing=tau, loss=loss)
+            c2, p2 = cams.clone(), pts.clone()
+            torch.cuda.synchronize()
+            t0 = time.time()
+            out = plan.lm_solve(c2, p2, uv, opts=o, lm_opts=bamg.LMOptions(max_iters=args.lm_iters))
+            torch.cuda.synchronize()
+            wall = time.time() - t0
+            key = f"{pc}_tau{tau}" + ("_huber" if loss == "huber" else "")
+            lmres[key] = {"s": wall, "lm_iters": out.iters, "accepted": out.accepted, "pcg_iters": out.pcg_iters,
+                          "termination": out.termination, "cost0": out.cost0, "cost": out.cost}
+            log(f"[bench] LM {pc} tau {tau} {loss}: {wall * 1e3:.1f} ms, {out.iters} iterations "
+                f"({out.accepted} accepted, {out.pcg_iters} PCG), cost {out.cost0:.4e} -> {out.cost:.6e}, "
+                f"stop: {out.termination}")
         result["lm_solve"] = lmres
 
     # ---- CPU baseline: the oracle on a bounded sample of the same workload

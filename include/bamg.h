@@ -57,6 +57,7 @@ enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_MULTIGRID = 1 };
 enum { BA_FP64 = 0, BA_MIXED = 1 };
 enum { BA_OP_AUTO = 0, BA_OP_IMPLICIT = 1, BA_OP_EXPLICIT = 2 };
 enum { BA_STOP_RESIDUAL = 0, BA_STOP_NASH_SOFER = 1 };
+enum { BA_LOSS_SQUARED = 0, BA_LOSS_HUBER = 1 };
 
 typedef struct {
   int32_t precond;          /* BA_PC_BLOCK_JACOBI (point block Jacobi, Section 2.2) or BA_PC_MULTIGRID */
@@ -90,7 +91,15 @@ typedef struct {
                                always uses the rtol test. */
   int32_t reserved0;
   double forcing;           /* tau of BA_STOP_NASH_SOFER, >= 0, default 0.1 */
-  int32_t reserved[4];
+  int32_t loss;             /* BA_LOSS_SQUARED (default), or BA_LOSS_HUBER: the robust loss of Section
+                               5.4 on s_o = |f_o|^2, rho(s) = s for s <= a^2 and 2 a sqrt(s) - a^2
+                               above (a = loss_scale; the paper's loss is a = 1). The step then solves
+                               the reweighted system: each observation's residual and Jacobian rows
+                               are multiplied by sqrt(rho'(s_o)) (iteratively reweighted least
+                               squares, rho's own curvature left out). Not supported by
+                               ba_lm_step_backward (BA_ERR_ARG). */
+  int32_t reserved1;
+  double loss_scale;        /* a of BA_LOSS_HUBER, > 0, default 1 (pixels) */
 } ba_opts;
 
 typedef struct {            /* (host) */
@@ -163,7 +172,11 @@ ba_status ba_lm_step_backward(ba_plan* p, const ba_opts* o, const double* cams,
 
 /* Residual and Jacobian blocks per observation (Section 2.1):
  * f [n_obs][2], F [n_obs][2][9] = d pi/d camera, E [n_obs][2][3] = d pi/d point,
- * in the caller's observation order. Any output may be NULL. */
+ * in the caller's observation order, without any robust weighting. Any output
+ * may be NULL. The plan's per-observation buffers are reused, so a step
+ * prepared earlier must be prepared again before ba_step_solve,
+ * ba_schur_apply, ba_schur_offdiag_apply or ba_precond_apply (they return
+ * BA_ERR_ARG until then). */
 ba_status ba_eval_jacobian(ba_plan* p, const double* cams, const double* pts, const double* uv,
                            double* f, double* F, double* E, void* stream);
 
@@ -283,12 +296,13 @@ typedef struct {                  /* (host) */
 /* Defaults listed above. (host) lo. */
 ba_status ba_lm_opts_default(ba_lm_opts* lo);
 
-/* Cost 1/2 sum_o |pi_o - u_o|^2 at (cams, pts) and the number of observations
- * whose point is at or behind the camera (x_cam.z >= 0) or whose residual is
- * not finite (those are left out of the sum). cost, n_invalid (host);
- * n_invalid may be NULL. Blocks until the values are ready. */
-ba_status ba_cost(ba_plan* p, const double* cams, const double* pts, const double* uv, double* cost,
-                  int64_t* n_invalid, void* stream);
+/* Cost 1/2 sum_o rho(|pi_o - u_o|^2) at (cams, pts), rho the loss of o (NULL:
+ * the squared loss, rho(s) = s), and the number of observations whose point is
+ * at or behind the camera (x_cam.z >= 0) or whose residual is not finite
+ * (those are left out of the sum). cost, n_invalid (host); n_invalid may be
+ * NULL. Blocks until the values are ready. */
+ba_status ba_cost(ba_plan* p, const ba_opts* o, const double* cams, const double* pts, const double* uv,
+                  double* cost, int64_t* n_invalid, void* stream);
 
 /* Levenberg-Marquardt from (cams, pts), updated in place [n_cam][9], [n_pt][3].
  * Each iteration solves one step (as ba_lm_step, with lambda = 1 / radius; the

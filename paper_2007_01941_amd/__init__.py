@@ -153,13 +153,14 @@ class Plan:
         return g_c, g_p, g_u, _stats(st, status)
 
     # ---- the Levenberg-Marquardt loop
-    def cost(self, cams, pts, uv):
-        """(1/2 sum |f_o|^2, number of observations with the point at or behind
-        the camera or a non-finite residual)."""
+    def cost(self, cams, pts, uv, opts: Options | None = None):
+        """(1/2 sum rho(|f_o|^2) with the loss of opts, number of observations
+        with the point at or behind the camera or a non-finite residual)."""
         self._check_inputs(cams, pts, uv)
         c = ctypes.c_double()
         bad = ctypes.c_int64()
-        _lib.check(_lib.LIB.ba_cost(self._h, _ptr(cams), _ptr(pts), _ptr(uv), ctypes.byref(c),
+        o = self._opts(opts)
+        _lib.check(_lib.LIB.ba_cost(self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv), ctypes.byref(c),
                                     ctypes.byref(bad), _stream()))
         return c.value, bad.value
 

@@ -18,6 +18,7 @@ PC_BLOCK_JACOBI, PC_MULTIGRID = 0, 1
 FP64, MIXED = 0, 1
 OP_AUTO, OP_IMPLICIT, OP_EXPLICIT = 0, 1, 2
 STOP_RESIDUAL, STOP_NASH_SOFER = 0, 1
+LOSS_SQUARED, LOSS_HUBER = 0, 1
 TERM_MAX_ITERS, TERM_FUNCTION, TERM_PARAMETER, TERM_RADIUS = 0, 1, 2, 3
 
 
@@ -45,7 +46,8 @@ class _Opts(ctypes.Structure):
                 ("level0_op", ctypes.c_int32), ("freeze_damping_in_grad", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("coarse_shift", ctypes.c_double),
                 ("stop_rule", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("forcing", ctypes.c_double), ("reserved", ctypes.c_int32 * 4)]
+                ("forcing", ctypes.c_double), ("loss", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("loss_scale", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -120,6 +122,8 @@ class Options:
     coarse_shift: float = 1e-10
     stop_rule: str = "residual"      # "residual" | "nash_sofer"
     forcing: float = 0.1
+    loss: str = "squared"            # "squared" | "huber"
+    loss_scale: float = 1.0
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -136,6 +140,8 @@ class Options:
         o.coarse_shift = self.coarse_shift
         o.stop_rule = {"residual": STOP_RESIDUAL, "nash_sofer": STOP_NASH_SOFER}[self.stop_rule]
         o.forcing = self.forcing
+        o.loss = {"squared": LOSS_SQUARED, "huber": LOSS_HUBER}[self.loss]
+        o.loss_scale = self.loss_scale
         return o
 
 
@@ -166,7 +172,7 @@ def _load():
         "ba_mg_level_data": [P, I32, I32, P, P],
         "ba_selftest_tile_mma": [P, P, P, I32, P],
         "ba_lm_opts_default": [P],
-        "ba_cost": [P, P, P, P, P, P, P],
+        "ba_cost": [P, P, P, P, P, P, P, P],
         "ba_lm_solve": [P, P, P, P, P, P, P, P, P],
         "ba_status_str": [I32],
         "ba_last_error": [],

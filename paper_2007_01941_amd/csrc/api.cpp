@@ -157,6 +157,8 @@ ba_status ba_opts_default(ba_opts* o) {
   o->coarse_shift = 1e-10;
   o->stop_rule = BA_STOP_RESIDUAL;
   o->forcing = 0.1;
+  o->loss = BA_LOSS_SQUARED;
+  o->loss_scale = 1.0;
   return BA_OK;
 }
 
@@ -178,6 +180,8 @@ static void validate_opts(const ba_opts* o) {
   BA_CHECK(o->stop_rule == BA_STOP_RESIDUAL || o->stop_rule == BA_STOP_NASH_SOFER, BA_ERR_ARG, "bad stop_rule");
   BA_CHECK(o->stop_rule != BA_STOP_NASH_SOFER || (o->forcing >= 0.0 && o->precision == BA_FP64), BA_ERR_ARG,
            "the Nash-Sofer rule needs forcing >= 0 and BA_FP64");
+  BA_CHECK(o->loss == BA_LOSS_SQUARED || o->loss == BA_LOSS_HUBER, BA_ERR_ARG, "bad loss");
+  BA_CHECK(o->loss == BA_LOSS_SQUARED || o->loss_scale > 0.0, BA_ERR_ARG, "loss_scale must be > 0");
   BA_CHECK(o->precision != BA_MIXED || (o->max_refine >= 1 && o->inner_rtol > 0.0 && o->inner_rtol < 1.0),
            BA_ERR_ARG, "bad refinement options");
 }
@@ -247,6 +251,9 @@ ba_status ba_eval_jacobian(ba_plan* P, const double* cams, const double* pts, co
                      P->obs_orig.p, P->n_obs_pad, P->F.p, P->E.p, P->fres.p, f, F, E);
   BA_LAUNCH_CHECK();
   BA_HIP(hipStreamSynchronize(s));
+  // the per-observation planes of a prepared step were overwritten
+  P->prepared = false;
+  P->prepared_mg = false;
   BA_API_END
 }
 
@@ -395,6 +402,7 @@ ba_status ba_lm_step_backward(ba_plan* P, const ba_opts* o, const double* cams, 
   BA_CHECK(P && cams && pts && uv && delta_cam && delta_pt && gd_cam && gd_pt && g_cams && g_pts && g_uv,
            BA_ERR_ARG, "null argument");
   validate_opts(o);
+  BA_CHECK(o->loss == BA_LOSS_SQUARED, BA_ERR_ARG, "the backward pass supports the squared loss only");
   return backward(P, o, cams, pts, uv, delta_cam, delta_pt, gd_cam, gd_pt, g_cams, g_pts, g_uv, st,
                   (hipStream_t)stream);
   BA_API_END
@@ -413,13 +421,14 @@ ba_status ba_lm_opts_default(ba_lm_opts* lo) {
   return BA_OK;
 }
 
-ba_status ba_cost(ba_plan* P, const double* cams, const double* pts, const double* uv, double* cost,
-                  int64_t* n_invalid, void* stream) {
+ba_status ba_cost(ba_plan* P, const ba_opts* o, const double* cams, const double* pts, const double* uv,
+                  double* cost, int64_t* n_invalid, void* stream) {
   BA_API_BEGIN
   BA_CHECK(P && cams && pts && uv && cost, BA_ERR_ARG, "null argument");
+  if (o) validate_opts(o);
   hipStream_t s = (hipStream_t)stream;
   LmWork& L = lm_work(P);
-  enqueue_cost(P, L, cams, pts, uv, s);
+  enqueue_cost(P, L, o, cams, pts, uv, s);
   read_scalars(L, nullptr, s);
   *cost = L.h_scal->cost;
   if (n_invalid) *n_invalid = (int64_t)L.h_scal->invalid;

@@ -8,7 +8,8 @@
 // radius /= max(1/3, 1 - (2 rho - 1)^3) and nu = 2; otherwise radius /= nu
 // and nu *= 2. Parameters are updated additively; a candidate that puts a
 // point at or behind an observing camera, or whose cost is not finite, is
-// rejected like any other failed step.
+// rejected like any other failed step. With the Huber loss the cost is
+// 1/2 sum rho(|f_o|^2) and the model that of the reweighted step.
 namespace bamg {
 
 struct LmWork {
@@ -44,14 +45,16 @@ static LmWork& lm_work(ba_plan* P) {
 }
 
 // Enqueue the cost at (cams, pts) into L.scal (cost, invalid, camflag).
-static void enqueue_cost(ba_plan* P, LmWork& L, const double* cams, const double* pts, const double* uv,
-                         hipStream_t s) {
+static void enqueue_cost(ba_plan* P, LmWork& L, const ba_opts* o, const double* cams, const double* pts,
+                         const double* uv, hipStream_t s) {
+  const int loss = o ? o->loss : BA_LOSS_SQUARED;
+  const double a = o ? o->loss_scale : 1.0;
   Scratch& W = *P->scratch;
   hipLaunchKernelGGL(k_lm_clear, dim3(1), dim3(64), 0, s, L.scal.p);
   hipLaunchKernelGGL(k_campre, dim3(ceil_div(P->n_cam, 256)), dim3(256), 0, s, P->n_cam, cams, L.campre.p,
                      &L.scal.p->camflag);
   hipLaunchKernelGGL(k_lm_cost, dim3(red_grid((int)P->n_obs)), dim3(256), 0, s, (int)P->n_obs, P->obs_cam.p,
-                     P->obs_pt.p, P->pt_orig.p, P->obs_orig.p, L.campre.p, pts, uv, W.partial.p, L.scal.p);
+                     P->obs_pt.p, P->pt_orig.p, P->obs_orig.p, L.campre.p, pts, uv, loss, a, W.partial.p, L.scal.p);
   BA_LAUNCH_CHECK();
 }
 
@@ -77,7 +80,7 @@ static ba_status lm_solve(ba_plan* P, const ba_opts* o_in, const ba_lm_opts* lo,
   ba_lm_summary out{};
   Timer total(s);
 
-  enqueue_cost(P, L, cams, pts, uv, s);
+  enqueue_cost(P, L, o_in, cams, pts, uv, s);
   read_scalars(L, nullptr, s);
   BA_CHECK(!L.h_scal->camflag && std::isfinite(L.h_scal->cost), BA_ERR_GEOMETRY,
            "non-finite initial parameters or cost");
@@ -112,7 +115,7 @@ static ba_status lm_solve(ba_plan* P, const ba_opts* o_in, const ba_lm_opts* lo,
                        (const double*)L.cams_new.p, L.campre.p, &L.scal.p->camflag);
     hipLaunchKernelGGL(k_lm_cost, dim3(red_grid((int)P->n_obs)), dim3(256), 0, s, (int)P->n_obs, P->obs_cam.p,
                        P->obs_pt.p, P->pt_orig.p, P->obs_orig.p, L.campre.p, (const double*)L.pts_new.p, uv,
-                       W.partial.p, L.scal.p);
+                       o.loss, o.loss_scale, W.partial.p, L.scal.p);
     BA_LAUNCH_CHECK();
     read_scalars(L, dots, s);
     const LmScal h = *L.h_scal;

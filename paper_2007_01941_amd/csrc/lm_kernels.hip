@@ -22,15 +22,16 @@ __global__ void k_lm_clear(LmScal* s) {
   }
 }
 
-// Cost at (campre, pts) over the point-major observations. uv is in the
-// caller's observation order (obs_orig maps to it), pts in caller point order.
+// Cost 1/2 sum rho(|f_o|^2) at (campre, pts) over the point-major observations.
+// uv is in the caller's observation order (obs_orig maps to it), pts in caller
+// point order.
 __global__ __launch_bounds__(256) void k_lm_cost(int n_obs, const int32_t* __restrict__ obs_cam,
                                                  const int32_t* __restrict__ obs_pt,
                                                  const int32_t* __restrict__ pt_orig,
                                                  const int32_t* __restrict__ obs_orig,
                                                  const double* __restrict__ campre, const double* __restrict__ pts,
-                                                 const double* __restrict__ uv, double* __restrict__ partial,
-                                                 LmScal* s) {
+                                                 const double* __restrict__ uv, int loss, double loss_a,
+                                                 double* __restrict__ partial, LmScal* s) {
   double v = 0.0;
   unsigned bad = 0;
   for (int o = blockIdx.x * 256 + threadIdx.x; o < n_obs; o += gridDim.x * 256) {
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(256) void k_lm_cost(int n_obs, const int32_t* __res
     double pi[2], Fo[18], Eo[6], z;
     project_jacobian(campre + (size_t)c * 24, X, pi, Fo, Eo, &z);
     const double f0 = pi[0] - uv[2 * i], f1 = pi[1] - uv[2 * i + 1];
-    const double e = f0 * f0 + f1 * f1;
+    const double e = loss_value(f0 * f0 + f1 * f1, loss, loss_a);
     if (z < 0.0 && isfinite(e)) v += e;
     else ++bad;
   }

@@ -155,6 +155,7 @@ __global__ __launch_bounds__(64) void k_explicit_s0(
     const int32_t* __restrict__ row_of, const int32_t* __restrict__ col,
     const int32_t* __restrict__ trans_pos, const int32_t* __restrict__ s0_ptr,
     const int32_t* __restrict__ s0_q, const double* __restrict__ campre, const double* __restrict__ prec,
+    const int32_t* __restrict__ pt_off, const int32_t* __restrict__ obs_cam, const double* __restrict__ wsq,
     double* __restrict__ S) {
   __shared__ double Us[128 * 9];
   __shared__ double Vs[128 * 9];
@@ -171,12 +172,32 @@ __global__ __launch_bounds__(64) void k_explicit_s0(
   for (int base = beg; base < end; base += 64) {
     const int nh = end - base < 64 ? end - base : 64;
     if (lane < nh) {
-      const double* rec = prec + (size_t)s0_q[base + lane] * PREC;
+      const int q = s0_q[base + lane];
+      const double* rec = prec + (size_t)q * PREC;
       const double X[3] = {rec[0], rec[1], rec[2]};
       const double C[9] = {rec[3], rec[4], rec[5], rec[4], rec[6], rec[7], rec[5], rec[7], rec[8]};
       double pi[2], fi[18], ei[6], fj[18], ej[6], z;
       project_jacobian(ci, X, pi, fi, ei, &z);
       project_jacobian(cj, X, pi, fj, ej, &z);
+      if (wsq) {
+        // robust loss: the rows of both observations scaled by their sqrt(rho')
+        double swi = 1.0, swj = 1.0;
+        for (int o = pt_off[q]; o < pt_off[q + 1]; ++o) {
+          const int c = obs_cam[o];
+          if (c == i) swi = wsq[o];
+          if (c == j) swj = wsq[o];
+        }
+#pragma unroll
+        for (int k = 0; k < 18; ++k) {
+          fi[k] *= swi;
+          fj[k] *= swj;
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+          ei[k] *= swi;
+          ej[k] *= swj;
+        }
+      }
       double ec[6];
 #pragma unroll
       for (int r = 0; r < 2; ++r)

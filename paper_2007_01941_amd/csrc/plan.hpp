@@ -120,6 +120,8 @@ struct ba_plan {
   bamg::DBuf<double> b;           // [n_cam][9]
   bamg::DBuf<double> Scc;         // [n_cam][81] block-Jacobi blocks (before inversion)
   bamg::DBuf<double> Sinv;        // [n_cam][81] inverses
+  bamg::DBuf<double> wsq;         // [n_obs_pad] sqrt(rho') per observation (robust loss only)
+  bool robust = false;            // the prepared step uses a robust loss
   bamg::DBuf<float> Sinv32;
   bamg::DBuf<uint32_t> errflag;   // device error bits
   bool prepared = false;

@@ -21,7 +21,7 @@ static size_t plan_bytes(const ba_plan* P) {
   b += P->campre.bytes() + P->F.bytes() + P->E.bytes() + P->fres.bytes() + P->F32.bytes() + P->E32.bytes();
   b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
   b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->Scc.bytes() + P->prec.bytes();
-  b += P->Sinv.bytes() + P->Sinv32.bytes();
+  b += P->Sinv.bytes() + P->Sinv32.bytes() + P->wsq.bytes();
   for (const Level& L : P->levels) {
     b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
     b += L.diag_pos.bytes() + L.trans_pos.bytes() + L.row_of.bytes() + L.agg.bytes() + L.agg_ptr.bytes();
@@ -588,7 +588,7 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   if (P->s0_chunks > 0)
     hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, P->s0_chunk_e.p, P->s0_chunk_beg.p,
                        L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
-                       L0.S.p);
+                       P->pt_off.p, P->obs_cam.p, P->robust ? P->wsq.p : nullptr, L0.S.p);
   L0.explicit_op = level0_explicit(P, o, mixed ? 4 : 8);
   BA_HIP(hipEventRecord(P->ev_lvl[0], s));
   for (int l = 0; l + 1 < nl; ++l) {
@@ -662,6 +662,9 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   P->prepared_mg = false;
   P->inspectable_mg = false;
   P->lambda = o->lambda;
+  P->robust = o->loss != BA_LOSS_SQUARED;
+  if (P->robust && !P->wsq.p) P->wsq.alloc((size_t)P->n_obs_pad);
+  double* wsq = P->robust ? P->wsq.p : nullptr;
   Timer tj(s);
   hipLaunchKernelGGL(k_campre, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
                      P->errflag.p);
@@ -669,11 +672,11 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
                      P->obs_slot.p, P->obs_cam.p, P->obs_orig.p, P->pt_orig.p, P->campre.p, pts, uv, P->n_obs_pad,
                      o->lambda, D, P->n_cam, P->F.p, P->E.p, P->fres.p, mixed ? P->F32.p : nullptr,
                      mixed ? P->E32.p : nullptr, P->Cinv.p, mixed ? P->Cinv32.p : nullptr, P->vgp.p, P->gp.p,
-                     P->Dp.p, P->prec.p, P->n_tiles, P->errflag.p);
+                     P->Dp.p, P->prec.p, P->n_tiles, o->loss, o->loss_scale, wsq, P->errflag.p);
   hipLaunchKernelGGL(k_camera_blocks, dim3(xcd_grid(P->n_cam)), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->cam_q.p,
                      P->n_obs_pad, P->campre.p, P->prec.p, P->fres.p, o->lambda, D, P->A.p,
                      mixed ? P->A32.p : nullptr, P->Dc.p, P->b.p, P->Scc.p, P->Sinv.p,
-                     mixed ? P->Sinv32.p : nullptr, P->n_cam, P->errflag.p);
+                     mixed ? P->Sinv32.p : nullptr, P->n_cam, wsq, P->errflag.p);
   BA_LAUNCH_CHECK();
   check_errflag(P, s, "normal blocks");
   const double tjac = tj.ms();

@@ -33,6 +33,20 @@ __global__ void k_campre(int n_cam, const double* __restrict__ cams, double* __r
   if (!fin) atomicOr(err, ERRF_NONFINITE);
 }
 
+// ---------------------------------------------------------------- robust loss
+
+// The Huber loss of Section 5.4 on s = |f_o|^2 with scale a: rho(s) = s for
+// s <= a^2, 2 a sqrt(s) - a^2 above (the squared loss is rho(s) = s).
+__device__ __forceinline__ double loss_value(double s, int loss, double a) {
+  return (loss == BA_LOSS_HUBER && s > a * a) ? 2.0 * a * sqrt(s) - a * a : s;
+}
+
+// sqrt(rho'(s)): the weight of an observation's residual and Jacobian rows in
+// the reweighted step (rho' = a / sqrt(s) above the threshold).
+__device__ __forceinline__ double loss_sqrt_weight(double s, int loss, double a) {
+  return (loss == BA_LOSS_HUBER && s > a * a) ? sqrt(a / sqrt(s)) : 1.0;
+}
+
 // ---------------------------------------------------------------- residual + Jacobian
 
 // The projection pi = f r p with p = -(x, y)/z, r = 1 + k1|p|^2 + k2|p|^4 and
@@ -182,6 +196,8 @@ __device__ __forceinline__ void finish_point(int q, int qo, const double C[6], c
 // writes f, F, E (and FP32 copies); sums C0 = sum E^T E and g_p = sum E^T f per
 // point in LDS; then per point C_p = C0 + D_p, C_p^-1 (packed), v_p = C_p^-1 g_p,
 // and the point record [X | C_p^-1 | v_p] read by the camera-side kernels.
+// With a robust loss (wsq non-null) every observation's rows are scaled by
+// sqrt(rho'(|f_o|^2)), stored in wsq for the kernels that recompute F_o, E_o.
 __global__ __launch_bounds__(256) void k_jacobian_tiles(
     const int32_t* __restrict__ tile_obs, const int32_t* __restrict__ tile_pt,
     const int32_t* __restrict__ pt_off, const uint32_t* __restrict__ obs_slot,
@@ -191,7 +207,8 @@ __global__ __launch_bounds__(256) void k_jacobian_tiles(
     int64_t stride, double lambda, const double* __restrict__ Dexp, int n_cam, double* __restrict__ F,
     double* __restrict__ E, double* __restrict__ fres, float* __restrict__ F32, float* __restrict__ E32,
     double* __restrict__ Cinv, float* __restrict__ Cinv32, double* __restrict__ vgp,
-    double* __restrict__ gp_out, double* __restrict__ Dp_out, double* __restrict__ prec, int n_tiles, uint32_t* err) {
+    double* __restrict__ gp_out, double* __restrict__ Dp_out, double* __restrict__ prec, int n_tiles,
+    int loss, double loss_a, double* __restrict__ wsq, uint32_t* err) {
   // per-observation contributions [E^T E (6) | E^T f (3)], summed per point in
   // observation order afterwards (deterministic, no atomics)
   __shared__ double part[9][TILE_OBS];
@@ -211,10 +228,21 @@ __global__ __launch_bounds__(256) void k_jacobian_tiles(
     const double X[3] = {pts[(size_t)qo * 3 + 0], pts[(size_t)qo * 3 + 1], pts[(size_t)qo * 3 + 2]};
     double pi[2], Fo[18], e[6], z;
     project_jacobian(campre + (size_t)c * 24, X, pi, Fo, e, &z);
-    const double r0 = pi[0] - uv[(size_t)oo * 2 + 0];
-    const double r1 = pi[1] - uv[(size_t)oo * 2 + 1];
+    double r0 = pi[0] - uv[(size_t)oo * 2 + 0];
+    double r1 = pi[1] - uv[(size_t)oo * 2 + 1];
     if (!(z < 0.0)) atomicOr(err, ERRF_GEOMETRY);
     if (!isfinite(r0) || !isfinite(r1) || !isfinite(X[0] + X[1] + X[2])) atomicOr(err, ERRF_NONFINITE);
+    if (wsq) {
+      // robust loss: the reweighted rows sqrt(rho') [f_o | F_o | E_o]
+      const double sw = loss_sqrt_weight(r0 * r0 + r1 * r1, loss, loss_a);
+      wsq[o] = sw;
+      r0 *= sw;
+      r1 *= sw;
+#pragma unroll
+      for (int k = 0; k < 18; ++k) Fo[k] *= sw;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] *= sw;
+    }
     fres[o] = r0;
     fres[stride + o] = r1;
 #pragma unroll
@@ -293,13 +321,15 @@ __device__ __forceinline__ void block_reduce64(double (&acc)[64], double* red /*
 //   pass 2:  T = sum F^T M F with M = E C_p^-1 E^T (2 x 2), the camera's share
 //            of W C^-1 W^T;  b = sum F^T (E v_p - f) = -g_c + W C^-1 g_p
 //   S_cc = A - T (diagonal block of S) and its inverse (block Jacobi).
+// With a robust loss the recomputed rows are scaled by the stored sqrt(rho').
 __global__ __launch_bounds__(256) void k_camera_blocks(
     const int32_t* __restrict__ cam_off, const int32_t* __restrict__ cam_obs,
     const int32_t* __restrict__ cam_q, int64_t stride, const double* __restrict__ campre,
     const double* __restrict__ prec, const double* __restrict__ fres, double lambda,
     const double* __restrict__ Dexp, double* __restrict__ A_out, float* __restrict__ A32,
     double* __restrict__ Dc_out, double* __restrict__ b_out, double* __restrict__ Scc_out,
-    double* __restrict__ Sinv, float* __restrict__ Sinv32, int n_cam, uint32_t* err) {
+    double* __restrict__ Sinv, float* __restrict__ Sinv32, int n_cam, const double* __restrict__ wsq,
+    uint32_t* err) {
   __shared__ double red[4 * 64];
   __shared__ double S[81];
   __shared__ double Adiag[9], Ad[45];
@@ -316,6 +346,11 @@ __global__ __launch_bounds__(256) void k_camera_blocks(
     const double X[3] = {rec[0], rec[1], rec[2]};
     double pi[2], f[18], e[6], z;
     project_jacobian(cp, X, pi, f, e, &z);
+    if (wsq) {
+      const double sw = wsq[cam_obs[i]];
+#pragma unroll
+      for (int k = 0; k < 18; ++k) f[k] *= sw;
+    }
     int idx = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a)
@@ -355,6 +390,13 @@ __global__ __launch_bounds__(256) void k_camera_blocks(
     const double f0 = fres[o], f1 = fres[stride + o];
     double pi[2], f[18], e[6], z;
     project_jacobian(cp, X, pi, f, e, &z);
+    if (wsq) {
+      const double sw = wsq[o];
+#pragma unroll
+      for (int k = 0; k < 18; ++k) f[k] *= sw;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] *= sw;
+    }
     double ec[6];
 #pragma unroll
     for (int r = 0; r < 2; ++r)

@@ -97,4 +97,5 @@ def test_lm_host_side_without_gpu():
     assert o.stop_rule == _lib.STOP_RESIDUAL and o.forcing == _lib.Options().forcing
     # null plan: rejected before any device work
     assert _lib.LIB.ba_lm_solve(None, ctypes.byref(o), ctypes.byref(lo), None, None, None, None, None, None) == -1
-    assert _lib.LIB.ba_cost(None, None, None, None, None, None, None) == -1
+    assert _lib.LIB.ba_cost(None, None, None, None, None, None, None, None) == -1
+    assert o.loss == _lib.LOSS_SQUARED and o.loss_scale == _lib.Options().loss_scale == 1.0
