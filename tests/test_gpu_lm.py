@@ -165,3 +165,4 @@ def test_lm_solve_multigrid_nash_sofer():
             assert h.cost_candidate < prev
             prev = h.cost_candidate
     assert out.pcg_iters <= 10 * out.iters
+
