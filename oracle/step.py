@@ -11,6 +11,7 @@ import dataclasses
 import numpy as np
 
 from . import aggregation as agglib
+from . import cluster as cl
 from . import multigrid as mg
 from .camera import jacobian_blocks, residuals
 from .normal import Normal, cholesky_solve, solve_full
@@ -44,7 +45,8 @@ def lm_step(cams, pts, obs_cam, obs_pt, uv, lam=1e-4, method="mg", rtol=1e-8,
             max_iter=10000, opts: mg.MGOptions = mg.MGOptions(), D=None, forcing=None, loss=None,
             loss_scale=1.0):
     """method: 'full' (sparse LU of J^T J + D), 'schur' (dense Cholesky of S),
-    'bj' (PCG, point-block-Jacobi), 'mg' (PCG, multigrid V-cycle).
+    'bj' (PCG, point-block-Jacobi), 'mg' (PCG, multigrid V-cycle), 'cj' (PCG,
+    visibility-based block Jacobi over camera clusters, oracle.cluster).
     forcing: Nash-Sofer tolerance tau for the PCG methods (None: residual rule only).
     loss: None (squared) or "huber" with scale loss_scale (oracle.robust)."""
     nrm = normal_for(cams, pts, obs_cam, obs_pt, uv, lam, D, loss, loss_scale)
@@ -64,6 +66,12 @@ def lm_step(cams, pts, obs_cam, obs_pt, uv, lam=1e-4, method="mg", rtol=1e-8,
     elif method == "mg":
         levels = hierarchy_for(nrm, cams, obs_cam, obs_pt, opts)
         M = lambda r: mg.vcycle(levels, r, opts)
+    elif method == "cj":
+        W0 = agglib.covisibility(obs_cam, obs_pt, n_cam, nrm.n_pt)
+        agg, n_agg = cl.clusters(W0, opts)
+        blocks = cl.cluster_inverses(nrm.S_sparse(), agg, n_agg)
+        M = lambda r: cl.apply(blocks, r)
+        levels = None
     else:
         raise ValueError(method)
     res = mg.pcg(nrm.S_apply, M, b, rtol, max_iter, forcing)
