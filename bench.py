@@ -213,6 +213,7 @@ def main():
     if not args.no_variants:
         var = {}
         for name, opts in (("bj_fp64", bamg.Options(precond="bj", precision="fp64", **base)),
+                           ("cj_fp64", bamg.Options(precond="cj", precision="fp64", **base)),
                            ("mg_mixed", bamg.Options(precond="mg", precision="mixed", **base)),
                            ("bj_mixed", bamg.Options(precond="bj", precision="mixed", **base))):
             vms, _, vst, vdc, _ = run(opts, max(2, args.steps // 2), 1)

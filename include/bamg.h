@@ -53,14 +53,18 @@ typedef enum {
   BA_ERR_LIMIT = -8       /* a documented size limit was exceeded */
 } ba_status;
 
-enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_MULTIGRID = 1 };
+enum { BA_PC_BLOCK_JACOBI = 0, BA_PC_MULTIGRID = 1, BA_PC_CLUSTER_JACOBI = 2 };
 enum { BA_FP64 = 0, BA_MIXED = 1 };
 enum { BA_OP_AUTO = 0, BA_OP_IMPLICIT = 1, BA_OP_EXPLICIT = 2 };
 enum { BA_STOP_RESIDUAL = 0, BA_STOP_NASH_SOFER = 1 };
 enum { BA_LOSS_SQUARED = 0, BA_LOSS_HUBER = 1 };
 
 typedef struct {
-  int32_t precond;          /* BA_PC_BLOCK_JACOBI (point block Jacobi, Section 2.2) or BA_PC_MULTIGRID */
+  int32_t precond;          /* BA_PC_BLOCK_JACOBI (point block Jacobi, Section 2.2), BA_PC_MULTIGRID,
+                               or BA_PC_CLUSTER_JACOBI: visibility-based block Jacobi (Section 2.2), the
+                               inverse of S's block-diagonal part over clusters of cameras, the
+                               clusters being the level-0 aggregates of Algorithm 2 (single cameras
+                               when the hierarchy has one level); BA_FP64 only */
   int32_t precision;        /* BA_FP64, or BA_MIXED: FP32 Schur product and preconditioner inside
                                FP64 iterative refinement; C^-1, coarse solve and outer residual FP64 */
   double lambda;            /* D = lambda * diag(J^T J) (Marquardt damping), default 1e-4 */

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbamg.so")
 
 BA_OK, BA_NOT_CONVERGED = 0, 1
-PC_BLOCK_JACOBI, PC_MULTIGRID = 0, 1
+PC_BLOCK_JACOBI, PC_MULTIGRID, PC_CLUSTER_JACOBI = 0, 1, 2
 FP64, MIXED = 0, 1
 OP_AUTO, OP_IMPLICIT, OP_EXPLICIT = 0, 1, 2
 STOP_RESIDUAL, STOP_NASH_SOFER = 0, 1
@@ -101,7 +101,7 @@ class LMOptions:
 @dataclasses.dataclass
 class Options:
     """Mirror of ba_opts (defaults as in ba_opts_default)."""
-    precond: str = "mg"              # "mg" | "bj"
+    precond: str = "mg"              # "mg" | "bj" | "cj" (visibility-based block Jacobi)
     precision: str = "fp64"          # "fp64" | "mixed"
     lam: float = 1e-4
     rtol: float = 1e-6
@@ -127,7 +127,7 @@ class Options:
 
     def to_c(self) -> _Opts:
         o = _Opts()
-        o.precond = {"bj": PC_BLOCK_JACOBI, "mg": PC_MULTIGRID}[self.precond]
+        o.precond = {"bj": PC_BLOCK_JACOBI, "mg": PC_MULTIGRID, "cj": PC_CLUSTER_JACOBI}[self.precond]
         o.precision = {"fp64": FP64, "mixed": MIXED}[self.precision]
         o.lam, o.rtol, o.max_iter = self.lam, self.rtol, self.max_iter
         o.max_refine, o.inner_rtol = self.max_refine, self.inner_rtol

@@ -164,7 +164,10 @@ ba_status ba_opts_default(ba_opts* o) {
 
 static void validate_opts(const ba_opts* o) {
   BA_CHECK(o, BA_ERR_ARG, "opts is NULL");
-  BA_CHECK(o->precond == BA_PC_BLOCK_JACOBI || o->precond == BA_PC_MULTIGRID, BA_ERR_ARG, "bad precond");
+  BA_CHECK(o->precond == BA_PC_BLOCK_JACOBI || o->precond == BA_PC_MULTIGRID ||
+               o->precond == BA_PC_CLUSTER_JACOBI, BA_ERR_ARG, "bad precond");
+  BA_CHECK(o->precond != BA_PC_CLUSTER_JACOBI || o->precision == BA_FP64, BA_ERR_ARG,
+           "the cluster preconditioner is FP64 only");
   BA_CHECK(o->precision == BA_FP64 || o->precision == BA_MIXED, BA_ERR_ARG, "bad precision");
   BA_CHECK(o->lambda >= 0.0, BA_ERR_ARG, "lambda must be >= 0");
   BA_CHECK(o->rtol > 0.0 && o->rtol < 1.0, BA_ERR_ARG, "rtol must be in (0, 1)");
@@ -254,6 +257,7 @@ ba_status ba_eval_jacobian(ba_plan* P, const double* cams, const double* pts, co
   // the per-observation planes of a prepared step were overwritten
   P->prepared = false;
   P->prepared_mg = false;
+  P->prepared_cj = false;
   BA_API_END
 }
 

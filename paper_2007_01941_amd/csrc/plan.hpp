@@ -122,6 +122,10 @@ struct ba_plan {
   bamg::DBuf<double> Sinv;        // [n_cam][81] inverses
   bamg::DBuf<double> wsq;         // [n_obs_pad] sqrt(rho') per observation (robust loss only)
   bool robust = false;            // the prepared step uses a robust loss
+  bamg::DBuf<int64_t> cj_off;     // [n_agg0 + 1] offsets of the cluster blocks in cj_inv
+  bamg::DBuf<double> cj_inv;      // cluster blocks of S, inverted (visibility-based block Jacobi)
+  int cj_max_n = 0;               // largest cluster block dimension (9 x members)
+  bool prepared_cj = false;
   bamg::DBuf<float> Sinv32;
   bamg::DBuf<uint32_t> errflag;   // device error bits
   bool prepared = false;

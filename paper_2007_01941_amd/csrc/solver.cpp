@@ -21,7 +21,7 @@ static size_t plan_bytes(const ba_plan* P) {
   b += P->campre.bytes() + P->F.bytes() + P->E.bytes() + P->fres.bytes() + P->F32.bytes() + P->E32.bytes();
   b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
   b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->Scc.bytes() + P->prec.bytes();
-  b += P->Sinv.bytes() + P->Sinv32.bytes() + P->wsq.bytes();
+  b += P->Sinv.bytes() + P->Sinv32.bytes() + P->wsq.bytes() + P->cj_off.bytes() + P->cj_inv.bytes();
   for (const Level& L : P->levels) {
     b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
     b += L.diag_pos.bytes() + L.trans_pos.bytes() + L.row_of.bytes() + L.agg.bytes() + L.agg_ptr.bytes();
@@ -406,9 +406,26 @@ template <class T> static const T* A_of(const ba_plan* P);
 template <> const double* A_of<double>(const ba_plan* P) { return P->A.p; }
 template <> const float* A_of<float>(const ba_plan* P) { return P->A32.p; }
 
+static void cluster_apply(ba_plan* P, const double* r, double* z, const int* done, hipStream_t s) {
+  BA_CHECK(P->prepared_cj, BA_ERR_ARG, "the step was prepared without the cluster preconditioner");
+  if (P->levels.size() < 2) {   // no aggregates: every camera is its own cluster
+    hipLaunchKernelGGL((k_bj_apply<double>), dim3(grid_of<double>(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam,
+                       P->Sinv.p, r, z, done);
+    return;
+  }
+  const Level& L0 = P->levels[0];
+  hipLaunchKernelGGL(k_cj_apply, dim3(L0.n_agg), dim3(256), (size_t)P->cj_max_n * sizeof(double), s,
+                     L0.agg_ptr.p, L0.agg_mem.p, P->cj_off.p, P->cj_inv.p, r, z, done);
+}
+static void cluster_apply(ba_plan*, const float*, float*, const int*, hipStream_t) {
+  BA_CHECK(false, BA_ERR_ARG, "the cluster preconditioner is FP64 only");
+}
+
 template <class T>
 static void precond_apply(ba_plan* P, const ba_opts* o, const T* r, T* z, const int* done, hipStream_t s) {
-  if (o->precond == BA_PC_BLOCK_JACOBI) {
+  if (o->precond == BA_PC_CLUSTER_JACOBI) {
+    cluster_apply(P, r, z, done, s);
+  } else if (o->precond == BA_PC_BLOCK_JACOBI) {
     hipLaunchKernelGGL((k_bj_apply<T>), dim3(grid_of<T>(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam,
                        Sinv_of<T>(P), r, z, done);
   } else {
@@ -564,6 +581,52 @@ static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
 //          level's dense inverse;
 //   side2: the Lanczos estimate of every level once its operator and block
 //          inverses are ready.
+// Explicit level-0 Schur complement (Section 3.6): diagonal blocks S_cc, then
+// the off-diagonal blocks from the shared points of every camera pair.
+static void assemble_s0(ba_plan* P, hipStream_t s) {
+  Level& L0 = P->levels[0];
+  hipLaunchKernelGGL(k_s0_init, dim3(grid_of<double>(L0.nnz * 81)), dim3(256), 0, s, (int64_t)L0.nnz * 81,
+                     L0.row_of.p, L0.col.p, P->Scc.p, L0.S.p);
+  if (P->s0_chunks > 0)
+    hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, P->s0_chunk_e.p, P->s0_chunk_beg.p,
+                       L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
+                       P->pt_off.p, P->obs_cam.p, P->robust ? P->wsq.p : nullptr, L0.S.p);
+}
+
+// Visibility-based block Jacobi: the level-0 aggregates' blocks of S, inverted.
+// With a single-level hierarchy every camera is its own cluster and the
+// block-Jacobi inverses of the step are used as they are.
+static void cluster_setup(ba_plan* P, hipStream_t s) {
+  if (P->levels.size() < 2) {
+    P->prepared_cj = true;
+    return;
+  }
+  Level& L0 = P->levels[0];
+  if (!P->cj_off.p) {
+    const std::vector<int32_t> aptr = L0.agg_ptr.download(s);
+    std::vector<int64_t> off((size_t)L0.n_agg + 1, 0);
+    int max_n = 0;
+    for (int a = 0; a < L0.n_agg; ++a) {
+      const int n = 9 * (aptr[a + 1] - aptr[a]);
+      off[a + 1] = off[a] + (int64_t)n * n;
+      max_n = std::max(max_n, n);
+    }
+    BA_CHECK((size_t)max_n * sizeof(double) <= 64 * 1024, BA_ERR_LIMIT,
+             "a cluster of %d cameras exceeds the cluster kernel's LDS", max_n / 9);
+    P->cj_off.upload(off, s);
+    P->cj_inv.alloc((size_t)off.back());
+    P->cj_max_n = max_n;
+  }
+  assemble_s0(P, s);
+  hipLaunchKernelGGL(k_cj_gather, dim3(L0.n_agg), dim3(256), 0, s, L0.agg_ptr.p, L0.agg_mem.p, L0.rowptr32.p,
+                     L0.col.p, L0.S.p, P->cj_off.p, P->cj_inv.p);
+  hipLaunchKernelGGL(k_cj_invert, dim3(L0.n_agg), dim3(256), 0, s, L0.agg_ptr.p, P->cj_off.p, P->cj_inv.p,
+                     P->errflag.p);
+  BA_LAUNCH_CHECK();
+  check_errflag(P, s, "cluster blocks");
+  P->prepared_cj = true;
+}
+
 static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixed, hipStream_t s) {
   const int nl = (int)P->levels.size();
   Level& L0 = P->levels[0];
@@ -583,12 +646,7 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   }
   // ---- s: explicit level-0 S (Section 3.6), needed for the Galerkin product
   // and, when cheaper than the implicit form, for smoothing
-  hipLaunchKernelGGL(k_s0_init, dim3(grid_of<double>(L0.nnz * 81)), dim3(256), 0, s, (int64_t)L0.nnz * 81,
-                     L0.row_of.p, L0.col.p, P->Scc.p, L0.S.p);
-  if (P->s0_chunks > 0)
-    hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, P->s0_chunk_e.p, P->s0_chunk_beg.p,
-                       L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
-                       P->pt_off.p, P->obs_cam.p, P->robust ? P->wsq.p : nullptr, L0.S.p);
+  assemble_s0(P, s);
   L0.explicit_op = level0_explicit(P, o, mixed ? 4 : 8);
   BA_HIP(hipEventRecord(P->ev_lvl[0], s));
   for (int l = 0; l + 1 < nl; ++l) {
@@ -660,6 +718,7 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   if (mixed) ensure_mixed(P);
   P->prepared = false;
   P->prepared_mg = false;
+  P->prepared_cj = false;
   P->inspectable_mg = false;
   P->lambda = o->lambda;
   P->robust = o->loss != BA_LOSS_SQUARED;
@@ -684,6 +743,7 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   P->prepared = true;
   Timer ts(s);
   if (o->precond == BA_PC_MULTIGRID) mg_setup(P, o, cams, mixed, s);
+  if (o->precond == BA_PC_CLUSTER_JACOBI) cluster_setup(P, s);
   const double tset = ts.ms();
   if (st) {
     st->t_jacobian_ms = tjac;
@@ -822,8 +882,10 @@ static ba_status solve_camera_system(ba_plan* P, const ba_opts* o, const double*
 
 static ba_status solve(ba_plan* P, const ba_opts* o, double* delta_cam, double* delta_pt, ba_stats* st,
                        hipStream_t s) {
-  BA_CHECK(o->precond == BA_PC_BLOCK_JACOBI || P->prepared_mg, BA_ERR_ARG,
+  BA_CHECK(o->precond != BA_PC_MULTIGRID || P->prepared_mg, BA_ERR_ARG,
            "the step was prepared without the multigrid preconditioner");
+  BA_CHECK(o->precond != BA_PC_CLUSTER_JACOBI || P->prepared_cj, BA_ERR_ARG,
+           "the step was prepared without the cluster preconditioner");
   BA_CHECK(o->precision == BA_FP64 || P->have_mixed, BA_ERR_ARG, "the step was prepared without BA_MIXED");
   Timer ts(s);
   Scratch& W = *P->scratch;
