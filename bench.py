@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--lm-iters", type=int, default=100, help="iteration cap of the LM loop runs (100 as in the paper)")
+    ap.add_argument("--scaling", default=None,
+                    help="comma-separated k: run the scaling study on k x k city grids with a sine-wave "
+                         "long-range error instead of the benchmark (one JSON line per run, then a summary)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -108,6 +111,10 @@ def main():
 
     import paper_2007_01941_amd as bamg
     from scenes import make_scene
+
+    if args.scaling:
+        run_scaling([int(k) for k in args.scaling.split(",")], max(1, args.steps), args.warmup)
+        return
 
     dev = torch.device("cuda:0")
     t0 = time.time()
@@ -271,6 +278,54 @@ def main():
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(sc, st.iters)
     print(json.dumps(result), flush=True)
+
+
+def run_scaling(ks, steps, warmup):
+    """Solve time and PCG iterations of one LM linear solve (FP64, rtol 1e-6) with
+    multigrid, point block Jacobi and visibility-based block Jacobi on k x k
+    city grids whose initial values carry a sine-wave long-range error (the
+    growing-diameter problems of the paper's scaling experiment); the summary
+    fits time ~ n_cam^e per preconditioner."""
+    import numpy as np
+    import torch
+    import paper_2007_01941_amd as bamg
+    from scenes import make_scene
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for k in ks:
+        sc = make_scene(f"sine{k}")
+        T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+        cams, pts, uv = T(sc.cams), T(sc.pts), T(sc.uv)
+        plan = bamg.Plan(sc.n_cam, sc.n_pt, T(sc.obs_cam, torch.int32), T(sc.obs_pt, torch.int32),
+                         bamg.Options(precond="mg"))
+        for pc in ("mg", "bj", "cj"):
+            o = bamg.Options(precond=pc, rtol=1e-6, max_iter=50000)
+            for _ in range(warmup):
+                plan.lm_step(cams, pts, uv, opts=o)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                _, _, st = plan.lm_step(cams, pts, uv, opts=o)
+            e1.record()
+            torch.cuda.synchronize()
+            row = {"k": k, "n_cam": sc.n_cam, "n_pt": sc.n_pt, "n_obs": sc.n_obs, "precond": pc,
+                   "ms_per_solve": e0.elapsed_time(e1) / steps, "pcg_iters": st.iters, "levels": st.nodes,
+                   "rel_res": st.rel_res}
+            rows.append(row)
+            log(f"[scaling] k={k} n_cam={sc.n_cam} {pc}: {row['ms_per_solve']:.2f} ms, {st.iters} iterations")
+            print(json.dumps(row), flush=True)
+        del plan
+    fits = {}
+    for pc in ("mg", "bj", "cj"):
+        r = [x for x in rows if x["precond"] == pc]
+        if len(r) >= 2:
+            n = np.log([x["n_cam"] for x in r])
+            fits[pc] = {"time_exponent": float(np.polyfit(n, np.log([x["ms_per_solve"] for x in r]), 1)[0]),
+                        "iteration_exponent": float(np.polyfit(n, np.log([x["pcg_iters"] for x in r]), 1)[0])}
+    print(json.dumps({"metric": "scaling: LM linear solve to rtol 1e-6 vs n_cam, sine-wave long-range error",
+                      "fits": fits}), flush=True)
 
 
 def subsample_points(sc, every):

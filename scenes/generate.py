@@ -88,8 +88,19 @@ def _forward_project(Rm, t, f, k1, k2, X):
     return s[:, None] * p, xc[:, 2]
 
 
-def _finish(name, rng, centers, dirs, X, obs_cam, obs_pt, sigma_px=1.0, sigma_par=1e-2):
-    """Truth parameters, noise-free and noisy pixels, perturbed initial values."""
+def sine_field(P, amplitude, wavelength):
+    """Long-range displacement of world positions P [n, 3]: x moves with
+    sin(2 pi y / wavelength), y with sin(2 pi x / wavelength), both by
+    `amplitude` metres. Smooth, so nearby cameras and points move together."""
+    w = 2.0 * np.pi / wavelength
+    return amplitude * np.column_stack([np.sin(w * P[:, 1]), np.sin(w * P[:, 0]), np.zeros(P.shape[0])])
+
+
+def _finish(name, rng, centers, dirs, X, obs_cam, obs_pt, sigma_px=1.0, sigma_par=1e-2, long_range=None):
+    """Truth parameters, noise-free and noisy pixels, perturbed initial values.
+    long_range = (amplitude, wavelength) adds sine_field to the initial camera
+    centres and points on top of the local noise (the long-range error of the
+    paper's scaling experiment); it draws no random numbers."""
     n_cam = centers.shape[0]
     Rm = look_rotations(dirs)
     omega = Rotation.from_matrix(Rm).as_rotvec()
@@ -114,10 +125,14 @@ def _finish(name, rng, centers, dirs, X, obs_cam, obs_pt, sigma_px=1.0, sigma_pa
     dR = Rotation.from_rotvec(rng.normal(0.0, sigma_par, (n_cam, 3))).as_matrix()
     Rp = np.einsum("nij,njk->nik", dR, Rm)
     cp = centers + rng.normal(0.0, sigma_par, centers.shape)
+    if long_range is not None:
+        cp = cp + sine_field(centers, *long_range)
     cams = np.column_stack([Rotation.from_matrix(Rp).as_rotvec(), -np.einsum("nij,nj->ni", Rp, cp),
                             f + rng.normal(0.0, sigma_par, n_cam), k1 + rng.normal(0.0, sigma_par, n_cam),
                             k2 + rng.normal(0.0, sigma_par, n_cam)])
     pts = X + rng.normal(0.0, sigma_par, X.shape)
+    if long_range is not None:
+        pts = pts + sine_field(X, *long_range)
     return Scene(name, cams_true, X.copy(), cams, pts, obs_cam, obs_pt, uv, uv_clean)
 
 
@@ -234,7 +249,7 @@ def _choose_observers(rng, centers, dirs, X, k_want, max_dist, half_angle_deg, k
 
 
 def city_scene(n_cam, n_pt, n_blocks, block_len, k_sampler, seed, name,
-               revisit_every=None, max_dist=15.0, half_angle_deg=60.0, chunk=1_000_000):
+               revisit_every=None, max_dist=15.0, half_angle_deg=60.0, chunk=1_000_000, long_range=None):
     """Street-view scene: a walk on a street grid and facade points at +-2 m
     lateral, 0-8 m high, each observed by its k nearest viewing cameras."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -261,7 +276,16 @@ def city_scene(n_cam, n_pt, n_blocks, block_len, k_sampler, seed, name,
         X_all.append(X[ok])
         have += ok.size
     X = np.concatenate(X_all)
-    return _finish(name, rng, centers, dirs, X, np.concatenate(oc_all), np.concatenate(op_all))
+    return _finish(name, rng, centers, dirs, X, np.concatenate(oc_all), np.concatenate(op_all),
+                   long_range=long_range)
+
+
+def scaling_scene(k):
+    """City of k x k blocks of 10 m with 5 cameras and 1,500 points per block and
+    a sine-wave long-range error (0.5 m over one city width): the growing-
+    diameter problems of the paper's scaling experiment (Section 5.2)."""
+    return city_scene(5 * k * k, 1500 * k * k, k, 10.0, _k_geometric, seed=100 + k, name=f"sine{k}",
+                      long_range=(0.5, 10.0 * k))
 
 
 def path_scene(n_cam, n_pt, seed, name, spacing=0.5, chunk=2_000_000):
@@ -345,6 +369,7 @@ def make_scene(name: str) -> Scene:
     city200   200 cameras / 20k points, 6x6 grid of 10 m blocks (seed 11)
     path500   500 cameras / 40k points (seed 12)
     city1k    1,000 cameras / 150k points, 12x12 grid (seed 13)
+    sine<k>   k x k city blocks with a sine-wave long-range error (scaling_scene)
     """
     if name == "ring64":
         return ring_scene(64, 4000, 8, seed=0, name=name)
@@ -363,6 +388,8 @@ def make_scene(name: str) -> Scene:
         return city_scene(1000, 150_000, 12, 10.0, _k_geometric, seed=13, name=name)
     if name == "path500":
         return path_scene(500, 40_000, seed=12, name=name)
+    if name.startswith("sine") and name[4:].isdigit():
+        return scaling_scene(int(name[4:]))
     raise KeyError(name)
 
 
