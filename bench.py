@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--scaling", default=None,
                     help="comma-separated k: run the scaling study on k x k city grids with a sine-wave "
                          "long-range error instead of the benchmark (one JSON line per run, then a summary)")
+    ap.add_argument("--scaling-lm", action="store_true",
+                    help="with --scaling: time whole LM runs (Nash-Sofer tau 0.01) to a common final cost")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -113,7 +115,11 @@ def main():
     from scenes import make_scene
 
     if args.scaling:
-        run_scaling([int(k) for k in args.scaling.split(",")], max(1, args.steps), args.warmup)
+        ks = [int(k) for k in args.scaling.split(",")]
+        if args.scaling_lm:
+            run_scaling_lm(ks, args.lm_iters)
+        else:
+            run_scaling(ks, max(1, args.steps), args.warmup)
         return
 
     dev = torch.device("cuda:0")
@@ -325,6 +331,61 @@ def run_scaling(ks, steps, warmup):
             fits[pc] = {"time_exponent": float(np.polyfit(n, np.log([x["ms_per_solve"] for x in r]), 1)[0]),
                         "iteration_exponent": float(np.polyfit(n, np.log([x["pcg_iters"] for x in r]), 1)[0])}
     print(json.dumps({"metric": "scaling: LM linear solve to rtol 1e-6 vs n_cam, sine-wave long-range error",
+                      "fits": fits}), flush=True)
+
+
+def run_scaling_lm(ks, lm_iters):
+    """The paper's scaling protocol: for each k x k sine-noise city grid, LM runs
+    (Nash-Sofer rule, constant tau = 0.01, FP64) with multigrid, point block
+    Jacobi and visibility-based block Jacobi; every run is timed up to the
+    first iteration at which its cost reaches the highest final cost of the
+    three (so that all end at the same objective), summing the iterations'
+    times (linear solve, setup, cost evaluations)."""
+    import numpy as np
+    import torch
+    import paper_2007_01941_amd as bamg
+    from scenes import make_scene
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for k in ks:
+        sc = make_scene(f"sine{k}")
+        T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+        cams, pts, uv = T(sc.cams), T(sc.pts), T(sc.uv)
+        plan = bamg.Plan(sc.n_cam, sc.n_pt, T(sc.obs_cam, torch.int32), T(sc.obs_pt, torch.int32),
+                         bamg.Options(precond="mg"))
+        runs = {}
+        for pc in ("mg", "bj", "cj"):
+            o = bamg.Options(precond=pc, rtol=1e-10, max_iter=5000, stop_rule="nash_sofer", forcing=0.01)
+            out = plan.lm_solve(cams.clone(), pts.clone(), uv, opts=o, lm_opts=bamg.LMOptions(max_iters=lm_iters))
+            runs[pc] = out
+        target = max(r.cost for r in runs.values())
+        for pc, out in runs.items():
+            t, cost, n_it, pcg = 0.0, out.cost0, 0, 0
+            for h in out.history:
+                t += h.t_ms
+                pcg += h.pcg_iters
+                n_it += 1
+                if h.accepted:
+                    cost = h.cost_candidate
+                if cost <= target * (1 + 1e-12):
+                    break
+            row = {"k": k, "n_cam": sc.n_cam, "n_obs": sc.n_obs, "precond": pc, "ms_to_target": t,
+                   "lm_iters_to_target": n_it, "pcg_iters_to_target": pcg, "target_cost": target,
+                   "cost0": out.cost0, "final_cost": out.cost, "lm_iters": out.iters}
+            rows.append(row)
+            log(f"[scaling-lm] k={k} n_cam={sc.n_cam} {pc}: {t:.1f} ms to cost {target:.6e} "
+                f"({n_it} LM iterations, {pcg} PCG)")
+            print(json.dumps(row), flush=True)
+        del plan
+    fits = {}
+    for pc in ("mg", "bj", "cj"):
+        r = [x for x in rows if x["precond"] == pc]
+        if len(r) >= 2:
+            n = np.log([x["n_cam"] for x in r])
+            fits[pc] = {"time_exponent": float(np.polyfit(n, np.log([x["ms_to_target"] for x in r]), 1)[0]),
+                        "pcg_exponent": float(np.polyfit(n, np.log([x["pcg_iters_to_target"] for x in r]), 1)[0])}
+    print(json.dumps({"metric": "scaling: LM time to a common cost vs n_cam (tau 0.01, sine-wave long-range error)",
                       "fits": fits}), flush=True)
 
 
