@@ -318,7 +318,8 @@ ba_status ba_cost(ba_plan* p, const ba_opts* o, const double* cams, const double
  * summary (host) may be NULL. Returns BA_OK whatever the termination rule.
  * Errors: BA_ERR_GEOMETRY if the initial parameters put a point at or behind
  * an observing camera or are not finite; the errors of ba_lm_step. After an
- * error cams and pts hold the last accepted parameters. Blocks. */
+ * error cams and pts hold the last accepted parameters. Afterwards the plan
+ * holds the step prepared at the last iteration's parameters. Blocks. */
 ba_status ba_lm_solve(ba_plan* p, const ba_opts* o, const ba_lm_opts* lo, double* cams, double* pts,
                       const double* uv, ba_lm_iter* history, ba_lm_summary* summary, void* stream);
 
