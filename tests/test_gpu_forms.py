@@ -32,7 +32,7 @@ def test_mixed_precision_refinement(pc):
 
 
 def test_mixed_inner_solve_alone_is_fp32_accurate():
-    # one refinement step: the FP32 solve alone (error vs the oracle ~ u_32 cond)
+    # one refinement step: the FP32 solve alone reaches its inner tolerance
     sc = scene("city200")
     plan, opts = plan_for(sc, precond="mg", precision="mixed", rtol=1e-3, inner_rtol=1e-3,
                           max_refine=1, coarse_max_nodes=16)
