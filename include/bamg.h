@@ -313,7 +313,9 @@ ba_status ba_cost(ba_plan* p, const ba_opts* o, const double* cams, const double
  * lambda of o is ignored and D = lambda diag(J^T J)), evaluates the model
  * decrease and the candidate's cost, accepts or rejects the candidate and
  * updates the radius. Updates are additive on every parameter. An inner solve
- * that reaches max_iter is used as it stands. o: the linear solver's options;
+ * that reaches max_iter is used as it stands; a step whose damped system is
+ * not numerically positive definite (BA_ERR_NOT_SPD from the step) is a failed
+ * step, recorded with an infinite candidate cost and handled as a rejection. o: the linear solver's options;
  * lo: the loop's. history (host) holds lo->max_iters entries or is NULL;
  * summary (host) may be NULL. Returns BA_OK whatever the termination rule.
  * Errors: BA_ERR_GEOMETRY if the initial parameters put a point at or behind

@@ -20,6 +20,8 @@ write the outer loop out. Readings taken here:
     cost, counts as a rejected step;
   * with the Huber loss (oracle.robust) the cost is 1/2 sum rho(|f_o|^2) and the
     model is that of the reweighted step, 1/2 |f~ + J~ delta|^2;
+  * a step whose damped system is not numerically positive definite (PCG or
+    a factorization breaks down) is a failed step, handled like a rejection;
   * stopping: max_iters iterations; |delta| <= parameter_tol (|x| +
     parameter_tol) before the candidate is evaluated; an accepted step whose
     cost decrease is <= function_tol times the previous cost; radius below
@@ -111,8 +113,16 @@ def solve(cams, pts, obs_cam, obs_pt, uv, o: LMOptions = LMOptions(), method="bj
     hist = []
     term = TERM_MAX_ITERS
     for _ in range(o.max_iters):
-        st = lm_step(cams, pts, obs_cam, obs_pt, uv, lam=1.0 / radius, method=method, rtol=rtol,
-                     max_iter=max_pcg, opts=mg_opts, forcing=forcing, loss=loss, loss_scale=loss_scale)
+        try:
+            st = lm_step(cams, pts, obs_cam, obs_pt, uv, lam=1.0 / radius, method=method, rtol=rtol,
+                         max_iter=max_pcg, opts=mg_opts, forcing=forcing, loss=loss, loss_scale=loss_scale)
+        except np.linalg.LinAlgError:
+            hist.append(Iteration(cost, np.inf, 0.0, -np.inf, radius, 0.0, False, 0))
+            radius, nu = radius_update(radius, nu, -np.inf, False, o)
+            if radius < o.min_radius:
+                term = TERM_RADIUS
+                break
+            continue
         dc, dp = st.delta_c, st.delta_p
         step_norm = float(np.sqrt(np.sum(dc * dc) + np.sum(dp * dp)))
         x_norm = float(np.sqrt(np.sum(cams * cams) + np.sum(pts * pts)))

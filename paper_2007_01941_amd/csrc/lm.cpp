@@ -8,7 +8,8 @@
 // radius /= max(1/3, 1 - (2 rho - 1)^3) and nu = 2; otherwise radius /= nu
 // and nu *= 2. Parameters are updated additively; a candidate that puts a
 // point at or behind an observing camera, or whose cost is not finite, is
-// rejected like any other failed step. With the Huber loss the cost is
+// rejected like any other failed step, and so is a step whose damped system is
+// not numerically positive definite. With the Huber loss the cost is
 // 1/2 sum rho(|f_o|^2) and the model that of the reweighted step.
 namespace bamg {
 
@@ -95,8 +96,39 @@ static ba_status lm_solve(ba_plan* P, const ba_opts* o_in, const ba_lm_opts* lo,
     Timer ti(s);
     o.lambda = 1.0 / radius;
     ba_stats st{};
-    prepare(P, &o, cams, pts, uv, nullptr, &st, s);
-    const ba_status ss = solve(P, &o, L.dc.p, L.dp.p, &st, s);
+    ba_status ss = BA_OK;
+    try {
+      prepare(P, &o, cams, pts, uv, nullptr, &st, s);
+      ss = solve(P, &o, L.dc.p, L.dp.p, &st, s);
+    } catch (const Fail& f) {
+      if (f.st != BA_ERR_NOT_SPD) throw;
+      // the damped system is not numerically positive definite (a block, the
+      // coarse matrix or PCG broke down): a failed step, handled as a rejection.
+      // Drain the plan's streams before the next attempt reuses its buffers.
+      BA_HIP(hipStreamSynchronize(P->side));
+      BA_HIP(hipStreamSynchronize(P->side2));
+      BA_HIP(hipMemsetAsync(P->errflag.p, 0, sizeof(uint32_t), s));
+      BA_HIP(hipStreamSynchronize(s));
+      if (history) {
+        ba_lm_iter& r = history[out.iters];
+        r = ba_lm_iter{};
+        r.cost = cost;
+        r.cost_candidate = INFINITY;
+        r.rho = -INFINITY;
+        r.radius = radius;
+        r.pcg_iters = st.iters;
+        r.t_ms = ti.ms();
+      }
+      out.iters += 1;
+      out.pcg_iters += st.iters;
+      radius /= nu;
+      nu *= 2.0;
+      if (radius < lo->min_radius) {
+        out.termination = BA_TERM_RADIUS;
+        break;
+      }
+      continue;
+    }
     if (ss < 0) return ss;   // cams, pts hold the last accepted parameters
     // predicted decrease, candidate, its cost and the norms of the stopping rules
     hipLaunchKernelGGL(k_lm_clear, dim3(1), dim3(64), 0, s, L.scal.p);

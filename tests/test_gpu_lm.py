@@ -166,3 +166,26 @@ def test_lm_solve_multigrid_nash_sofer():
             prev = h.cost_candidate
     assert out.pcg_iters <= 10 * out.iters
 
+
+
+def test_lm_survives_breakdowns():
+    """With almost no damping (radius 1e12) from the hard start the damped
+    systems can stop being numerically positive definite; the loop treats such
+    a step as failed (infinite candidate cost, radius shrunk as for a
+    rejection) instead of aborting, and still lowers the cost."""
+    import paper_2007_01941_amd as bamg
+    sc = tiny_scene(10, 150, seed=21, k_min=2, k_max=5)
+    pts0 = hard_start(sc)
+    plan, opts = plan_for(sc, precond="bj", rtol=1e-10, max_iter=5000)
+    cams, pts, uv = inputs(sc, pts=pts0)
+    out = plan.lm_solve(cams, pts, uv, opts=opts, lm_opts=bamg.LMOptions(max_iters=25, radius0=1e12))
+    failed = [i for i, h in enumerate(out.history) if np.isinf(h.cost_candidate) and h.step_norm == 0.0]
+    print(f"[gpu] lm breakdowns at iterations {failed}; cost {out.cost0:.3e} -> {out.cost:.3e}", flush=True)
+    nu = 2.0
+    for a, b in zip(out.history, out.history[1:]):
+        if a.accepted:
+            nu = 2.0
+        else:
+            assert b.radius == a.radius / nu
+            nu *= 2.0
+    assert out.cost < out.cost0

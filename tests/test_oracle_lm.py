@@ -149,3 +149,19 @@ def test_lm_rejections_shrink_radius():
             assert b.radius == a.radius / nu
             nu *= 2.0
     assert any(i.accepted for i in h) and res.cost < res.cost0
+
+
+def test_lm_breakdown_is_a_failed_step():
+    """With almost no damping (radius 1e12) the hard start's first damped systems
+    are not numerically positive definite and PCG breaks down: the loop counts
+    those as failed steps, shrinks the radius as for a rejection and goes on to
+    lower the cost."""
+    sc = _scene()
+    pts = hard_start(sc)
+    res = lm.solve(sc.cams, pts, sc.obs_cam, sc.obs_pt, sc.uv, lm.LMOptions(max_iters=25, radius0=1e12),
+                   method="bj", rtol=1e-10)
+    failed = [i for i, h in enumerate(res.history) if np.isinf(h.cost_candidate) and h.step_norm == 0.0]
+    assert failed, "expected at least one breakdown"
+    i = failed[0]
+    assert res.history[i + 1].radius == res.history[i].radius / 2.0
+    assert res.cost < res.cost0
