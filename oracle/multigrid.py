@@ -61,6 +61,8 @@ class MGOptions:
     max_levels: int = 12
     min_ratio: float = 0.9
     coarse_shift: float = 1e-10
+    smooth_prolongator: bool = False   # Section 3.5's comparison: P = (I - w D^-1 S) P_tent
+    smooth_omega: float = 4.0 / 3.0    # w = smooth_omega / lambda_max(D^-1 S)
 
 
 def splitmix64(x):
@@ -215,6 +217,16 @@ class Level:
     cscale: np.ndarray = None  # coarsest level: equilibration diag(S)^-1/2
 
 
+def smoothed_prolongator(S, bs, P, lmax, omega_scale=4.0 / 3.0):
+    """Smoothed aggregation (Section 3.5 weighs it against the unsmoothed P the
+    paper uses): one damped block-Jacobi sweep applied to the tentative
+    prolongator, P_s = (I - w D^-1 S) P with D the bs x bs block diagonal of S
+    and w = omega_scale / lambda_max(D^-1 S) (the usual 4/3 of Vanek et al.)."""
+    Dinv = np.linalg.inv(block_diagonal(S, bs))
+    Dinv_s = sp.block_diag(list(Dinv), format="csr")
+    return (P - (omega_scale / lmax) * (Dinv_s @ (S @ P))).tocsr()
+
+
 def build_hierarchy(S0, K0, W0, opts: MGOptions = MGOptions(), apply_S0=None):
     """Set up the whole hierarchy from the explicit level-0 Schur complement S0,
     the camera near-nullspace rows K0 [n_cam, 9, 16] and the covisibility W0."""
@@ -231,6 +243,10 @@ def build_hierarchy(S0, K0, W0, opts: MGOptions = MGOptions(), apply_S0=None):
         if n_agg > opts.min_ratio * n:
             break
         Pb, Kc, P = tentative_prolongator(K, agg, n_agg)
+        if opts.smooth_prolongator:
+            Dinv_l = np.linalg.inv(block_diagonal(S, bs))
+            lm = lanczos_lmax(lambda x, S=S: S @ x, Dinv_l, lanczos_start(S.shape[0], l), opts.lanczos_steps)
+            P = smoothed_prolongator(S, bs, sp.csr_matrix(P), lm, opts.smooth_omega)
         lev.agg, lev.n_agg, lev.Pb, lev.Kc, lev.P = agg, n_agg, Pb, Kc, P
         S = (P.T @ S @ P).tocsr()
         W = agglib.coarse_covisibility(W, agg, n_agg)
