@@ -99,3 +99,19 @@ def test_lm_host_side_without_gpu():
     assert _lib.LIB.ba_lm_solve(None, ctypes.byref(o), ctypes.byref(lo), None, None, None, None, None, None) == -1
     assert _lib.LIB.ba_cost(None, None, None, None, None, None, None, None) == -1
     assert o.loss == _lib.LOSS_SQUARED and o.loss_scale == _lib.Options().loss_scale == 1.0
+
+
+def test_build_entry_does_not_load_the_library_first():
+    """build() must work on a tree without libbamg.so: neither importing the
+    entry module nor loading the build script imports the package (which loads
+    the library)."""
+    import subprocess
+    import sys
+    code = ("import sys, os, importlib.util\n"
+            "import __graft_entry__\n"
+            "spec = importlib.util.spec_from_file_location('_b', os.path.join('paper_2007_01941_amd', 'build.py'))\n"
+            "m = importlib.util.module_from_spec(spec); spec.loader.exec_module(m)\n"
+            "assert hasattr(m, 'build')\n"
+            "assert 'paper_2007_01941_amd' not in sys.modules, 'package imported'\n")
+    p = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert p.returncode == 0, p.stderr
