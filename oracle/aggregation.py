@@ -5,16 +5,20 @@ Test infrastructure only.
 Strength of connection (Section 3.2): with v_k the 0/1 vector of points seen by
 camera k, G_ij = v_i^T v_j / (|v_i| |v_j|) for i != j and 0 on the diagonal.
 Writing W = V V^T (integer covisibility counts; W_ii = |v_i|^2),
-G_ij = W_ij / sqrt(W_ii W_jj). Both sides of the method evaluate this in
-IEEE FP64 exactly as written: float(W_ij) / sqrt(float(W_ii) * float(W_jj)).
+G_ij = W_ij / sqrt(W_ii W_jj). The aggregation only ever compares two strengths
+of the same row, G_ij against G_ik, and since every quantity is a positive
+integer that comparison is decided exactly, without rounding:
+    G_ij > G_ik  <=>  W_ij^2 W_kk > W_ik^2 W_jj
+(Python integers, so no product overflows).
 
-Aggregation (Algorithm 2): visit nodes in index order; an unaggregated node i
-scans its neighbours j by decreasing G_ij and either forms a new aggregate
-{i, j} with the first unaggregated one, or joins the first neighbour's
-aggregate holding fewer than 20 nodes.
+Aggregation (Algorithm 2): nodes are visited in index order. A node that is
+not yet in an aggregate is grouped with the strongest neighbour it may join:
+a neighbour that is itself ungrouped starts a new aggregate of the two, a
+grouped one lends its aggregate if that still holds fewer than 20 nodes.
 
 Readings where the paper is silent:
-  * equal strengths: the lower neighbour index comes first;
+  * equal strengths (equal as exact rationals): the lower neighbour index comes
+    first;
   * "20 dofs" is read as 20 nodes (cameras at level 0, aggregates above);
   * a node still unaggregated after the sweep joins the aggregate of its first
     neighbour in the same order, even past the cap; a node with no neighbour
@@ -25,6 +29,8 @@ Readings where the paper is silent:
     and G_{l+1} is computed from W_{l+1} by the same formula.
 """
 from __future__ import annotations
+
+import functools
 
 import numpy as np
 import scipy.sparse as sp
@@ -42,21 +48,38 @@ def covisibility(obs_cam, obs_pt, n_cam, n_pt):
 
 
 def strength(W_ij, W_ii, W_jj):
+    """G_ij as a float (for reports; the ordering never uses it)."""
     return float(W_ij) / np.sqrt(float(W_ii) * float(W_jj))
+
+
+def compare_strength(w_ij, w_jj, w_ik, w_kk):
+    """Sign of G_ij - G_ik for two neighbours j, k of the same row i, exactly:
+    +1, 0 or -1 as W_ij^2 W_kk is greater than, equal to or less than
+    W_ik^2 W_jj (W_ii cancels)."""
+    lhs = int(w_ij) * int(w_ij) * int(w_kk)
+    rhs = int(w_ik) * int(w_ik) * int(w_jj)
+    return (lhs > rhs) - (lhs < rhs)
 
 
 def neighbour_order(W):
     """For every node, its neighbours sorted by decreasing G (ties: lower index)."""
     W = W.tocsr()
     W.sort_indices()
-    diag = W.diagonal()
+    diag = [int(d) for d in W.diagonal()]
     orders = []
     for i in range(W.shape[0]):
         cols = W.indices[W.indptr[i]:W.indptr[i + 1]]
         vals = W.data[W.indptr[i]:W.indptr[i + 1]]
-        nb = [(-strength(v, diag[i], diag[j]), int(j)) for j, v in zip(cols, vals) if j != i]
-        nb.sort()
-        orders.append([j for _, j in nb])
+        nb = [(int(j), int(v)) for j, v in zip(cols, vals) if j != i]
+
+        def before(a, b):          # a = (j, W_ij), b = (k, W_ik): -1 if a comes first
+            c = compare_strength(a[1], diag[a[0]], b[1], diag[b[0]])
+            if c != 0:
+                return -c
+            return (a[0] > b[0]) - (a[0] < b[0])
+
+        nb.sort(key=functools.cmp_to_key(before))
+        orders.append([j for j, _ in nb])
     return orders
 
 
@@ -65,30 +88,33 @@ def aggregate(W, cap=AGG_CAP):
     n = W.shape[0]
     orders = neighbour_order(W)
     agg = -np.ones(n, dtype=np.int64)
-    size = []
+    members = []                   # members[a]: nodes of aggregate a, in joining order
+
+    def partner(i):
+        """Strongest neighbour that i may be grouped with (None if every neighbour
+        sits in a full aggregate): ungrouped, or in an aggregate below the cap."""
+        return next((j for j in orders[i] if agg[j] < 0 or len(members[agg[j]]) < cap), None)
+
     for i in range(n):
-        if agg[i] != -1:
+        if agg[i] >= 0:
             continue
-        for j in orders[i]:
-            if agg[j] == -1:
-                agg[i] = agg[j] = len(size)
-                size.append(2)
-                break
-            if size[agg[j]] < cap:
-                agg[i] = agg[j]
-                size[agg[j]] += 1
-                break
-    for i in range(n):
-        if agg[i] != -1:
-            continue
-        if orders[i]:
-            a = agg[orders[i][0]]
-            agg[i] = a
-            size[a] += 1
+        j = partner(i)
+        if j is None:
+            continue                # a leftover, placed after the sweep
+        if agg[j] < 0:
+            agg[i] = agg[j] = len(members)
+            members.append([i, j])
         else:
-            agg[i] = len(size)
-            size.append(1)
-    return agg, len(size)
+            agg[i] = agg[j]
+            members[agg[j]].append(i)
+    for i in np.nonzero(agg < 0)[0]:
+        if orders[i]:               # every neighbour of a leftover is grouped by now
+            agg[i] = agg[orders[i][0]]
+            members[agg[i]].append(int(i))
+        else:
+            agg[i] = len(members)
+            members.append([int(i)])
+    return agg, len(members)
 
 
 def coarse_covisibility(W, agg, n_agg):

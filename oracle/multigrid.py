@@ -25,12 +25,12 @@ Readings where the paper is silent:
     published by Steele, Lea and Flood (2014) and Vigna: z = x + 0x9E3779B97F4A7C15,
     z = (z ^ z>>30) * 0xBF58476D1CE4E5B9, z = (z ^ z>>27) * 0x94D049BB133111EB,
     out = z ^ z>>31.
-  * Coarsest direct solve: Cholesky of the equilibrated matrix s S s + eps I
-    with s = diag(S)^-1/2 and eps = 1e-10 (the same inverse up to eps; the
-    shift is insurance that keeps the factorization positive definite when
-    the coarsest Galerkin operator is nearly singular to FP64 rounding, which
-    happens when some observation is nearly perpendicular to its camera's
-    axis and blows up its Jacobian).
+  * Coarsest direct solve (Algorithm 1's direct solve): Cholesky of the
+    equilibrated matrix s S s with s = diag(S)^-1/2, which has the same inverse
+    as S up to the scaling and keeps the factor accurate when the camera
+    parameters live on very different scales. No shift is added: the coarsest
+    operator P^T S P is symmetric positive definite whenever S is (P has
+    orthonormal columns on disjoint rows).
   * Coarsening stops when a level has <= 128 nodes, or the next level would keep
     more than 0.9 of the nodes, or at 12 levels.
   * PCG: Saad Algorithm 9.1 from x0 = 0; stop when ||r||_2 <= rtol ||b||_2 on the
@@ -60,7 +60,6 @@ class MGOptions:
     coarse_max_nodes: int = 128
     max_levels: int = 12
     min_ratio: float = 0.9
-    coarse_shift: float = 1e-10
     smooth_prolongator: bool = False   # Section 3.5's comparison: P = (I - w D^-1 S) P_tent
     smooth_omega: float = 4.0 / 3.0    # w = smooth_omega / lambda_max(D^-1 S)
 
@@ -259,7 +258,7 @@ def build_hierarchy(S0, K0, W0, opts: MGOptions = MGOptions(), apply_S0=None):
             # parameters live on very different scales)
             lev.cscale = 1.0 / np.sqrt(np.diag(Sd))
             Ss = Sd * lev.cscale[:, None] * lev.cscale[None, :]
-            lev.chol = np.linalg.cholesky(Ss + opts.coarse_shift * np.eye(Ss.shape[0]))
+            lev.chol = np.linalg.cholesky(Ss)
         else:
             Dblk = block_diagonal(lev.S, lev.bs)
             lev.Dinv = np.linalg.inv(Dblk)
