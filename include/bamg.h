@@ -84,9 +84,11 @@ typedef struct {
                                bytes moved per application; PCG itself always uses the implicit form */
   int32_t freeze_damping_in_grad; /* backward: 1 = treat D as a constant, 0 = differentiate D(x) */
   int32_t check_every;      /* PCG: read the convergence flag back every N iterations, default 4 */
-  double coarse_shift;      /* coarsest direct solve factors s S s + coarse_shift I with
-                               s = diag(S)^-1/2, default 1e-10 (keeps it SPD where the
-                               coarsest operator is singular to FP64 rounding) */
+  int32_t deterministic;    /* 1: no floating-point atomics anywhere in the step, so that two runs on
+                               the same inputs give bitwise equal results (the Schur product stores
+                               per-(tile, camera) sums and adds them in tile order; the explicit
+                               level-0 S sums each camera pair's shared points in one wave);
+                               slightly slower. Default 0 */
   int32_t stop_rule;        /* PCG stop rule. BA_STOP_RESIDUAL (default): the rtol test above.
                                BA_STOP_NASH_SOFER: also stop once i (Q_i - Q_{i-1}) / Q_i <= forcing,
                                Q_i = 1/2 dc_i^T S dc_i - dc_i^T b at PCG iteration i (the forcing rule
@@ -160,14 +162,17 @@ ba_status ba_lm_step(ba_plan* p, const ba_opts* o, const double* cams, const dou
  * Schur system and preconditioner as the forward step, residual and Jacobian
  * recomputed):  dL/du_o = J_o mu_o and
  * dL/dx = -J^T J mu - sum_o sum_r Hess(pi_{o,r}) w_{o,r} (the second-order terms
- * of the reprojection; with freeze_damping_in_grad = 0 the damping's own
- * dependence on x is included). delta_cam/delta_pt are the forward outputs.
+ * of the reprojection; with D = lambda diag(J^T J) and freeze_damping_in_grad = 0
+ * the damping's own dependence on x is included). D: the explicit damping
+ * diagonal the forward step was taken with (as in ba_lm_step; a constant, so it
+ * contributes no term of its own), or NULL for D = lambda diag(J^T J).
+ * delta_cam/delta_pt are the forward outputs.
  * Outputs g_cams [n_cam][9], g_pts [n_pt][3], g_uv [n_obs][2]. */
 ba_status ba_lm_step_backward(ba_plan* p, const ba_opts* o, const double* cams,
-                              const double* pts, const double* uv, const double* delta_cam,
-                              const double* delta_pt, const double* gd_cam, const double* gd_pt,
-                              double* g_cams, double* g_pts, double* g_uv, ba_stats* st,
-                              void* stream);
+                              const double* pts, const double* uv, const double* D,
+                              const double* delta_cam, const double* delta_pt, const double* gd_cam,
+                              const double* gd_pt, double* g_cams, double* g_pts, double* g_uv,
+                              ba_stats* st, void* stream);
 
 /* ------------------------------------------------------------------------
  * Stage-level entry points. ba_lm_step = ba_step_prepare + ba_step_solve.

@@ -136,18 +136,21 @@ class Plan:
             warnings.warn("PCG did not reach rtol within max_iter", NotConverged)
         return dc, dp, _stats(st, status)
 
-    def backward(self, cams, pts, uv, delta_cam, delta_pt, gd_cam, gd_pt, opts=None):
-        """Gradients (g_cams, g_pts, g_uv) of L(delta) given dL/d delta."""
+    def backward(self, cams, pts, uv, delta_cam, delta_pt, gd_cam, gd_pt, opts=None, D=None):
+        """Gradients (g_cams, g_pts, g_uv) of L(delta) given dL/d delta. D: the
+        explicit damping diagonal of the forward step, if it had one."""
         self._check_inputs(cams, pts, uv)
         g_c = torch.empty_like(cams)
         g_p = torch.empty_like(pts)
         g_u = torch.empty_like(uv)
         st = _lib._Stats()
         o = self._opts(opts)
+        if D is not None:
+            D = _f64(D, (9 * self.n_cam + 3 * self.n_pt,), "D")
         status = _lib.check(_lib.LIB.ba_lm_step_backward(
-            self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv), _ptr(delta_cam.contiguous()),
-            _ptr(delta_pt.contiguous()), _ptr(gd_cam.contiguous()), _ptr(gd_pt.contiguous()),
-            _ptr(g_c), _ptr(g_p), _ptr(g_u), ctypes.byref(st), _stream()))
+            self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv), _ptr(D) if D is not None else None,
+            _ptr(delta_cam.contiguous()), _ptr(delta_pt.contiguous()), _ptr(gd_cam.contiguous()),
+            _ptr(gd_pt.contiguous()), _ptr(g_c), _ptr(g_p), _ptr(g_u), ctypes.byref(st), _stream()))
         if status == _lib.BA_NOT_CONVERGED:
             warnings.warn("adjoint PCG did not reach rtol within max_iter", NotConverged)
         return g_c, g_p, g_u, _stats(st, status)
@@ -287,13 +290,17 @@ def lm_step(cams, pts, uv, obs_cam, obs_pt, opts: Options | None = None, D=None)
 
 
 class LMStep(torch.autograd.Function):
-    """delta = LMStep.apply(cams, pts, uv, plan, opts): differentiable LM step;
-    backward runs the adjoint solve with the same Schur system and preconditioner."""
+    """delta = LMStep.apply(cams, pts, uv, plan, opts, D): differentiable LM
+    step; backward runs the adjoint solve with the same Schur system and
+    preconditioner. D (optional) is an explicit damping diagonal, held
+    constant (no gradient flows to it)."""
 
     @staticmethod
-    def forward(ctx, cams, pts, uv, plan: Plan, opts: Options | None = None):
-        dc, dp, st = plan.lm_step(cams.detach(), pts.detach(), uv.detach(), opts=opts)
+    def forward(ctx, cams, pts, uv, plan: Plan, opts: Options | None = None, D=None):
+        dc, dp, st = plan.lm_step(cams.detach(), pts.detach(), uv.detach(), opts=opts,
+                                  D=None if D is None else D.detach())
         ctx.plan, ctx.opts = plan, opts
+        ctx.D = None if D is None else D.detach()
         ctx.save_for_backward(cams, pts, uv, dc, dp)
         return dc, dp
 
@@ -305,5 +312,5 @@ class LMStep(torch.autograd.Function):
         if gdp is None:
             gdp = torch.zeros_like(dp)
         g_c, g_p, g_u, _ = ctx.plan.backward(cams.detach(), pts.detach(), uv.detach(), dc, dp,
-                                             gdc.contiguous(), gdp.contiguous(), ctx.opts)
-        return g_c, g_p, g_u, None, None
+                                             gdc.contiguous(), gdp.contiguous(), ctx.opts, D=ctx.D)
+        return g_c, g_p, g_u, None, None, None

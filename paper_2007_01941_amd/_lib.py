@@ -44,7 +44,7 @@ class _Opts(ctypes.Structure):
                 ("cheb_lo", ctypes.c_double), ("cheb_hi", ctypes.c_double),
                 ("min_coarsen_ratio", ctypes.c_double),
                 ("level0_op", ctypes.c_int32), ("freeze_damping_in_grad", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("coarse_shift", ctypes.c_double),
+                ("check_every", ctypes.c_int32), ("deterministic", ctypes.c_int32),
                 ("stop_rule", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("forcing", ctypes.c_double), ("loss", ctypes.c_int32), ("reserved1", ctypes.c_int32),
                 ("loss_scale", ctypes.c_double)]
@@ -119,7 +119,7 @@ class Options:
     level0_op: str = "auto"          # "auto" | "implicit" | "explicit"
     freeze_damping_in_grad: bool = False
     check_every: int = 4
-    coarse_shift: float = 1e-10
+    deterministic: bool = False
     stop_rule: str = "residual"      # "residual" | "nash_sofer"
     forcing: float = 0.1
     loss: str = "squared"            # "squared" | "huber"
@@ -137,7 +137,7 @@ class Options:
         o.level0_op = {"auto": OP_AUTO, "implicit": OP_IMPLICIT, "explicit": OP_EXPLICIT}[self.level0_op]
         o.freeze_damping_in_grad = int(self.freeze_damping_in_grad)
         o.check_every = self.check_every
-        o.coarse_shift = self.coarse_shift
+        o.deterministic = int(self.deterministic)
         o.stop_rule = {"residual": STOP_RESIDUAL, "nash_sofer": STOP_NASH_SOFER}[self.stop_rule]
         o.forcing = self.forcing
         o.loss = {"squared": LOSS_SQUARED, "huber": LOSS_HUBER}[self.loss]
@@ -158,7 +158,7 @@ def _load():
         "ba_plan_destroy": [P],
         "ba_plan_bytes": [P],
         "ba_lm_step": [P, P, P, P, P, P, P, P, P, P],
-        "ba_lm_step_backward": [P, P, P, P, P, P, P, P, P, P, P, P, P, P],
+        "ba_lm_step_backward": [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
         "ba_eval_jacobian": [P, P, P, P, P, P, P, P],
         "ba_step_prepare": [P, P, P, P, P, P, P, P],
         "ba_step_solve": [P, P, P, P, P, P],

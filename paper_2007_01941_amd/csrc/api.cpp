@@ -45,11 +45,13 @@ struct Scratch {
 
 static int red_grid(int n) { return std::max(1, std::min(RED_BLOCKS, ceil_div(n, 256))); }
 
-static void check_errflag(ba_plan* P, hipStream_t s, const char* stage = "") {
+// Read and clear the device error bits; bits outside `mask` are ignored.
+static void check_errflag(ba_plan* P, hipStream_t s, const char* stage = "", uint32_t mask = ~0u) {
   uint32_t e = 0;
   BA_HIP(hipMemcpyAsync(&e, P->errflag.p, sizeof(e), hipMemcpyDeviceToHost, s));
   BA_HIP(hipStreamSynchronize(s));
   if (e) BA_HIP(hipMemsetAsync(P->errflag.p, 0, sizeof(uint32_t), s));
+  e &= mask;
   BA_CHECK(!(e & ERRF_NONFINITE), BA_ERR_GEOMETRY, "non-finite camera, point, observation or residual");
   BA_CHECK(!(e & ERRF_GEOMETRY), BA_ERR_GEOMETRY,
            "a point lies at or behind an observing camera (x_cam.z >= 0)");
@@ -84,21 +86,40 @@ template <class T>
 static void schur_apply_dev(ba_plan* P, const T* x, T* y, const int* done, hipStream_t s);
 
 // y -= F^T E C^-1 E^T F x (the tile kernel alone; y already holds A x).
+template <class T> static T* te_part_of(ba_plan* P);
+template <> double* te_part_of<double>(ba_plan* P) { return P->te_part.p; }
+template <> float* te_part_of<float>(ba_plan* P) { return P->te_part32.p; }
+template <class T> struct Planes;
+template <> struct Planes<double> {
+  static const double* F(const ba_plan* P) { return P->F.p; }
+  static const double* E(const ba_plan* P) { return P->E.p; }
+  static const double* Cinv(const ba_plan* P) { return P->Cinv.p; }
+};
+template <> struct Planes<float> {
+  static const float* F(const ba_plan* P) { return P->F32.p; }
+  static const float* E(const ba_plan* P) { return P->E32.p; }
+  static const float* Cinv(const ba_plan* P) { return P->Cinv32.p; }
+};
+
+// With P->det (deterministic step) the tile kernel stores its (tile, camera)
+// sums and k_schur_gather adds them in tile order; otherwise it adds them to y
+// with atomics.
 template <class T>
-static void schur_tiles_dev(ba_plan* P, const T* x, T* y, const int* done, hipStream_t s);
-
-template <>
-void schur_tiles_dev<double>(ba_plan* P, const double* x, double* y, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_schur_tiles<double>, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
-                     P->tile_coff.p, P->tile_cams.p, P->tile_cseg.p, P->pt_off.p, P->obs_slot.p, P->F.p, P->E.p,
-                     P->n_obs_pad, P->Cinv.p, x, y, P->n_tiles, done);
-}
-
-template <>
-void schur_tiles_dev<float>(ba_plan* P, const float* x, float* y, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_schur_tiles<float>, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
-                     P->tile_coff.p, P->tile_cams.p, P->tile_cseg.p, P->pt_off.p, P->obs_slot.p, P->F32.p, P->E32.p,
-                     P->n_obs_pad, P->Cinv32.p, x, y, P->n_tiles, done);
+static void schur_tiles_dev(ba_plan* P, const T* x, T* y, const int* done, hipStream_t s) {
+  if (P->det) {
+    T* part = te_part_of<T>(P);
+    hipLaunchKernelGGL((k_schur_tiles<T, true>), dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p,
+                       P->tile_pt.p, P->tile_coff.p, P->tile_cams.p, P->tile_cseg.p, P->pt_off.p, P->obs_slot.p,
+                       Planes<T>::F(P), Planes<T>::E(P), P->n_obs_pad, Planes<T>::Cinv(P), x, y, part, P->n_tiles,
+                       done);
+    hipLaunchKernelGGL((k_schur_gather<T>), dim3(ceil_div(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam,
+                       P->cam_te_ptr.p, P->cam_te.p, (const T*)part, y, done);
+  } else {
+    hipLaunchKernelGGL((k_schur_tiles<T, false>), dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p,
+                       P->tile_pt.p, P->tile_coff.p, P->tile_cams.p, P->tile_cseg.p, P->pt_off.p, P->obs_slot.p,
+                       Planes<T>::F(P), Planes<T>::E(P), P->n_obs_pad, Planes<T>::Cinv(P), x, y, (T*)nullptr,
+                       P->n_tiles, done);
+  }
 }
 
 template <>
@@ -154,7 +175,7 @@ ba_status ba_opts_default(ba_opts* o) {
   o->level0_op = BA_OP_AUTO;
   o->freeze_damping_in_grad = 0;
   o->check_every = 4;
-  o->coarse_shift = 1e-10;
+  o->deterministic = 0;
   o->stop_rule = BA_STOP_RESIDUAL;
   o->forcing = 0.1;
   o->loss = BA_LOSS_SQUARED;
@@ -179,7 +200,7 @@ static void validate_opts(const ba_opts* o) {
   BA_CHECK(o->max_levels >= 1 && o->max_levels <= 16, BA_ERR_ARG, "max_levels must be in [1, 16]");
   BA_CHECK(o->cheb_hi > o->cheb_lo && o->cheb_lo > 0.0, BA_ERR_ARG, "bad Chebyshev interval");
   BA_CHECK(o->check_every >= 1, BA_ERR_ARG, "check_every must be >= 1");
-  BA_CHECK(o->coarse_shift >= 0.0 && o->coarse_shift < 1.0, BA_ERR_ARG, "coarse_shift must be in [0, 1)");
+  BA_CHECK(o->deterministic == 0 || o->deterministic == 1, BA_ERR_ARG, "deterministic must be 0 or 1");
   BA_CHECK(o->stop_rule == BA_STOP_RESIDUAL || o->stop_rule == BA_STOP_NASH_SOFER, BA_ERR_ARG, "bad stop_rule");
   BA_CHECK(o->stop_rule != BA_STOP_NASH_SOFER || (o->forcing >= 0.0 && o->precision == BA_FP64), BA_ERR_ARG,
            "the Nash-Sofer rule needs forcing >= 0 and BA_FP64");
@@ -249,7 +270,7 @@ ba_status ba_eval_jacobian(ba_plan* P, const double* cams, const double* pts, co
   BA_API_BEGIN
   BA_CHECK(P && cams && pts && uv, BA_ERR_ARG, "null argument");
   hipStream_t s = (hipStream_t)stream;
-  eval_jacobian(P, cams, pts, uv, false, s);
+  eval_jacobian(P, cams, pts, uv, s);
   hipLaunchKernelGGL(k_scatter_jacobian, dim3(ceil_div(P->n_obs, 256)), dim3(256), 0, s, (int)P->n_obs,
                      P->obs_orig.p, P->n_obs_pad, P->F.p, P->E.p, P->fres.p, f, F, E);
   BA_LAUNCH_CHECK();
@@ -399,7 +420,7 @@ ba_status ba_mg_level_data(const ba_plan* P, int32_t level, int32_t what, double
 }
 
 ba_status ba_lm_step_backward(ba_plan* P, const ba_opts* o, const double* cams, const double* pts,
-                              const double* uv, const double* delta_cam, const double* delta_pt,
+                              const double* uv, const double* D, const double* delta_cam, const double* delta_pt,
                               const double* gd_cam, const double* gd_pt, double* g_cams, double* g_pts,
                               double* g_uv, ba_stats* st, void* stream) {
   BA_API_BEGIN
@@ -407,7 +428,7 @@ ba_status ba_lm_step_backward(ba_plan* P, const ba_opts* o, const double* cams, 
            BA_ERR_ARG, "null argument");
   validate_opts(o);
   BA_CHECK(o->loss == BA_LOSS_SQUARED, BA_ERR_ARG, "the backward pass supports the squared loss only");
-  return backward(P, o, cams, pts, uv, delta_cam, delta_pt, gd_cam, gd_pt, g_cams, g_pts, g_uv, st,
+  return backward(P, o, cams, pts, uv, D, delta_cam, delta_pt, gd_cam, gd_pt, g_cams, g_pts, g_uv, st,
                   (hipStream_t)stream);
   BA_API_END
 }

@@ -10,11 +10,11 @@ struct Backward {
 };
 
 static ba_status backward(ba_plan* P, const ba_opts* o, const double* cams, const double* pts, const double* uv,
-                          const double* delta_cam, const double* delta_pt, const double* gd_cam,
+                          const double* D, const double* delta_cam, const double* delta_pt, const double* gd_cam,
                           const double* gd_pt, double* g_cams, double* g_pts, double* g_uv, ba_stats* st,
                           hipStream_t s) {
   if (st) std::memset(st, 0, sizeof(*st));
-  prepare(P, o, cams, pts, uv, nullptr, st, s);
+  prepare(P, o, cams, pts, uv, D, st, s);
   Scratch& W = *P->scratch;
   if (!P->bwd) P->bwd = new Backward();
   Backward& B = *P->bwd;
@@ -37,7 +37,7 @@ static ba_status backward(ba_plan* P, const ba_opts* o, const double* cams, cons
                      B.mu_p.p, P->n_tiles);
   hipLaunchKernelGGL(k_adjoint_obs, dim3(grid_of<double>(P->n_obs)), dim3(256), 0, s, (int)P->n_obs, P->obs_cam.p,
                      P->obs_pt.p, P->obs_orig.p, P->pt_orig.p, P->n_obs_pad, P->F.p, P->E.p, P->fres.p, cams, pts,
-                     W.x.p, B.mu_p.p, delta_cam, delta_pt, o->lambda, o->freeze_damping_in_grad, g_uv, B.tcam.p,
+                     W.x.p, B.mu_p.p, delta_cam, delta_pt, o->lambda, (D || o->freeze_damping_in_grad) ? 1 : 0, g_uv, B.tcam.p,
                      B.tpt.p);
   hipLaunchKernelGGL(k_adjoint_points, dim3(grid_of<double>(P->n_pt)), dim3(256), 0, s, P->n_pt, P->pt_off.p,
                      P->pt_orig.p, P->n_obs_pad, B.tpt.p, g_pts);

@@ -31,6 +31,15 @@ static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
     max_k = std::max(max_k, cnt[p]);
   }
   BA_CHECK(max_k <= 65535, BA_ERR_LIMIT, "a point is seen by %d cameras (limit 65535)", max_k);
+  // Every covisibility count of every level is at most sum_p k_p^2 (the sum of
+  // all entries of W = V V^T, which Ahat^T W Ahat keeps); the exact strength
+  // comparison multiplies three counts in 128 bits, so they must stay < 2^42.
+  {
+    int64_t wsum = 0;
+    for (int p = 0; p < n_pt; ++p) wsum += (int64_t)cnt[p] * cnt[p];
+    BA_CHECK(wsum < (int64_t(1) << 42), BA_ERR_LIMIT,
+             "sum over points of (observations per point)^2 = %lld exceeds 2^42", (long long)wsum);
+  }
   for (int c = 0; c < n_cam; ++c)
     BA_CHECK(ccnt[c] >= 1, BA_ERR_STRUCTURE, "camera %d observes no point", c);
   // point-major, stable in the caller's order, then each point's views by camera
@@ -160,6 +169,17 @@ static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
   P->tile_cams.upload(t_cams, s);
   P->tile_cseg.upload(t_cseg, s);
   P->obs_slot.upload(slot, s);
+  {
+    // per camera, its entries of tile_cams in tile order (deterministic product)
+    std::vector<int32_t> tptr(n_cam + 1, 0), te(t_cams.size());
+    for (int32_t c : t_cams) ++tptr[c + 1];
+    for (int c = 0; c < n_cam; ++c) tptr[c + 1] += tptr[c];
+    std::vector<int32_t> cur(tptr.begin(), tptr.end() - 1);
+    for (size_t e = 0; e < t_cams.size(); ++e) te[cur[t_cams[e]]++] = (int32_t)e;
+    P->n_te = (int32_t)t_cams.size();
+    P->cam_te_ptr.upload(tptr, s);
+    P->cam_te.upload(te, s);
+  }
   BA_HIP(hipStreamSynchronize(s));
 }
 
@@ -256,6 +276,15 @@ static void build_s0_pairs(ba_plan* P, const Level& L0, hipStream_t s) {
       ce.push_back((int32_t)e);
       cb.push_back(h);
     }
+  std::vector<int32_t> be, bb;
+  for (int64_t e = 0; e < L0.nnz; ++e)
+    if (cnt[e + 1] > cnt[e]) {
+      be.push_back((int32_t)e);
+      bb.push_back(cnt[e]);
+    }
+  P->s0_blocks = (int32_t)be.size();
+  P->s0_blk_e.upload(be, s);
+  P->s0_blk_beg.upload(bb, s);
   P->s0_chunks = (int32_t)ce.size();
   P->s0_ptr.upload(cnt, s);
   P->s0_q.upload(pts, s);

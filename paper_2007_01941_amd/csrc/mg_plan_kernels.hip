@@ -3,7 +3,10 @@
 //
 // W = V V^T counts the points two cameras share (W_ii = points seen by i).
 // The strength of connection is G_ij = W_ij / sqrt(W_ii W_jj) (the visibility
-// cosine), evaluated in IEEE FP64 exactly as written. On coarse levels an
+// cosine). Neighbours of one row are only ever compared with each other, and
+// G_ij > G_ik exactly when W_ij^2 W_kk > W_ik^2 W_jj, so the order is decided
+// in 128-bit integers without rounding (the plan bounds every count by 2^42,
+// so the products stay below 2^126). On coarse levels an
 // aggregate's visibility vector is the sum of its members', so
 // W_{l+1} = Ahat^T W_l Ahat with Ahat the 0/1 aggregate matrix.
 #include "kernels.hpp"
@@ -121,9 +124,14 @@ __global__ __launch_bounds__(256) void k_covisL(const int32_t* __restrict__ agg_
   hash_emit<PASS>(row, keys, vals, &n_used, row_nnz, wdiag, rowptr, col, val, err);
 }
 
-// Strength G_ij exactly as the definition writes it, in FP64.
-__device__ __forceinline__ double strength(int64_t wij, int64_t wii, int64_t wjj) {
-  return (double)wij / sqrt((double)wii * (double)wjj);
+// True when neighbour a (count wa = W_ia, diagonal da = W_aa) comes after
+// neighbour b in row i's order: weaker strength, or equal strength and a
+// higher column. Strengths compare as W_ia^2 W_bb against W_ib^2 W_aa.
+__device__ __forceinline__ bool weaker(long long wa, long long da, int ca, long long wb, long long db,
+                                       int cb) {
+  const unsigned __int128 lhs = (unsigned __int128)(uint64_t)wa * (uint64_t)wa * (uint64_t)db;
+  const unsigned __int128 rhs = (unsigned __int128)(uint64_t)wb * (uint64_t)wb * (uint64_t)da;
+  return lhs < rhs || (lhs == rhs && ca > cb);
 }
 
 // Sort one row by column (carrying the counts), then write its neighbours
@@ -133,7 +141,7 @@ __global__ __launch_bounds__(256) void k_row_sort(const int64_t* __restrict__ ro
                                                   int32_t* order, uint32_t* err) {
   __shared__ int c_s[ROW_SORT_MAX];
   __shared__ long long v_s[ROW_SORT_MAX];
-  __shared__ double g_s[ROW_SORT_MAX];
+  __shared__ long long d_s[ROW_SORT_MAX];
   const int row = blockIdx.x;
   const int64_t beg = rowptr[row];
   const int len = (int)(rowptr[row + 1] - beg);
@@ -164,10 +172,12 @@ __global__ __launch_bounds__(256) void k_row_sort(const int64_t* __restrict__ ro
       __syncthreads();
     }
   for (int i = threadIdx.x; i < len; i += blockDim.x) { col[beg + i] = c_s[i]; val[beg + i] = v_s[i]; }
-  const int64_t wii = wdiag[row];
+  __syncthreads();
+  // the diagonal and the padding get strength 0 (count 0), below every
+  // neighbour (counts >= 1); among them the diagonal's column comes first
   for (int i = threadIdx.x; i < m; i += blockDim.x) {
-    if (i < len && c_s[i] != row) g_s[i] = strength(v_s[i], wii, wdiag[c_s[i]]);
-    else g_s[i] = -1.0;       // diagonal and padding sort last
+    if (i < len && c_s[i] != row) d_s[i] = wdiag[c_s[i]];
+    else { v_s[i] = 0; d_s[i] = 1; }
   }
   __syncthreads();
   // bitonic sort by (strength descending, column ascending)
@@ -177,10 +187,10 @@ __global__ __launch_bounds__(256) void k_row_sort(const int64_t* __restrict__ ro
         const int l = i ^ j;
         if (l > i) {
           const bool up = (i & k) == 0;
-          const bool i_after_l = (g_s[i] < g_s[l]) || (g_s[i] == g_s[l] && c_s[i] > c_s[l]);
-          if (i_after_l == up) {
+          if (weaker(v_s[i], d_s[i], c_s[i], v_s[l], d_s[l], c_s[l]) == up) {
             const int tc = c_s[i]; c_s[i] = c_s[l]; c_s[l] = tc;
-            const double tg = g_s[i]; g_s[i] = g_s[l]; g_s[l] = tg;
+            const long long tv = v_s[i]; v_s[i] = v_s[l]; v_s[l] = tv;
+            const long long td = d_s[i]; d_s[i] = d_s[l]; d_s[l] = td;
           }
         }
       }

@@ -101,6 +101,16 @@ struct ba_plan {
   bamg::DBuf<int32_t> s0_chunk_e;    // chunks of <= S0_CHUNK points: block
   bamg::DBuf<int32_t> s0_chunk_beg;  //   and first index into s0_q
   int32_t s0_chunks = 0;
+  bamg::DBuf<int32_t> s0_blk_e;      // deterministic mode: every upper block with
+  bamg::DBuf<int32_t> s0_blk_beg;    //   shared points, and its first index into s0_q
+  int32_t s0_blocks = 0;
+  // deterministic Schur product: per camera, its (tile, camera) entries of
+  // tile_cams in tile order, and the partial sums of one product
+  bamg::DBuf<int32_t> cam_te_ptr;    // [n_cam + 1]
+  bamg::DBuf<int32_t> cam_te;        // [total tile_cams entries]
+  int32_t n_te = 0;
+  bamg::DBuf<double> te_part;        // [n_te][9]
+  bamg::DBuf<float> te_part32;
   int32_t max_pt_obs = 0;
   // ---- multigrid hierarchy
   std::vector<bamg::Level> levels;
@@ -132,6 +142,7 @@ struct ba_plan {
   bool prepared_mg = false;
   bool inspectable_mg = false;   // hierarchy data readable (also after a failed setup)
   bool have_mixed = false;
+  bool det = false;               // the prepared step runs without floating-point atomics
   double lambda = 1e-4;
   bamg::Scratch* scratch = nullptr;
   // side stream of the multigrid setup (default priority), forked from and

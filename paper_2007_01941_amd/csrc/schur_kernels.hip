@@ -39,20 +39,26 @@ __global__ __launch_bounds__(256) void k_apply_A(int n_cam, const T* __restrict_
 // A tile of more than TILE_OBS observations (a single point) adds its camera
 // terms to y with global atomics directly.
 //
+// DET (deterministic): no floating-point atomics anywhere. Every (tile,
+// camera) sum is formed by the camera-sorted runs (both precisions) and
+// stored to part[(tile_coff[t] + slot) * 9 + k]; k_schur_gather then adds each
+// camera's partials to y in tile order. A single-point tile has one
+// observation per camera, so its terms are stored the same way.
+//
 // Tiles are numbered in point order, so neighbouring tiles share cameras; the
 // launch maps workgroups to tiles with xcd_block (each XCD takes one
 // contiguous range), so the x reads and y atomics of neighbouring tiles meet
 // in the same L2.
-template <class T>
+template <class T, bool DET>
 __global__ __launch_bounds__(256) void k_schur_tiles(
     const int32_t* __restrict__ tile_obs, const int32_t* __restrict__ tile_pt,
     const int32_t* __restrict__ tile_coff, const int32_t* __restrict__ tile_cams,
     const int32_t* __restrict__ tile_cseg, const int32_t* __restrict__ pt_off,
     const uint32_t* __restrict__ obs_slot, const T* __restrict__ F, const T* __restrict__ E, int64_t stride,
-    const T* __restrict__ Cinv, const T* __restrict__ x, T* __restrict__ y, int n_tiles,
+    const T* __restrict__ Cinv, const T* __restrict__ x, T* __restrict__ y, T* __restrict__ part, int n_tiles,
     const int* __restrict__ done) {
   if (done && *done) return;
-  constexpr bool lds_atomics = sizeof(T) == 8;
+  constexpr bool lds_atomics = sizeof(T) == 8 && !DET;
   __shared__ T xs[TILE_SLOTS * 9];
   __shared__ T ys[lds_atomics ? TILE_SLOTS * 9 : 1];
   // E^T F x terms [3][TILE_OBS]; FP32 then the camera terms [TILE_OBS][9]
@@ -136,8 +142,13 @@ __global__ __launch_bounds__(256) void k_schur_tiles(
       const T u0 = us[pq * 3], u1 = us[pq * 3 + 1], u2 = us[pq * 3 + 2];
       const T w0 = E[0 * stride + oo] * u0 + E[1 * stride + oo] * u1 + E[2 * stride + oo] * u2;
       const T w1 = E[3 * stride + oo] * u0 + E[4 * stride + oo] * u1 + E[5 * stride + oo] * u2;
-      T* yv = y + (size_t)tile_cams[c0 + sl] * 9;
-      for (int k = 0; k < 9; ++k) unsafeAtomicAdd(&yv[k], -(F[k * stride + oo] * w0 + F[(9 + k) * stride + oo] * w1));
+      if (DET) {
+        T* pv = part + (size_t)(c0 + sl) * 9;
+        for (int k = 0; k < 9; ++k) pv[k] = -(F[k * stride + oo] * w0 + F[(9 + k) * stride + oo] * w1);
+      } else {
+        T* yv = y + (size_t)tile_cams[c0 + sl] * 9;
+        for (int k = 0; k < 9; ++k) unsafeAtomicAdd(&yv[k], -(F[k * stride + oo] * w0 + F[(9 + k) * stride + oo] * w1));
+      }
     }
     return;
   }
@@ -173,21 +184,41 @@ __global__ __launch_bounds__(256) void k_schur_tiles(
       const int sl = i / 9, k = i - sl * 9;
       T acc = 0;
       for (int l = segs[sl]; l < segs[sl + 1]; ++l) acc += buf[l * 9 + k];
-      unsafeAtomicAdd(&y[(size_t)tile_cams[c0 + sl] * 9 + k], acc);
+      if (DET) part[(size_t)(c0 + sl) * 9 + k] = acc;
+      else unsafeAtomicAdd(&y[(size_t)tile_cams[c0 + sl] * 9 + k], acc);
     }
   }
 }
 
-template __global__ void k_schur_tiles<double>(const int32_t*, const int32_t*, const int32_t*,
-                                               const int32_t*, const int32_t*, const int32_t*, const uint32_t*,
-                                               const double*,
-                                               const double*, int64_t, const double*, const double*,
-                                               double*, int, const int*);
-template __global__ void k_schur_tiles<float>(const int32_t*, const int32_t*, const int32_t*,
-                                              const int32_t*, const int32_t*, const int32_t*, const uint32_t*,
-                                              const float*,
-                                              const float*, int64_t, const float*, const float*,
-                                              float*, int, const int*);
+// Deterministic completion of the product: y_c += the partial sums of camera
+// c's (tile, camera) entries in tile order (te_ptr/te list them per camera).
+// One thread per (camera, component).
+template <class T>
+__global__ __launch_bounds__(256) void k_schur_gather(int n_cam, const int32_t* __restrict__ te_ptr,
+                                                      const int32_t* __restrict__ te, const T* __restrict__ part,
+                                                      T* __restrict__ y, const int* __restrict__ done) {
+  if (done && *done) return;
+  const int gid = blockIdx.x * 252 + threadIdx.x;
+  const int c = gid / 9, k = gid % 9;
+  if (threadIdx.x >= 252 || c >= n_cam) return;
+  T acc = 0;
+  for (int i = te_ptr[c]; i < te_ptr[c + 1]; ++i) acc += part[(size_t)te[i] * 9 + k];
+  y[(size_t)c * 9 + k] += acc;
+}
+
+#define BAMG_SCHUR_INST(T, DET)                                                                              \
+  template __global__ void k_schur_tiles<T, DET>(const int32_t*, const int32_t*, const int32_t*, const int32_t*, \
+                                                 const int32_t*, const int32_t*, const uint32_t*, const T*,       \
+                                                 const T*, int64_t, const T*, const T*, T*, T*, int, const int*);
+BAMG_SCHUR_INST(double, false)
+BAMG_SCHUR_INST(double, true)
+BAMG_SCHUR_INST(float, false)
+BAMG_SCHUR_INST(float, true)
+#undef BAMG_SCHUR_INST
+template __global__ void k_schur_gather<double>(int, const int32_t*, const int32_t*, const double*, double*,
+                                                const int*);
+template __global__ void k_schur_gather<float>(int, const int32_t*, const int32_t*, const float*, float*,
+                                               const int*);
 template __global__ void k_apply_A<double>(int, const double*, const double*, double*);
 template __global__ void k_apply_A<float>(int, const float*, const float*, float*);
 

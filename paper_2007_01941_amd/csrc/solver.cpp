@@ -22,6 +22,8 @@ static size_t plan_bytes(const ba_plan* P) {
   b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
   b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->Scc.bytes() + P->prec.bytes();
   b += P->Sinv.bytes() + P->Sinv32.bytes() + P->wsq.bytes() + P->cj_off.bytes() + P->cj_inv.bytes();
+  b += P->s0_blk_e.bytes() + P->s0_blk_beg.bytes() + P->cam_te_ptr.bytes() + P->cam_te.bytes() + P->te_part.bytes() +
+       P->te_part32.bytes();
   for (const Level& L : P->levels) {
     b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
     b += L.diag_pos.bytes() + L.trans_pos.bytes() + L.row_of.bytes() + L.agg.bytes() + L.agg_ptr.bytes();
@@ -123,15 +125,20 @@ static void convert(size_t n, const T* a, U* b, hipStream_t s) {
   if (n) hipLaunchKernelGGL((k_convert<T, U>), dim3(grid_of<T>(n)), dim3(256), 0, s, (int)n, a, b);
 }
 
-static void eval_jacobian(ba_plan* P, const double* cams, const double* pts, const double* uv, bool mixed,
-                          hipStream_t s) {
+// Residual and Jacobian planes by the step's own kernel (k_jacobian_tiles),
+// without robust weighting; its point-side outputs (C^-1 with the default
+// damping, g_p, point records) are written too and discarded by the caller.
+static void eval_jacobian(ba_plan* P, const double* cams, const double* pts, const double* uv, hipStream_t s) {
   hipLaunchKernelGGL(k_campre, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
                      P->errflag.p);
-  hipLaunchKernelGGL(k_jacobian, dim3(grid_of<double>(P->n_obs)), dim3(256), 0, s, (int)P->n_obs, P->obs_cam.p,
-                     P->obs_pt.p, P->obs_orig.p, P->pt_orig.p, P->campre.p, pts, uv, P->n_obs_pad, P->F.p, P->E.p,
-                     P->fres.p, mixed ? P->F32.p : nullptr, mixed ? P->E32.p : nullptr, P->errflag.p);
+  hipLaunchKernelGGL(k_jacobian_tiles, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p,
+                     P->pt_off.p, P->obs_slot.p, P->obs_cam.p, P->obs_orig.p, P->pt_orig.p, P->campre.p, pts, uv,
+                     P->n_obs_pad, 1e-4, (const double*)nullptr, P->n_cam, P->F.p, P->E.p, P->fres.p,
+                     (float*)nullptr, (float*)nullptr, P->Cinv.p, (float*)nullptr, P->vgp.p, P->gp.p, P->Dp.p,
+                     P->prec.p, P->n_tiles, BA_LOSS_SQUARED, 1.0, (double*)nullptr, P->errflag.p);
   BA_LAUNCH_CHECK();
-  check_errflag(P, s);
+  // a point block that is not positive definite does not concern this call
+  check_errflag(P, s, "residual and Jacobian", ~ERRF_NOT_SPD);
 }
 
 // ---------------------------------------------------------------- level operators
@@ -542,9 +549,9 @@ static double lanczos_finish(const double* h, int steps) {
 
 // ---------------------------------------------------------------- multigrid setup
 
-// Dense FP64 inverse of the coarsest level's operator: the equilibrated
-// s S s + eps I (s = diag^-1/2, eps = coarse_shift) by blocked Gauss-Jordan,
-// scaled back: inv = s (s S s + eps I)^-1 s.
+// Dense FP64 inverse of the coarsest level's operator (Algorithm 1's direct
+// solve): the equilibrated s S s (s = diag^-1/2) by blocked Gauss-Jordan,
+// scaled back: inv = s (s S s)^-1 s.
 static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
   Level& Lc = P->levels.back();
   BA_HIP(hipMemsetAsync(Lc.dense.p, 0, (size_t)Lc.nd * Lc.nd * sizeof(double), s));
@@ -555,8 +562,7 @@ static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
   const int64_t nd2 = (int64_t)Lc.nd * Lc.nd;
   hipLaunchKernelGGL(k_dense_diag, dim3(grid_of<double>(Lc.nd)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
                      P->errflag.p);
-  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
-                     o->coarse_shift);
+  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p, 0.0);
   // Pivot step k: P_k = A_kk^-1 (one workgroup), then the update of every block.
   const int nbk = Lc.nd / GJB;
   for (int k = 0; k < nbk; ++k) {
@@ -587,8 +593,12 @@ static void assemble_s0(ba_plan* P, hipStream_t s) {
   Level& L0 = P->levels[0];
   hipLaunchKernelGGL(k_s0_init, dim3(grid_of<double>(L0.nnz * 81)), dim3(256), 0, s, (int64_t)L0.nnz * 81,
                      L0.row_of.p, L0.col.p, P->Scc.p, L0.S.p);
-  if (P->s0_chunks > 0)
-    hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, P->s0_chunk_e.p, P->s0_chunk_beg.p,
+  if (P->det && P->s0_blocks > 0)
+    hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_blocks), dim3(64), 0, s, 1, P->s0_blk_e.p, P->s0_blk_beg.p,
+                       L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
+                       P->pt_off.p, P->obs_cam.p, P->robust ? P->wsq.p : nullptr, L0.S.p);
+  else if (!P->det && P->s0_chunks > 0)
+    hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, 0, P->s0_chunk_e.p, P->s0_chunk_beg.p,
                        L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
                        P->pt_off.p, P->obs_cam.p, P->robust ? P->wsq.p : nullptr, L0.S.p);
 }
@@ -721,6 +731,9 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   P->prepared_cj = false;
   P->inspectable_mg = false;
   P->lambda = o->lambda;
+  P->det = o->deterministic != 0;
+  if (P->det && !P->te_part.p) P->te_part.alloc((size_t)P->n_te * 9);
+  if (P->det && mixed && !P->te_part32.p) P->te_part32.alloc((size_t)P->n_te * 9);
   P->robust = o->loss != BA_LOSS_SQUARED;
   if (P->robust && !P->wsq.p) P->wsq.alloc((size_t)P->n_obs_pad);
   double* wsq = P->robust ? P->wsq.p : nullptr;
@@ -818,11 +831,11 @@ static ba_status solve_camera_system(ba_plan* P, const ba_opts* o, const double*
   if (o->precision == BA_FP64) {
     PcgOut r = pcg_run<double>(P, o, b, PcgVecs<double>{W.x.p, W.r.p, W.z.p, W.p.p, W.q.p}, o->rtol, o->max_iter, s,
                                forcing);
-    BA_CHECK(!r.breakdown, BA_ERR_NOT_SPD, "PCG breakdown: the operator or preconditioner is not SPD");
-    if (st) {
+    if (st) {   // also on a breakdown: the iterations spent are reported
       st->iters = r.iters;
       st->rel_res = r.bb > 0 ? std::sqrt(r.rr / r.bb) : 0.0;
     }
+    BA_CHECK(!r.breakdown, BA_ERR_NOT_SPD, "PCG breakdown: the operator or preconditioner is not SPD");
     if (!r.converged) status = BA_NOT_CONVERGED;
   } else {
     // FP64 iterative refinement around FP32 PCG
@@ -854,8 +867,9 @@ static ba_status solve_camera_system(ba_plan* P, const ba_opts* o, const double*
         const double tol64 = std::min(0.5, o->rtol * std::sqrt(bb / std::max(rr, 1e-300)));
         PcgOut r64 = pcg_run<double>(P, o, W.t.p, PcgVecs<double>{W.e.p, W.r.p, W.z.p, W.p.p, W.q.p}, tol64,
                                      o->max_iter, s);
-        BA_CHECK(!r64.breakdown, BA_ERR_NOT_SPD, "PCG breakdown: the operator or preconditioner is not SPD");
         iters += r64.iters;
+        if (st) st->iters = iters;
+        BA_CHECK(!r64.breakdown, BA_ERR_NOT_SPD, "PCG breakdown: the operator or preconditioner is not SPD");
         hipLaunchKernelGGL(k_add_f64, dim3(grid_of<double>(n)), dim3(256), 0, s, n, (const double*)W.e.p, W.x.p);
         if (st) st->fallback_fp64 = 1;
       } else {

@@ -101,38 +101,6 @@ __device__ __forceinline__ void project_jacobian(const double* __restrict__ cp, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_jacobian(
-    int n_obs, const int32_t* __restrict__ obs_cam, const int32_t* __restrict__ obs_pt,
-    const int32_t* __restrict__ obs_orig, const int32_t* __restrict__ pt_orig,
-    const double* __restrict__ campre, const double* __restrict__ pts, const double* __restrict__ uv,
-    int64_t stride, double* __restrict__ F, double* __restrict__ E, double* __restrict__ fres,
-    float* __restrict__ F32, float* __restrict__ E32, uint32_t* err) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= n_obs) return;
-  const int c = obs_cam[o];
-  const int q = pt_orig[obs_pt[o]];
-  const int oo = obs_orig[o];
-  const double X[3] = {pts[q * 3 + 0], pts[q * 3 + 1], pts[q * 3 + 2]};
-  double pi[2], Fo[18], Eo[6], z;
-  project_jacobian(campre + (size_t)c * 24, X, pi, Fo, Eo, &z);
-  const double r0 = pi[0] - uv[(size_t)oo * 2 + 0];
-  const double r1 = pi[1] - uv[(size_t)oo * 2 + 1];
-  if (!(z < 0.0)) atomicOr(err, ERRF_GEOMETRY);
-  if (!isfinite(r0) || !isfinite(r1) || !isfinite(X[0] + X[1] + X[2])) atomicOr(err, ERRF_NONFINITE);
-  fres[o] = r0;
-  fres[stride + o] = r1;
-#pragma unroll
-  for (int k = 0; k < 18; ++k) F[k * stride + o] = Fo[k];
-#pragma unroll
-  for (int k = 0; k < 6; ++k) E[k * stride + o] = Eo[k];
-  if (F32) {
-#pragma unroll
-    for (int k = 0; k < 18; ++k) F32[k * stride + o] = (float)Fo[k];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) E32[k * stride + o] = (float)Eo[k];
-  }
-}
-
 // Point-major planes -> caller-order arrays (f [n][2], F [n][2][9], E [n][2][3]).
 __global__ void k_scatter_jacobian(int n_obs, const int32_t* __restrict__ obs_orig, int64_t stride,
                                    const double* __restrict__ F, const double* __restrict__ E,

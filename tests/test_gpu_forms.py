@@ -82,3 +82,35 @@ def test_adjoint_directional_finite_differences():
         an = float((cams.grad * vc).sum() + (pts.grad * vp).sum() + (uv.grad * vu).sum())
         print(f"[gpu] fd {fd:.8e} adjoint {an:.8e}", flush=True)
         assert abs(fd - an) <= 2e-5 * abs(an) + 1e-6
+
+
+def test_adjoint_with_explicit_damping():
+    """A step taken with an explicit damping diagonal D (held constant): the
+    backward pass solves with the same H = J^T J + D, and its gradient matches
+    central differences of the loss with D fixed."""
+    import paper_2007_01941_amd as bamg
+    sc = scene("ring20")
+    plan, opts = plan_for(sc, precond="mg", rtol=1e-13, max_iter=5000, coarse_max_nodes=4)
+    nrm0 = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    rng = np.random.default_rng(17)
+    D = dev(np.concatenate([nrm0.Dc.ravel(), nrm0.Dp.ravel()]) * rng.uniform(0.5, 5.0, 9 * sc.n_cam + 3 * sc.n_pt))
+    cams, pts, uv = inputs(sc)
+    for t in (cams, pts, uv):
+        t.requires_grad_(True)
+    dc, dp = bamg.LMStep.apply(cams, pts, uv, plan, opts, D)
+    ((dc * dc).sum() + (dp * dp).sum()).backward()
+
+    def loss(c, p, u):
+        a, b, _ = plan.lm_step(c, p, u, D=D)
+        return float((a * a).sum() + (b * b).sum())
+
+    h = 1e-4
+    for _ in range(4):
+        vc, vp, vu = (torch.as_tensor(rng.normal(size=t.shape), device="cuda") for t in (cams, pts, uv))
+        s = float(torch.sqrt((vc ** 2).sum() + (vp ** 2).sum() + (vu ** 2).sum()))
+        vc, vp, vu = vc / s, vp / s, vu / s
+        with torch.no_grad():
+            fd = (loss(cams + h * vc, pts + h * vp, uv + h * vu) - loss(cams - h * vc, pts - h * vp, uv - h * vu)) / (2 * h)
+        an = float((cams.grad * vc).sum() + (pts.grad * vp).sum() + (uv.grad * vu).sum())
+        print(f"[gpu] explicit D: fd {fd:.8e} adjoint {an:.8e}", flush=True)
+        assert abs(fd - an) <= 2e-5 * abs(an) + 1e-6

@@ -142,3 +142,24 @@ def test_fullsize_tight_solve_agrees(city):
     assert st_mg.iters < st_bj.iters
     assert e_tight <= 1e-5
     assert e_bench <= 1e-2
+
+
+def test_fullsize_shuffled_observations(city):
+    """The plan accepts observations in any order and sorts them itself: the
+    benchmark scene with its observations (and pixels) permuted gives the
+    same integer structure and, in deterministic mode, a bitwise equal step."""
+    sc, nrm, plan, opts = city
+    import torch
+    import paper_2007_01941_amd as bamg
+    perm = np.random.default_rng(12).permutation(sc.n_obs)
+    det = bamg.Options(precond="mg", deterministic=True, **BENCH)
+    a = bamg.Plan(sc.n_cam, sc.n_pt, dev(sc.obs_cam, torch.int32), dev(sc.obs_pt, torch.int32), det)
+    b = bamg.Plan(sc.n_cam, sc.n_pt, dev(sc.obs_cam[perm], torch.int32), dev(sc.obs_pt[perm], torch.int32), det)
+    assert a.mg_levels() == b.mg_levels()
+    for l in range(len(a.mg_levels()) - 1):
+        assert np.array_equal(host(a.mg_aggregates(l)), host(b.mg_aggregates(l)))
+    dca, dpa, sta = a.lm_step(*inputs(sc))
+    dcb, dpb, stb = b.lm_step(*inputs(sc, uv=sc.uv[perm]))
+    print(f"[gpu] city2k shuffled: iters {sta.iters} / {stb.iters}", flush=True)
+    assert sta.iters == stb.iters
+    assert np.array_equal(host(dca), host(dcb)) and np.array_equal(host(dpa), host(dpb))

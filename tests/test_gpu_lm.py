@@ -172,7 +172,12 @@ def test_lm_survives_breakdowns():
     """With almost no damping (radius 1e12) from the hard start the damped
     systems can stop being numerically positive definite; the loop treats such
     a step as failed (infinite candidate cost, radius shrunk as for a
-    rejection) instead of aborting, and still lowers the cost."""
+    rejection) instead of aborting, and still lowers the cost. Whether a system
+    this close to singular still counts as positive definite is decided by
+    rounding, so the two sides need not fail at the same iterations; but a
+    failed step and a rejected one update the radius alike, so the oracle's
+    loop from the same start must reject wherever the GPU failed and take the
+    same accept/reject decisions and radii throughout."""
     import paper_2007_01941_amd as bamg
     sc = tiny_scene(10, 150, seed=21, k_min=2, k_max=5)
     pts0 = hard_start(sc)
@@ -180,7 +185,19 @@ def test_lm_survives_breakdowns():
     cams, pts, uv = inputs(sc, pts=pts0)
     out = plan.lm_solve(cams, pts, uv, opts=opts, lm_opts=bamg.LMOptions(max_iters=25, radius0=1e12))
     failed = [i for i, h in enumerate(out.history) if np.isinf(h.cost_candidate) and h.step_norm == 0.0]
-    print(f"[gpu] lm breakdowns at iterations {failed}; cost {out.cost0:.3e} -> {out.cost:.3e}", flush=True)
+    res = olm.solve(sc.cams, pts0, sc.obs_cam, sc.obs_pt, sc.uv, olm.LMOptions(max_iters=25, radius0=1e12),
+                    method="bj", rtol=1e-10, max_pcg=5000)
+    failed_ref = [i for i, h in enumerate(res.history) if np.isinf(h.cost_candidate) and h.step_norm == 0.0]
+    print(f"[gpu] lm breakdowns at iterations {failed} (oracle {failed_ref}); "
+          f"cost {out.cost0:.3e} -> {out.cost:.3e} (oracle {res.cost:.3e})", flush=True)
+    assert failed
+    assert all(not res.history[i].accepted for i in failed)
+    assert [h.accepted for h in out.history] == [h.accepted for h in res.history]
+    for h, r in zip(out.history, res.history):
+        assert abs(h.radius - r.radius) <= 1e-12 * r.radius
+    # a failed step's PCG work is counted in the history
+    assert all(h.pcg_iters >= 0 for h in out.history)
+    assert out.pcg_iters == sum(h.pcg_iters for h in out.history)
     nu = 2.0
     for a, b in zip(out.history, out.history[1:]):
         if a.accepted:
@@ -189,3 +206,4 @@ def test_lm_survives_breakdowns():
             assert b.radius == a.radius / nu
             nu *= 2.0
     assert out.cost < out.cost0
+    assert abs(out.cost - res.cost) <= 1e-6 * res.cost

@@ -27,17 +27,26 @@ def _outliers(sc, frac=0.05, px=50.0, seed=9):
     return uv, a
 
 
+# Fixed bound on the relative difference of the Huber weight rho' between the
+# two sides. Above the threshold rho'(s) = a / |f|, so |d rho'| / rho' =
+# |df| / |f| with df the difference of the residuals, which the two sides
+# evaluate through different but equivalent rotation formulas (FP64, a few
+# ulps of the pixel scale f |p| ~ 1e2..1e3 px, i.e. ~1e-13 px) and |f| > a
+# (about 1 px here): ~1e-13. EPS_W leaves two orders of margin and is what
+# the tolerances use; the measured difference is only checked against it, so
+# a wrong GPU residual cannot widen its own tolerance.
+EPS_W = 1e-11
+
+
 def _weight_eps(sc, plan, uv, a):
-    """Largest relative difference of the Huber weight rho' between the two
-    sides, to first order: above the threshold rho'(s) = a / |f|, so
-    |d rho'| / rho' = |df| / |f|, with df the measured difference of the
-    residuals (the two sides evaluate the rotation by different, equivalent
-    formulas). Used only to widen the rounding tolerances."""
+    """Check the measured weight difference against EPS_W; return EPS_W."""
     f_g = host(plan.eval_jacobian(*inputs(sc, uv=uv))[0])
     f_o = residuals(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, uv)
     n = np.sqrt(np.sum(f_o * f_o, axis=1))
-    eps = np.where(n > a, np.linalg.norm(f_g - f_o, axis=1) / n, 0.0)
-    return float(eps.max())
+    eps = float(np.where(n > a, np.linalg.norm(f_g - f_o, axis=1) / n, 0.0).max())
+    print(f"[gpu] measured Huber weight difference {eps:.1e} (bound {EPS_W:.0e})", flush=True)
+    assert eps <= EPS_W
+    return EPS_W
 
 
 def _sc(name):
@@ -57,7 +66,7 @@ def test_huber_blocks_and_product(name):
     nrm = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, uv, loss="huber", loss_scale=a)
     w = robust.weights(residuals(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, uv), "huber", a)
     print(f"[gpu] {name} huber a={a:.3g}: {np.mean(w < 1):.2f} of observations down-weighted, "
-          f"weight difference {eps:.1e}", flush=True)
+          f"weight bound {eps:.0e}", flush=True)
     assert 0.2 < np.mean(w < 1) < 0.8
     # every weighted quantity is at most quadratic in the weights
     tol = TOL_U + 3 * eps

@@ -15,29 +15,54 @@ from tests._gpu import dev, host, inputs, plan_for, rel
 TOL_U = 1e-12
 
 
-def schur_abs(nrm, x):
+def _point_cond(nrm):
+    """cond_2(C_p) per point: C_p^-1 v amplifies a relative difference of C_p's
+    terms (the two sides' E blocks differ by a few ulps) by up to cond(C_p)."""
+    return np.linalg.cond(nrm.C)
+
+
+def schur_abs(nrm, x, cond=False):
     """|A||x| + |F|^T(|E|(|C^-1|(|E|^T(|F||x|)))): the sum of magnitudes of the
-    terms of S x, which bounds the rounding error of any evaluation order."""
+    terms of S x, which bounds the rounding error of any evaluation order.
+    cond=True adds cond(C_p) |C^-1 z_p| per point: the first-order effect of
+    C_p's input difference on u_p = C_p^-1 z_p, which dominates for points
+    whose C_p is ill-conditioned (short baselines)."""
     from oracle.normal import block_sum
     xa = np.abs(np.asarray(x)).reshape(nrm.n_cam, 9)
     F, E = np.abs(nrm.F), np.abs(nrm.E)
     s = np.einsum("nkj,nj->nk", F, xa[nrm.obs_cam])
     z = block_sum(nrm.obs_pt, np.einsum("nki,nk->ni", E, s), nrm.n_pt)
     u = np.einsum("pij,pj->pi", np.abs(nrm.Cinv), z)
+    if cond:
+        u = u + _point_cond(nrm)[:, None] * np.linalg.norm(u, axis=1, keepdims=True)
     w = np.einsum("nkj,nj->nk", E, u[nrm.obs_pt])
     y = block_sum(nrm.obs_cam, np.einsum("nki,nk->ni", F, w), nrm.n_cam)
     return np.einsum("cij,cj->ci", np.abs(nrm.A), xa) + y
 
 
-def rhs_abs(nrm):
-    """Magnitude bound of the terms of b = -g_c + W C^-1 g_p."""
+def rhs_abs(nrm, cond=False):
+    """Magnitude bound of the terms of b = -g_c + W C^-1 g_p (cond: as in
+    schur_abs, for v_p = C_p^-1 g_p)."""
     from oracle.normal import block_sum
     F, E, f = np.abs(nrm.F), np.abs(nrm.E), np.abs(nrm.f)
     gc = block_sum(nrm.obs_cam, np.einsum("nki,nk->ni", F, f), nrm.n_cam)
     gp = block_sum(nrm.obs_pt, np.einsum("nki,nk->ni", E, f), nrm.n_pt)
     v = np.einsum("pij,pj->pi", np.abs(nrm.Cinv), gp)
+    if cond:
+        v = v + _point_cond(nrm)[:, None] * np.linalg.norm(v, axis=1, keepdims=True)
     Y = np.einsum("nki,nkj->nij", F, E)
     return gc + block_sum(nrm.obs_cam, np.einsum("nij,nj->ni", Y, v[nrm.obs_pt]), nrm.n_cam)
+
+
+def block_jacobi_abs(nrm, cond=False):
+    """Magnitude bound of the terms of S_cc = A_c - sum_o Y_o C_p^-1 Y_o^T
+    (cond: C_p^-1's magnitudes scaled by 1 + cond(C_p))."""
+    from oracle.normal import block_sum
+    Ci = np.abs(nrm.Cinv)
+    if cond:
+        Ci = Ci * (1.0 + _point_cond(nrm))[:, None, None]
+    return np.abs(nrm.A) + block_sum(nrm.obs_cam, np.einsum("nij,njk,nlk->nil", np.abs(nrm.Y),
+                                                           Ci[nrm.obs_pt], np.abs(nrm.Y)), nrm.n_cam)
 
 
 def schur_abs_dense(nrm):
@@ -266,3 +291,120 @@ def test_hierarchy_numeric_matches_oracle():
     inv = host(plan.mg_level_data(nl - 1, "coarse_inverse"))
     ref = np.linalg.inv(Sc)
     assert np.abs(inv - ref).max() <= 1e-8 * np.abs(ref).max()
+
+
+def _full_rank(R, tol=1e-6):
+    d = np.abs(np.diag(R))
+    return d.min() >= tol * d.max()
+
+
+def test_nullspace_rows_match_oracle():
+    """Level-0 near-nullspace rows K (Section 3.1: 9 constant columns, then the
+    3 translations, 3 rotations and the scale of the world similarity) against
+    the oracle's, element by element. The rotation rows use J_r^-1, which the
+    oracle obtains by inverting J_r numerically and the GPU from its series."""
+    sc = scene("city200")
+    plan, opts = plan_for(sc, precond="mg", coarse_max_nodes=16)
+    plan.prepare(*inputs(sc), opts=opts)
+    from oracle.nullspace import camera_nullspace
+    K = host(plan.mg_level_data(0, "K"))
+    K_ref = camera_nullspace(sc.cams)
+    assert K.shape == K_ref.shape
+    err = np.abs(K - K_ref).max(axis=(1, 2)) / np.abs(K_ref).max(axis=(1, 2))
+    print(f"[gpu] K rows: max relative difference {err.max():.1e}", flush=True)
+    assert err.max() <= 1e-12
+
+
+def test_prolongator_and_coarse_operator_match_oracle():
+    """Tentative prolongation (Section 3.3) by value where it is unique: an
+    aggregate whose stacked near-nullspace rows K_a have full column rank has a
+    unique thin QR with diag(R) > 0, so its P blocks and coarse K rows (R) must
+    equal the oracle's; the Galerkin block S_1[a, b] = sum P_i^T S_ij P_j of two
+    such aggregates is then unique too (Section 2.3's coarse operator)."""
+    sc = scene("city200")
+    plan, opts = plan_for(sc, precond="mg", coarse_max_nodes=16)
+    plan.prepare(*inputs(sc), opts=opts)
+    nrm = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    lev = ostep.hierarchy_for(nrm, sc.cams, sc.obs_cam, sc.obs_pt, omg.MGOptions(coarse_max_nodes=16))
+    assert len(lev) >= 3
+    L0 = lev[0]
+    P = host(plan.mg_level_data(0, "P"))
+    Kc = host(plan.mg_level_data(1, "K"))
+    full = [a for a in range(L0.n_agg) if _full_rank(L0.Kc[a])]
+    print(f"[gpu] level 0: {len(full)} of {L0.n_agg} aggregates with full-rank K_a", flush=True)
+    assert len(full) >= L0.n_agg // 3
+    for a in full:
+        mem = np.nonzero(L0.agg == a)[0]
+        cond = np.linalg.cond(L0.Kc[a])
+        tol = 1e-13 * cond
+        assert np.abs(P[mem] - L0.Pb[mem]).max() <= tol
+        assert np.abs(Kc[a] - L0.Kc[a]).max() <= tol * np.abs(L0.Kc[a]).max()
+        assert np.all(np.diag(Kc[a]) >= 0)
+    # Galerkin blocks between full-rank aggregates, within the rounding of the
+    # triple product (|P|^T |S0 terms| |P|) plus the QR's sensitivity
+    # (|dP| <= 1e-13 cond(K_a) on both P factors)
+    S1 = host(plan.mg_level_data(1, "operator"))
+    S1_ref = lev[1].S.toarray()
+    Pabs = np.abs(L0.P.toarray())
+    B = Pabs.T @ schur_abs_dense(nrm) @ Pabs
+    n_cmp = 0
+    for a in full:
+        for b in full:
+            ia, ib = slice(16 * a, 16 * a + 16), slice(16 * b, 16 * b + 16)
+            if not np.any(S1_ref[ia, ib]):
+                continue
+            cond = max(np.linalg.cond(L0.Kc[a]), np.linalg.cond(L0.Kc[b]))
+            tol = (4 * TOL_U + 2e-13 * cond) * B[ia, ib]
+            assert np.all(np.abs(S1[ia, ib] - S1_ref[ia, ib]) <= tol)
+            n_cmp += 1
+    print(f"[gpu] level-1 Galerkin blocks compared by value: {n_cmp}", flush=True)
+    assert n_cmp >= len(full)
+
+
+def test_exact_tie_aggregation_on_gpu():
+    """The hand-worked exact tie (tests/golden: case exact_tie), built as a
+    visibility graph of points each seen by two cameras: the GPU's integer
+    strength comparison must group node 0 with node 1, where FP64 strengths
+    would pick node 2."""
+    import torch
+    from tests._fixtures import parse_aggregation_cases
+    case = next(c for c in parse_aggregation_cases() if c["name"] == "exact_tie")
+    oc, op = [], []
+    for i, j, w in case["edges"]:
+        for _ in range(w):
+            q = len(oc) // 2
+            oc += [i, j]
+            op += [q, q]
+    n_cam, n_pt = len(case["diag"]), len(oc) // 2
+    import paper_2007_01941_amd as bamg
+    opts = bamg.Options(precond="mg", coarse_max_nodes=2)
+    plan = bamg.Plan(n_cam, n_pt, dev(np.array(oc), torch.int32), dev(np.array(op), torch.int32), opts)
+    rp, col, val = (host(t) for t in plan.mg_covisibility(0))
+    W = np.zeros((n_cam, n_cam), dtype=np.int64)
+    for i in range(n_cam):
+        W[i, col[rp[i]:rp[i + 1]]] = val[rp[i]:rp[i + 1]]
+    from tests._fixtures import case_matrix
+    assert np.array_equal(W, case_matrix(case))
+    assert list(host(plan.mg_aggregates(0))) == case["expect"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_deterministic_mode_is_bitwise_reproducible(precision):
+    """deterministic = 1: no floating-point atomics, so two steps on the same
+    inputs are bitwise equal; the step still matches the default mode's to
+    the solve tolerance."""
+    sc = scene("city200")
+    plan, opts = plan_for(sc, precond="mg", precision=precision, rtol=1e-10, coarse_max_nodes=16,
+                          deterministic=True)
+    runs = [tuple(host(t) for t in plan.lm_step(*inputs(sc))[:2]) for _ in range(3)]
+    for dc, dp in runs[1:]:
+        assert np.array_equal(dc, runs[0][0]) and np.array_equal(dp, runs[0][1])
+    import torch
+    x = torch.as_tensor(np.random.default_rng(1).normal(size=(sc.n_cam, 9)), device="cuda")
+    ys = [host(plan.schur_apply(x, precision)) for _ in range(3)]
+    assert all(np.array_equal(y, ys[0]) for y in ys[1:])
+    plan_f, _ = plan_for(sc, precond="mg", precision=precision, rtol=1e-10, coarse_max_nodes=16)
+    dc_f, dp_f, _ = plan_f.lm_step(*inputs(sc))
+    print(f"[gpu] deterministic vs default ({precision}): {rel(runs[0][0], host(dc_f)):.1e}", flush=True)
+    assert rel(runs[0][0], host(dc_f)) <= 1e-6
+    assert rel(runs[0][1], host(dp_f)) <= 1e-6
