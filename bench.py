@@ -10,6 +10,13 @@ and back-substitution. Inputs are resident in HBM before timing starts; the
 integer plan (layout, covisibility, aggregation) is built once beforehand, as
 in an LM loop over a fixed visibility graph, and timed separately.
 
+Besides the headline workload the default run measures two more scenes, each
+in its own entry of "legs": the long path without loop closures (10,000
+cameras, ~25M observations), where the precision form (FP32 product and
+V-cycle inside FP64 refinement) is compared with the FP64 path, and the
+largest single-GPU scene (30,000 cameras, ~78M observations), measured in
+the precision form with the adjoint solve.
+
 Prints ONE JSON line (the driver's contract); see the design doc for the fields.
 """
 import argparse
@@ -25,7 +32,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RCS solve s to rtol 1e-6 (MG vs block-Jacobi, FP32 vs FP64); matvec GB/s"
 HBM_PEAK_GBPS = 8000.0
-PROFILE_PMC = os.path.join(ROOT, "profiles", "k_schur_tiles_city2k_traffic.txt")
+PROFILE_DIR = os.path.join(ROOT, "profiles")
 WORKLOADS = {
     "city2k": "city-grid street-view scene",
     "path10k": "5 km street path without loop closures",
@@ -58,22 +65,188 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM traffic per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
-    if not os.path.exists(PROFILE_PMC):
+def read_traffic(scene, prec):
+    """HBM bytes per launch of k_schur_tiles<prec> on `scene` from the committed
+    rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy
+    kernel), if it was taken on the current kernel source; else None."""
+    path = os.path.join(PROFILE_DIR, f"k_schur_tiles_{scene}_traffic.txt")
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(PROFILE_PMC):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha") != kernel_source_hash():
         return None
     try:
-        return float(vals["traffic_bytes_per_launch"])
+        return float(vals[f"traffic_bytes_per_launch_{prec}"])
     except (KeyError, ValueError):
         return None
+
+
+def to_device(sc, torch, dev):
+    T = lambda a, dt=torch.float64: torch.as_tensor(__import__("numpy").ascontiguousarray(a), dtype=dt, device=dev)
+    return T(sc.cams), T(sc.pts), T(sc.uv), T(sc.obs_cam, torch.int32), T(sc.obs_pt, torch.int32)
+
+
+def time_steps(plan, cams, pts, uv, opts, steps, warmup):
+    """Whole LM steps, timed with HIP events around `steps` back-to-back calls.
+    Returns (ms per step, wall s, stats of the last step, dc, dp)."""
+    import torch
+    for _ in range(warmup):
+        plan.lm_step(cams, pts, uv, opts=opts)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_wall = time.time()
+    ev0.record()
+    for _ in range(steps):
+        dc, dp, st = plan.lm_step(cams, pts, uv, opts=opts)
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / steps, time.time() - t_wall, st, dc, dp
+
+
+def time_launches(fn, reps):
+    """Seconds per call of fn (device work enqueued on the current stream)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def measure_products(bamg, plan, sc, cams, pts, uv, base, reps=50):
+    """The implicit Schur product (A x included) per precision, and the tile
+    kernel alone (k_schur_tiles: y -= W C^-1 W^T x, one launch per call) with
+    its roofline per precision."""
+    import torch
+    x = torch.randn(sc.n_cam, 9, dtype=torch.float64, device="cuda:0")
+    y = torch.zeros_like(x)
+    mat, roof = {}, {}
+    for prec, s, mode in (("fp64", 8, "fp64"), ("fp32", 4, "mixed")):
+        plan.prepare(cams, pts, uv, opts=bamg.Options(precond="bj", precision=mode, **base))
+        t = time_launches(lambda: plan.schur_apply(x, mode), reps)
+        B = schur_bytes(sc.n_obs, sc.n_pt, sc.n_cam, s)
+        mat[prec] = {"s_per_apply": t, "algorithmic_bytes": B, "GBps": B / t / 1e9}
+        tk = time_launches(lambda: plan.schur_offdiag_apply(x, y, mode), reps)
+        Bk = kernel_bytes(sc.n_obs, sc.n_pt, sc.n_cam, s)
+        a = Bk / tk / 1e9
+        kname = "double" if prec == "fp64" else "float"
+        roof[prec] = {"kernel": f"k_schur_tiles<{kname}>: y -= W C^-1 W^T x (implicit Schur product)",
+                      "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                      "frac": a / HBM_PEAK_GBPS, "traffic": read_traffic(sc.name, prec),
+                      "algorithmic_bytes": Bk, "s_per_launch": tk}
+        log(f"[bench] {sc.name} Schur product {prec}: {t * 1e6:.1f} us/apply ({B / t / 1e9:.0f} GB/s); "
+            f"tile kernel {tk * 1e6:.1f} us/launch, {a:.0f} GB/s = {a / HBM_PEAK_GBPS:.3f} of peak")
+    return mat, roof
+
+
+def step_entry(ms, st, dc=None, ref=None):
+    import torch
+    e = {"s_per_step": ms / 1e3, "pcg_iters": st.iters, "refine_steps": st.refine_steps,
+         "fp64_fallback": st.fallback_fp64, "rel_res": st.rel_res,
+         "phases_ms": {"jacobian_and_blocks": st.t_jacobian_ms, "setup": st.t_setup_ms, "solve": st.t_solve_ms}}
+    if dc is not None and ref is not None:
+        e["rel_diff_vs_mg_fp64"] = float(torch.linalg.norm(dc - ref) / torch.linalg.norm(ref))
+    return e
+
+
+def true_residual(plan, bamg, cams, pts, uv, dc, base):
+    """|b - S dc| / |b| with the FP64 product of a freshly prepared FP64 step."""
+    import torch
+    plan.prepare(cams, pts, uv, opts=bamg.Options(precond="bj", precision="fp64", **base))
+    b = plan.step_blocks()[0]
+    r = b - plan.schur_apply(dc.contiguous(), "fp64")
+    return float(torch.linalg.norm(r) / torch.linalg.norm(b))
+
+
+def run_leg(bamg, name, cache, steps, warmup):
+    """One extra workload: multigrid and block Jacobi in FP64 and in the
+    precision form, the products and tile-kernel rooflines, the true residual
+    of each step under the FP64 product, and (largest scene) the adjoint."""
+    import torch
+    from scenes import cached_scene
+    t0 = time.time()
+    sc = cached_scene(name, cache)
+    log(f"[bench] leg {name}: scene {sc.summary()} ready in {time.time() - t0:.1f}s")
+    cams, pts, uv, oc, op = to_device(sc, torch, "cuda:0")
+    base = dict(rtol=1e-6, max_iter=5000)
+    t0 = time.time()
+    plan = bamg.Plan(sc.n_cam, sc.n_pt, oc, op, bamg.Options(precond="mg", **base))
+    torch.cuda.synchronize()
+    leg = {"workload": f"{name}: {WORKLOADS[name]}, {sc.n_cam} cameras, {sc.n_pt} points, {sc.n_obs} "
+                       f"observations (seeded)",
+           "plan_s": time.time() - t0, "levels": plan.mg_levels(),
+           "device_GiB": plan.device_bytes / 2 ** 30}
+    log(f"[bench] leg {name}: plan {leg['plan_s']:.1f}s, levels {leg['levels']}, {leg['device_GiB']:.1f} GiB")
+    runs = {}
+    ref = None
+    for key, pc, prec, n, w in (("mg_fp64", "mg", "fp64", steps, warmup), ("mg_mixed", "mg", "mixed", steps, warmup),
+                                ("bj_fp64", "bj", "fp64", 1, 1), ("bj_mixed", "bj", "mixed", 1, 1)):
+        o = bamg.Options(precond=pc, precision=prec, **base)
+        ms, _, st, dc, dp = time_steps(plan, cams, pts, uv, o, n, w)
+        if key == "mg_fp64":
+            ref = dc.clone()
+        runs[key] = step_entry(ms, st, dc, ref)
+        runs[key]["true_rel_res"] = true_residual(plan, bamg, cams, pts, uv, dc, base)
+        log(f"[bench] leg {name} {key}: {ms:.2f} ms/step, iters {st.iters} (refine {st.refine_steps}), "
+            f"true residual {runs[key]['true_rel_res']:.2e}")
+        if key == "mg_mixed":
+            dc_m, dp_m = dc.clone(), dp.clone()
+    leg["steps"] = runs
+    leg["matvec"], leg["roofline"] = measure_products(bamg, plan, sc, cams, pts, uv, base)
+    if name == "city30k":
+        # the differentiation form in the precision form: backward of the step
+        # (loss |delta|^2), adjoint PCG with the same hierarchy
+        mixed = bamg.Options(precond="mg", precision="mixed", **base)
+        bw = []
+        for i in range(2):
+            torch.cuda.synchronize()
+            t1 = time.time()
+            g = plan.backward(cams, pts, uv, dc_m, dp_m, 2 * dc_m, 2 * dp_m, opts=mixed)
+            torch.cuda.synchronize()
+            if i > 0:
+                bw.append(time.time() - t1)
+        gst = g[3]
+        leg["adjoint"] = {"s_per_backward": sum(bw) / len(bw), "pcg_iters": gst.iters,
+                          "adjoint_solve_and_gradients_ms": gst.t_solve_ms,
+                          "setup_ms": gst.t_setup_ms, "jacobian_and_blocks_ms": gst.t_jacobian_ms}
+        log(f"[bench] leg {name} adjoint: {leg['adjoint']['s_per_backward'] * 1e3:.1f} ms "
+            f"(solve and gradients {gst.t_solve_ms:.1f} ms, {gst.iters} PCG)")
+    del plan
+    torch.cuda.empty_cache()
+    return leg
+
+
+def kernel_only(bamg, name, cache, reps):
+    """Only the tile kernel, for counter collection: reps launches of
+    k_schur_tiles<double>, then of k_schur_tiles<float>, on `name`."""
+    import torch
+    from scenes import cached_scene
+    sc = cached_scene(name, cache)
+    cams, pts, uv, oc, op = to_device(sc, torch, "cuda:0")
+    base = dict(rtol=1e-6, max_iter=5000)
+    plan = bamg.Plan(sc.n_cam, sc.n_pt, oc, op, bamg.Options(precond="bj", **base))
+    x = torch.randn(sc.n_cam, 9, dtype=torch.float64, device="cuda:0")
+    y = torch.zeros_like(x)
+    out = {"scene": name, "reps": reps}
+    for prec, mode, s in (("fp64", "fp64", 8), ("fp32", "mixed", 4)):
+        plan.prepare(cams, pts, uv, opts=bamg.Options(precond="bj", precision=mode, **base))
+        torch.cuda.synchronize()
+        for _ in range(reps):
+            plan.schur_offdiag_apply(x, y, mode)
+        torch.cuda.synchronize()
+        out[f"algorithmic_bytes_{prec}"] = kernel_bytes(sc.n_obs, sc.n_pt, sc.n_cam, s)
+    out["kernel_source_sha"] = kernel_source_hash()
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -84,6 +257,12 @@ def main():
     ap.add_argument("--scene", default="city2k")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-legs", action="store_true", help="skip the long-path and largest-scene legs")
+    ap.add_argument("--legs", default="path10k,city30k", help="comma-separated extra workloads")
+    ap.add_argument("--scene-cache", default=None,
+                    help="directory for generated scenes (npz), reused by later runs on the same machine")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="only launch the Schur tile kernel (FP64 then FP32) on --scene, for counters")
     ap.add_argument("--lm-iters", type=int, default=100, help="iteration cap of the LM loop runs (100 as in the paper)")
     ap.add_argument("--scaling", default=None,
                     help="comma-separated k: run the scaling study on k x k city grids with a sine-wave "
@@ -112,7 +291,11 @@ def main():
         return
 
     import paper_2007_01941_amd as bamg
-    from scenes import make_scene
+    from scenes import cached_scene
+
+    if args.kernel_only:
+        kernel_only(bamg, args.scene, args.scene_cache, 5)
+        return
 
     if args.scaling:
         ks = [int(k) for k in args.scaling.split(",")]
@@ -124,11 +307,9 @@ def main():
 
     dev = torch.device("cuda:0")
     t0 = time.time()
-    sc = make_scene(args.scene)
-    log(f"[bench] scene {sc.summary()} generated in {time.time() - t0:.1f}s")
-    T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
-    cams, pts, uv = T(sc.cams), T(sc.pts), T(sc.uv)
-    oc, op = T(sc.obs_cam, torch.int32), T(sc.obs_pt, torch.int32)
+    sc = cached_scene(args.scene, args.scene_cache)
+    log(f"[bench] scene {sc.summary()} ready in {time.time() - t0:.1f}s")
+    cams, pts, uv, oc, op = to_device(sc, torch, dev)
     torch.cuda.synchronize()
 
     base = dict(rtol=1e-6, max_iter=5000)
@@ -139,27 +320,9 @@ def main():
     log(f"[bench] plan built in {plan_s:.2f}s, levels {plan.mg_levels()}, "
         f"device bytes {plan.device_bytes / 2**30:.2f} GiB")
 
-    def run(opts, steps, warmup):
-        for _ in range(warmup):
-            plan.lm_step(cams, pts, uv, opts=opts)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        stats = []
-        t_wall = time.time()
-        ev0.record()
-        for _ in range(steps):
-            dc, dp, st = plan.lm_step(cams, pts, uv, opts=opts)
-            stats.append(st)
-        ev1.record()
-        torch.cuda.synchronize()
-        wall = time.time() - t_wall
-        ms = ev0.elapsed_time(ev1) / steps
-        return ms, wall, stats, dc, dp
-
     # ---- headline: MG, FP64
     mg64 = bamg.Options(precond="mg", precision="fp64", **base)
-    ms, wall, stats, dc, dp = run(mg64, args.steps, args.warmup)
-    st = stats[-1]
+    ms, wall, st, dc, dp = time_steps(plan, cams, pts, uv, mg64, args.steps, args.warmup)
     log(f"[bench] MG FP64: {ms:.2f} ms/step (iters {st.iters}, rel_res {st.rel_res:.2e}, "
         f"jac {st.t_jacobian_ms:.2f} setup {st.t_setup_ms:.2f} solve {st.t_solve_ms:.2f} ms)")
     result = {
@@ -176,51 +339,11 @@ def main():
         "plan_s": plan_s,
     }
 
-    # ---- dominant kernel: implicit Schur product, timed on the library's stream
-    stream = torch.cuda.current_stream()
-    x = torch.randn(sc.n_cam, 9, dtype=torch.float64, device=dev)
-    mat = {}
-    for prec, s in (("fp64", 8), ("fp32", 4)):
-        opts = bamg.Options(precond="bj", precision="fp64" if prec == "fp64" else "mixed", **base)
-        plan.prepare(cams, pts, uv, opts=opts)
-        for _ in range(3):
-            plan.schur_apply(x, "fp64" if prec == "fp64" else "mixed")
-        reps = 50
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record(stream)
-        for _ in range(reps):
-            plan.schur_apply(x, "fp64" if prec == "fp64" else "mixed")
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) / reps / 1e3
-        B = schur_bytes(sc.n_obs, sc.n_pt, sc.n_cam, s)
-        mat[prec] = {"s_per_apply": t, "algorithmic_bytes": B, "GBps": B / t / 1e9}
-        log(f"[bench] Schur product {prec}: {t * 1e6:.1f} us/apply, {B / t / 1e9:.0f} GB/s")
+    # ---- dominant kernel: the Schur tile kernel, timed on the library's stream
+    mat, roof = measure_products(bamg, plan, sc, cams, pts, uv, base)
     result["matvec"] = mat
-    # the dominant kernel alone (k_schur_tiles<double>: y -= W C^-1 W^T x), one launch per call
-    plan.prepare(cams, pts, uv, opts=bamg.Options(precond="bj", precision="fp64", **base))
-    y = torch.zeros_like(x)
-    for _ in range(3):
-        plan.schur_offdiag_apply(x, y)
-    reps = 50
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(reps):
-        plan.schur_offdiag_apply(x, y)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    tk = e0.elapsed_time(e1) / reps / 1e3
-    Bk = kernel_bytes(sc.n_obs, sc.n_pt, sc.n_cam, 8)
-    log(f"[bench] k_schur_tiles<double>: {tk * 1e6:.1f} us/launch, {Bk / tk / 1e9:.0f} GB/s")
-    # the committed counter summary was taken on the city-grid workload
-    traffic = read_traffic() if sc.name == "city2k" else None
-    a = Bk / tk / 1e9
-    result["roofline"] = {"kernel": "k_schur_tiles<double>: y -= W C^-1 W^T x (implicit Schur product)",
-                          "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                          "frac": a / HBM_PEAK_GBPS, "traffic": traffic,
-                          "algorithmic_bytes": Bk, "s_per_launch": tk}
+    result["roofline"] = roof["fp64"]
+    result["roofline_fp32"] = roof["fp32"]
 
     # ---- comparison variants
     if not args.no_variants:
@@ -228,15 +351,11 @@ def main():
         for name, opts in (("bj_fp64", bamg.Options(precond="bj", precision="fp64", **base)),
                            ("cj_fp64", bamg.Options(precond="cj", precision="fp64", **base)),
                            ("mg_mixed", bamg.Options(precond="mg", precision="mixed", **base)),
-                           ("bj_mixed", bamg.Options(precond="bj", precision="mixed", **base))):
-            vms, _, vst, vdc, _ = run(opts, max(2, args.steps // 2), 1)
-            s2 = vst[-1]
-            var[name] = {"s_per_step": vms / 1e3, "pcg_iters": s2.iters, "refine_steps": s2.refine_steps,
-                         "fp64_fallback": s2.fallback_fp64,
-                         "rel_res": s2.rel_res, "phases_ms": {"jacobian_and_blocks": s2.t_jacobian_ms,
-                                                              "setup": s2.t_setup_ms,
-                                                              "solve": s2.t_solve_ms},
-                         "rel_diff_vs_mg_fp64": float(torch.linalg.norm(vdc - dc) / torch.linalg.norm(dc))}
+                           ("bj_mixed", bamg.Options(precond="bj", precision="mixed", **base)),
+                           ("mg_fp64_deterministic", bamg.Options(precond="mg", precision="fp64",
+                                                                  deterministic=True, **base))):
+            vms, _, s2, vdc, _ = time_steps(plan, cams, pts, uv, opts, max(2, args.steps // 2), 1)
+            var[name] = step_entry(vms, s2, vdc, dc)
             log(f"[bench] {name}: {vms:.2f} ms/step, iters {s2.iters}, rel_res {s2.rel_res:.2e}")
         result["variants"] = var
 
@@ -283,6 +402,13 @@ def main():
     # ---- CPU baseline: the oracle on a bounded sample of the same workload
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(sc, st.iters)
+
+    # ---- the other workloads of the metric, each on its own plan
+    del plan
+    torch.cuda.empty_cache()
+    if not args.no_legs:
+        result["legs"] = {name: run_leg(bamg, name, args.scene_cache, 3, 1)
+                          for name in args.legs.split(",") if name and name != sc.name}
     print(json.dumps(result), flush=True)
 
 
@@ -400,19 +526,21 @@ def subsample_points(sc, every):
     return (sc.cams, sc.pts[keep], sc.obs_cam[m], remap[sc.obs_pt[m]].astype(np.int32), sc.uv[m])
 
 
-def cpu_baseline(sc, gpu_iters):
-    """The oracle (numpy/scipy FP64, as written) timed on a bounded sample of the
-    workload: every 4th point of the same scene with all its cameras. Residual,
-    Jacobian and normal blocks, the multigrid hierarchy setup, and 3 MG-PCG
-    iterations are timed; every phase scales with the observation count, so the
-    per-step estimate scales them by n_obs(full)/n_obs(sample) and the
-    iterations to the GPU's iteration count."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample_run(cams, pts, oc, op, uv, sample_iters):
+    """The oracle's phases on one sample: (jacobian s, setup s, s per MG-PCG
+    iteration, CPU seconds used, wall seconds)."""
     from oracle import multigrid as omg
     from oracle import step as ostep
-
-    log("[bench] oracle CPU baseline on a point subsample ...")
-    cams, pts, oc, op, uv = subsample_points(sc, 4)
-    scale = sc.n_obs / oc.shape[0]
     r0 = resource.getrusage(resource.RUSAGE_SELF)
     w0 = time.time()
     t = time.time()
@@ -422,23 +550,48 @@ def cpu_baseline(sc, gpu_iters):
     t = time.time()
     levels = ostep.hierarchy_for(nrm, cams, oc, op, omg.MGOptions())
     t_setup = time.time() - t
-    sample_iters = 3
     t = time.time()
     omg.pcg(nrm.S_apply, lambda r: omg.vcycle(levels, r), b, 1e-30, max_iter=sample_iters)
     t_iter = (time.time() - t) / sample_iters
     wall = time.time() - w0
     r1 = resource.getrusage(resource.RUSAGE_SELF)
     cpu = (r1.ru_utime - r0.ru_utime) + (r1.ru_stime - r0.ru_stime)
-    est = scale * (t_jac + t_setup + gpu_iters * t_iter)
-    log(f"[bench] oracle sample: jac {t_jac:.1f}s setup {t_setup:.1f}s {t_iter:.2f}s/iter "
-        f"(x{scale:.2f}) -> {est:.1f}s per step at {gpu_iters} iterations")
-    return {"value": est, "unit": "s", "cores": round(cpu / wall, 2), "kind": "oracle",
+    return t_jac, t_setup, t_iter, cpu, wall
+
+
+def cpu_baseline(sc, gpu_iters):
+    """The oracle (numpy/scipy FP64, as written) timed on a bounded sample of the
+    workload: every 4th point of the same scene with all its cameras. Residual,
+    Jacobian and normal blocks, the multigrid hierarchy setup, and 3 MG-PCG
+    iterations are timed, once with the host's default thread count (all cores
+    available to BLAS) and once restricted to one thread; every phase scales
+    with the observation count, so the per-step estimate scales them by
+    n_obs(full)/n_obs(sample) and the iterations to the GPU's iteration count."""
+    from threadpoolctl import threadpool_limits
+
+    log("[bench] oracle CPU baseline on a point subsample ...")
+    cams, pts, oc, op, uv = subsample_points(sc, 4)
+    scale = sc.n_obs / oc.shape[0]
+    sample_iters = 3
+    out = {}
+    for key, limit in (("all_cores", None), ("one_thread", 1)):
+        with threadpool_limits(limits=limit):
+            t_jac, t_setup, t_iter, cpu, wall = oracle_sample_run(cams, pts, oc, op, uv, sample_iters)
+        est = scale * (t_jac + t_setup + gpu_iters * t_iter)
+        out[key] = {"s_per_step": est, "cores": round(cpu / wall, 2), "sample_wall_s": round(wall, 1),
+                    "phases_s": {"jacobian_and_blocks": scale * t_jac, "mg_setup": scale * t_setup,
+                                 "pcg": scale * gpu_iters * t_iter, "per_pcg_iteration": scale * t_iter}}
+        log(f"[bench] oracle ({key}): jac {t_jac:.1f}s setup {t_setup:.1f}s {t_iter:.2f}s/iter "
+            f"(x{scale:.2f}) -> {est:.1f}s per step at {gpu_iters} iterations, {cpu / wall:.2f} cores")
+    a = out["all_cores"]
+    return {"value": a["s_per_step"], "unit": "s", "cores": a["cores"], "kind": "oracle",
             "sample": (f"oracle (numpy/scipy FP64) on every 4th point of {sc.name} with all "
                        f"{sc.n_cam} cameras ({oc.shape[0]} of {sc.n_obs} observations): residual, "
-                       f"Jacobian and normal blocks {t_jac:.1f}s, multigrid setup {t_setup:.1f}s, "
-                       f"{t_iter:.2f}s per MG-PCG iteration; scaled by the observation ratio "
-                       f"{scale:.2f} and to the GPU's {gpu_iters} iterations"),
-            "host_cpus": os.cpu_count(), "sample_wall_s": round(wall, 1)}
+                       f"Jacobian and normal blocks, multigrid setup and {sample_iters} MG-PCG iterations "
+                       f"timed; scaled by the observation ratio {scale:.2f} and to the GPU's {gpu_iters} "
+                       f"iterations"),
+            "phases_s": a["phases_s"], "one_thread": out["one_thread"], "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(), "sample_wall_s": a["sample_wall_s"]}
 
 
 if __name__ == "__main__":

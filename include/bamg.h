@@ -330,12 +330,6 @@ ba_status ba_cost(ba_plan* p, const ba_opts* o, const double* cams, const double
 ba_status ba_lm_solve(ba_plan* p, const ba_opts* o, const ba_lm_opts* lo, double* cams, double* pts,
                       const double* uv, ba_lm_iter* history, ba_lm_summary* summary, void* stream);
 
-/* Self-test of the FP64 matrix-core tile products the coarse factorization is
- * built from: C += X Y^T (mode 0), C += X^T Y (mode 1), C += X Y (mode 2), with
- * X, Y, C 16 x 16 row-major device arrays. Lets a test confirm the operand
- * layout of the MFMA 16x16x4 FP64 instruction on the running GPU. */
-ba_status ba_selftest_tile_mma(const double* X, const double* Y, double* C, int32_t mode, void* stream);
-
 const char* ba_status_str(ba_status e);
 const char* ba_last_error(void);
 

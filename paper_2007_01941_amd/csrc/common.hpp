@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/bamg.h"
+#include "../../include/bamg_selftest.h"
 
 namespace bamg {
 

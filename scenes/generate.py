@@ -417,3 +417,27 @@ def tiny_scene(n_cam, n_pt, seed, k_min=2, k_max=None, shuffle=True) -> Scene:
         sc.obs_cam, sc.obs_pt = sc.obs_cam[perm], sc.obs_pt[perm]
         sc.uv, sc.uv_clean = sc.uv[perm], sc.uv_clean[perm]
     return sc
+
+
+# ---------------------------------------------------------------- cache
+
+_FIELDS = ("cams_true", "pts_true", "cams", "pts", "obs_cam", "obs_pt", "uv", "uv_clean")
+
+
+def cached_scene(name: str, cache_dir: str | None) -> Scene:
+    """make_scene(name), kept as <cache_dir>/<name>.npz (plain arrays, no pickled
+    objects) so that repeated runs on one machine skip the generation. With
+    cache_dir None the scene is generated every time."""
+    import os
+    if not cache_dir:
+        return make_scene(name)
+    path = os.path.join(cache_dir, f"{name}.npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            return Scene(name, *(z[f] for f in _FIELDS))
+    sc = make_scene(name)
+    os.makedirs(cache_dir, exist_ok=True)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **{f: getattr(sc, f) for f in _FIELDS})
+    os.replace(tmp, path)
+    return sc

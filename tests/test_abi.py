@@ -7,12 +7,12 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "bamg.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("bamg.h", "bamg_selftest.h")]
 LIB = os.path.join(ROOT, "paper_2007_01941_amd", "libbamg.so")
 
 
 def declared():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(ba_[a-z0-9_]+)\s*\(", src)))
 
