@@ -101,24 +101,24 @@ template <> struct Planes<float> {
   static const float* Cinv(const ba_plan* P) { return P->Cinv32.p; }
 };
 
-// With P->det (deterministic step) the tile kernel stores its (tile, camera)
-// sums and k_schur_gather adds them in tile order; otherwise it adds them to y
-// with atomics.
+// With P->det (deterministic step) the group kernel stores its (group,
+// camera) sums and k_schur_gather adds them in group order; otherwise it adds
+// them to y with atomics.
 template <class T>
 static void schur_tiles_dev(ba_plan* P, const T* x, T* y, const int* done, hipStream_t s) {
   if (P->det) {
     T* part = te_part_of<T>(P);
-    hipLaunchKernelGGL((k_schur_tiles<T, true>), dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p,
-                       P->tile_pt.p, P->tile_coff.p, P->tile_cams.p, P->tile_cseg.p, P->pt_off.p, P->obs_slot.p,
-                       Planes<T>::F(P), Planes<T>::E(P), P->n_obs_pad, Planes<T>::Cinv(P), x, y, part, P->n_tiles,
-                       done);
-    hipLaunchKernelGGL((k_schur_gather<T>), dim3(ceil_div(9 * P->n_cam, 252)), dim3(256), 0, s, P->n_cam,
+    hipLaunchKernelGGL((k_schur_groups<T, true>), dim3(xcd_grid(P->n_groups)), dim3(256), 0, s, P->grp_tile.p,
+                       P->grp_coff.p, P->grp_cams.p, P->tile_obs.p, P->tile_pt.p, P->tile_coff.p, P->tile_cseg.p,
+                       P->tile_cslot.p, P->pt_off.p, P->obs_slot.p, Planes<T>::F(P), Planes<T>::E(P), P->n_obs_pad,
+                       Planes<T>::Cinv(P), x, y, part, P->n_groups, done);
+    hipLaunchKernelGGL((k_schur_gather<T>), dim3(ceil_div(P->n_cam, 4)), dim3(256), 0, s, P->n_cam,
                        P->cam_te_ptr.p, P->cam_te.p, (const T*)part, y, done);
   } else {
-    hipLaunchKernelGGL((k_schur_tiles<T, false>), dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p,
-                       P->tile_pt.p, P->tile_coff.p, P->tile_cams.p, P->tile_cseg.p, P->pt_off.p, P->obs_slot.p,
-                       Planes<T>::F(P), Planes<T>::E(P), P->n_obs_pad, Planes<T>::Cinv(P), x, y, (T*)nullptr,
-                       P->n_tiles, done);
+    hipLaunchKernelGGL((k_schur_groups<T, false>), dim3(xcd_grid(P->n_groups)), dim3(256), 0, s, P->grp_tile.p,
+                       P->grp_coff.p, P->grp_cams.p, P->tile_obs.p, P->tile_pt.p, P->tile_coff.p, P->tile_cseg.p,
+                       P->tile_cslot.p, P->pt_off.p, P->obs_slot.p, Planes<T>::F(P), Planes<T>::E(P), P->n_obs_pad,
+                       Planes<T>::Cinv(P), x, y, (T*)nullptr, P->n_groups, done);
   }
 }
 

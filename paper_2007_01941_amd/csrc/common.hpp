@@ -106,7 +106,8 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 constexpr int TILE_OBS = 256;     // observations per tile (one per thread)
 constexpr int S0_CHUNK = 128;    // shared points per wave in the explicit level-0 S
 constexpr int PREC = 16;         // doubles per point record (X 3, C^-1 6, C^-1 g_p 3, padding)
-constexpr int TILE_SLOTS = 96;    // cameras of a tile kept in LDS (others go to global atomics)
+constexpr int GROUP_SLOTS = 96;   // cameras of a tile group kept in LDS (others go to global memory)
+constexpr int GROUP_TILES = 8;    // most tiles in one group of the Schur product
 
 // Block size of the MG levels above level 0 (16 near-nullspace columns, Section 3.3).
 constexpr int NS = 16;

@@ -145,6 +145,46 @@ static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
   }
   P->n_tiles = n_tiles;
   P->max_tile_cams = max_tc;
+  // Groups of consecutive tiles for the Schur product: a group takes tiles
+  // while it has fewer than G of them and the union of their cameras fits
+  // GROUP_SLOTS; a tile of one point with more than TILE_OBS observations is a
+  // group of its own. Grouping saves atomics but costs parallelism: G keeps at
+  // least ~8192 workgroups (about six per compute unit) per product.
+  const int G = std::max(1, std::min(GROUP_TILES, n_tiles / 8192));
+  std::vector<int32_t> g_tile{0}, g_coff{0}, g_cams, t_cslot(t_cams.size());
+  {
+    std::vector<int32_t> gmark(n_cam, -1), gslot(n_cam, 0);
+    int gid = 0, g_n = 0, g_u = 0;
+    bool g_big = false;
+    for (int t = 0; t < n_tiles; ++t) {
+      const bool big = t_obs[t + 1] - t_obs[t] > TILE_OBS;
+      int add = 0;
+      for (int e = t_coff[t]; e < t_coff[t + 1]; ++e) add += gmark[t_cams[e]] != gid;
+      if (g_n > 0 && (big || g_big || g_n >= G || g_u + add > GROUP_SLOTS)) {
+        g_tile.push_back(t);
+        g_coff.push_back((int32_t)g_cams.size());
+        ++gid;
+        g_n = g_u = 0;
+      }
+      for (int e = t_coff[t]; e < t_coff[t + 1]; ++e) {
+        const int c = t_cams[e];
+        if (gmark[c] != gid) {
+          gmark[c] = gid;
+          gslot[c] = g_u++;
+          g_cams.push_back(c);
+        }
+        t_cslot[e] = gslot[c];
+      }
+      for (int64_t o = t_obs[t]; o < t_obs[t + 1]; ++o)
+        slot[o] = (slot[o] & ~0xffffu) | (uint32_t)gslot[P->h_obs_cam[o]];
+      ++g_n;
+      g_big = big;
+    }
+    g_tile.push_back(n_tiles);
+    g_coff.push_back((int32_t)g_cams.size());
+    BA_CHECK(g_cams.size() < (size_t)INT32_MAX / 9, BA_ERR_LIMIT, "too many group camera entries");
+  }
+  P->n_groups = (int32_t)g_tile.size() - 1;
   P->max_pt_obs = max_k;
   // upload
   std::vector<int32_t> pt_off32(P->h_pt_off.begin(), P->h_pt_off.end());
@@ -168,15 +208,19 @@ static void build_observation_layout(ba_plan* P, const std::vector<int32_t>& oc,
   P->tile_coff.upload(t_coff, s);
   P->tile_cams.upload(t_cams, s);
   P->tile_cseg.upload(t_cseg, s);
+  P->tile_cslot.upload(t_cslot, s);
   P->obs_slot.upload(slot, s);
+  P->grp_tile.upload(g_tile, s);
+  P->grp_coff.upload(g_coff, s);
+  P->grp_cams.upload(g_cams, s);
   {
-    // per camera, its entries of tile_cams in tile order (deterministic product)
-    std::vector<int32_t> tptr(n_cam + 1, 0), te(t_cams.size());
-    for (int32_t c : t_cams) ++tptr[c + 1];
+    // per camera, its entries of grp_cams in group order (deterministic product)
+    std::vector<int32_t> tptr(n_cam + 1, 0), te(g_cams.size());
+    for (int32_t c : g_cams) ++tptr[c + 1];
     for (int c = 0; c < n_cam; ++c) tptr[c + 1] += tptr[c];
     std::vector<int32_t> cur(tptr.begin(), tptr.end() - 1);
-    for (size_t e = 0; e < t_cams.size(); ++e) te[cur[t_cams[e]]++] = (int32_t)e;
-    P->n_te = (int32_t)t_cams.size();
+    for (size_t e = 0; e < g_cams.size(); ++e) te[cur[g_cams[e]]++] = (int32_t)e;
+    P->n_te = (int32_t)g_cams.size();
     P->cam_te_ptr.upload(tptr, s);
     P->cam_te.upload(te, s);
   }
@@ -276,15 +320,16 @@ static void build_s0_pairs(ba_plan* P, const Level& L0, hipStream_t s) {
       ce.push_back((int32_t)e);
       cb.push_back(h);
     }
-  std::vector<int32_t> be, bb;
-  for (int64_t e = 0; e < L0.nnz; ++e)
-    if (cnt[e + 1] > cnt[e]) {
-      be.push_back((int32_t)e);
-      bb.push_back(cnt[e]);
+  std::vector<int32_t> be, bch;
+  for (size_t c = 0; c < ce.size(); ++c)
+    if (c == 0 || ce[c] != ce[c - 1]) {
+      be.push_back(ce[c]);
+      bch.push_back((int32_t)c);
     }
+  bch.push_back((int32_t)ce.size());
   P->s0_blocks = (int32_t)be.size();
   P->s0_blk_e.upload(be, s);
-  P->s0_blk_beg.upload(bb, s);
+  P->s0_blk_ch.upload(bch, s);
   P->s0_chunks = (int32_t)ce.size();
   P->s0_ptr.upload(cnt, s);
   P->s0_q.upload(pts, s);

@@ -150,11 +150,11 @@ __global__ void k_s0_init(int64_t n, const int32_t* __restrict__ row_of, const i
 // its 2 rows of U and V in LDS; then U^T V accumulates on the FP64 matrix
 // cores (16 x 16 x 4, 9 x 9 used), two points per instruction; the chunk's
 // sum is added to blocks (i, j) and (j, i) with global atomics.
-// det = 1 (deterministic): the launch lists whole blocks instead of chunks
-// (chunk_beg = first shared point of the block), each wave sums all of its
-// block's points in order and stores (i, j) and (j, i), with no atomics.
+// part != NULL (deterministic mode): each chunk stores its 9 x 9 sum to
+// part[chunk] instead, and k_s0_gather adds the chunks of every block in
+// order; no atomics.
 __global__ __launch_bounds__(64) void k_explicit_s0(
-    int det, const int32_t* __restrict__ chunk_e, const int32_t* __restrict__ chunk_beg,
+    double* __restrict__ part, const int32_t* __restrict__ chunk_e, const int32_t* __restrict__ chunk_beg,
     const int32_t* __restrict__ row_of, const int32_t* __restrict__ col,
     const int32_t* __restrict__ trans_pos, const int32_t* __restrict__ s0_ptr,
     const int32_t* __restrict__ s0_q, const double* __restrict__ campre, const double* __restrict__ prec,
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(64) void k_explicit_s0(
   const int kq = lane >> 4, cc = lane & 15;
   d4 acc = {0, 0, 0, 0};
   const int beg = chunk_beg[ch];
-  const int end = det ? s0_ptr[e + 1] : min(s0_ptr[e + 1], beg + S0_CHUNK);
+  const int end = min(s0_ptr[e + 1], beg + S0_CHUNK);
   for (int base = beg; base < end; base += 64) {
     const int nh = end - base < 64 ? end - base : 64;
     if (lane < nh) {
@@ -237,15 +237,32 @@ __global__ __launch_bounds__(64) void k_explicit_s0(
   for (int t = 0; t < 4; ++t) {
     const int r = 4 * t + kq;
     if (r < 9 && cc < 9) {
-      if (det) {
-        S[(size_t)e * 81 + r * 9 + cc] = -acc[t];
-        S[(size_t)trans_pos[e] * 81 + cc * 9 + r] = -acc[t];
+      if (part) {
+        part[(size_t)ch * 81 + r * 9 + cc] = acc[t];
       } else {
         unsafeAtomicAdd(&S[(size_t)e * 81 + r * 9 + cc], -acc[t]);
         unsafeAtomicAdd(&S[(size_t)trans_pos[e] * 81 + cc * 9 + r], -acc[t]);
       }
     }
   }
+}
+
+// Deterministic completion of the explicit level-0 S: block e (upper, listed
+// in blk_e with its chunks blk_ch[i] .. blk_ch[i + 1]) and its transpose get
+// minus the sum of the chunks' partial products, added in chunk order. One
+// thread per (block, entry).
+__global__ __launch_bounds__(256) void k_s0_gather(int n_blk, const int32_t* __restrict__ blk_e,
+                                                   const int32_t* __restrict__ blk_ch,
+                                                   const int32_t* __restrict__ trans_pos,
+                                                   const double* __restrict__ part, double* __restrict__ S) {
+  const int gid = blockIdx.x * 243 + threadIdx.x;
+  const int i = gid / 81, m = gid - i * 81;
+  if (threadIdx.x >= 243 || i >= n_blk) return;
+  double acc = 0.0;
+  for (int ch = blk_ch[i]; ch < blk_ch[i + 1]; ++ch) acc += part[(size_t)ch * 81 + m];
+  const int e = blk_e[i], r = m / 9, c = m - r * 9;
+  S[(size_t)e * 81 + m] = -acc;
+  S[(size_t)trans_pos[e] * 81 + c * 9 + r] = -acc;
 }
 
 // ---------------------------------------------------------------- Galerkin product

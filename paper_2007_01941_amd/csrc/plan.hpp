@@ -92,8 +92,14 @@ struct ba_plan {
   bamg::DBuf<int32_t> tile_coff;  // [n_tiles + 1] offsets into tile_cams
   bamg::DBuf<int32_t> tile_cams;  // distinct cameras of each tile, ascending
   bamg::DBuf<int32_t> tile_cseg;  // per tile_cams entry: first rank of that camera's observations
-  bamg::DBuf<uint32_t> obs_slot;  // [n_obs] camera slot | point slot << 16 | rank by camera << 24
+  bamg::DBuf<uint32_t> obs_slot;  // [n_obs] group camera slot | point slot << 16 | rank by camera << 24
+  bamg::DBuf<int32_t> tile_cslot; // per tile_cams entry: its camera's slot in the tile's group
   int32_t max_tile_cams = 0;
+  // ---- groups of consecutive tiles (one workgroup each in the Schur product)
+  int32_t n_groups = 0;
+  bamg::DBuf<int32_t> grp_tile;   // [n_groups + 1] tile range of each group
+  bamg::DBuf<int32_t> grp_coff;   // [n_groups + 1] offsets into grp_cams
+  bamg::DBuf<int32_t> grp_cams;   // cameras of each group, in slot order
   // ---- explicit level-0 S: for every upper off-diagonal block (i, j) of the
   // level-0 pattern, the (reordered) points cameras i and j share
   bamg::DBuf<int32_t> s0_ptr;     // [nnz0 + 1]
@@ -102,12 +108,13 @@ struct ba_plan {
   bamg::DBuf<int32_t> s0_chunk_beg;  //   and first index into s0_q
   int32_t s0_chunks = 0;
   bamg::DBuf<int32_t> s0_blk_e;      // deterministic mode: every upper block with
-  bamg::DBuf<int32_t> s0_blk_beg;    //   shared points, and its first index into s0_q
+  bamg::DBuf<int32_t> s0_blk_ch;     //   shared points, and its chunk range [i, i + 1)
   int32_t s0_blocks = 0;
-  // deterministic Schur product: per camera, its (tile, camera) entries of
-  // tile_cams in tile order, and the partial sums of one product
+  bamg::DBuf<double> s0_part;        // deterministic mode: [s0_chunks][81] chunk sums
+  // deterministic Schur product: per camera, its (group, camera) entries of
+  // grp_cams in group order, and the partial sums of one product
   bamg::DBuf<int32_t> cam_te_ptr;    // [n_cam + 1]
-  bamg::DBuf<int32_t> cam_te;        // [total tile_cams entries]
+  bamg::DBuf<int32_t> cam_te;        // [total grp_cams entries]
   int32_t n_te = 0;
   bamg::DBuf<double> te_part;        // [n_te][9]
   bamg::DBuf<float> te_part32;

@@ -23,193 +23,271 @@ __global__ __launch_bounds__(256) void k_apply_A(int n_cam, const T* __restrict_
   y[(size_t)c * 9 + i] = s;
 }
 
-// y -= F^T E C^-1 E^T F x, one workgroup per tile of <= TILE_OBS observations
-// belonging to whole points (one thread per observation, coalesced plane
-// reads; every load of the tile is issued before the first barrier).
-//  1. s_o = F_o x_c(o) with x staged in LDS for the tile's first TILE_SLOTS
-//     cameras; each thread leaves E_o^T s_o in LDS.
+// y -= F^T E C^-1 E^T F x. Observations are cut (at plan time) into tiles of
+// at most TILE_OBS observations of whole points, and consecutive tiles into
+// groups whose cameras fit GROUP_SLOTS; one workgroup of 256 threads works
+// through one group, one tile at a time, one thread per observation:
+//  1. s_o = F_o x_c(o) with the group's x staged in LDS once; each thread
+//     leaves E_o^T s_o in LDS.
 //  2. One thread per point adds its observations' terms in order and applies
 //     C_p^-1: u_p.
-//  3. The camera terms -F_o^T E_o u_p are summed per (tile, camera) in LDS and
-//     added to y with one global atomic per (tile, camera, component). FP64:
-//     LDS atomic adds into per-camera slots. FP32: each thread leaves its
-//     terms at its observation's rank in the tile's camera-sorted order and
-//     one thread per (camera, component) adds its camera's run (FP32 LDS
-//     atomics contend badly when many lanes share a camera).
-// A tile of more than TILE_OBS observations (a single point) adds its camera
-// terms to y with global atomics directly.
+//  3. The camera terms -F_o^T E_o u_p are summed per camera into the group's
+//     LDS accumulators: FP64 by LDS atomic adds; FP32 (whose LDS atomics
+//     contend badly when many lanes share a camera) and the deterministic
+//     mode by runs: each thread leaves its terms at its observation's rank in
+//     the tile's camera-sorted order, and one thread per (camera, component)
+//     adds its camera's run.
+// At the end of the group each (camera, component) sum is added to y with one global
+// atomic (DET: stored to part[(grp_coff[g] + slot) * 9 + k] and added in
+// group order by k_schur_gather). Groups are tiles of whole points ordered by
+// their lowest camera, so neighbouring tiles share most cameras and a group
+// issues far fewer atomics than its tiles would one by one.
 //
-// DET (deterministic): no floating-point atomics anywhere. Every (tile,
-// camera) sum is formed by the camera-sorted runs (both precisions) and
-// stored to part[(tile_coff[t] + slot) * 9 + k]; k_schur_gather then adds each
-// camera's partials to y in tile order. A single-point tile has one
-// observation per camera, so its terms are stored the same way.
+// A group of one tile may hold more cameras than GROUP_SLOTS: the others read
+// x from global memory and add their sums to y directly (DET: store them). A
+// tile of more than TILE_OBS observations (a single point) is a group of its
+// own, with one camera per observation: each term goes to y (or part) directly.
 //
-// Tiles are numbered in point order, so neighbouring tiles share cameras; the
-// launch maps workgroups to tiles with xcd_block (each XCD takes one
-// contiguous range), so the x reads and y atomics of neighbouring tiles meet
+// The launch maps workgroups to groups with xcd_block (each XCD takes one
+// contiguous range), so the x reads and y atomics of neighbouring groups meet
 // in the same L2.
-template <class T, bool DET>
-__global__ __launch_bounds__(256) void k_schur_tiles(
-    const int32_t* __restrict__ tile_obs, const int32_t* __restrict__ tile_pt,
-    const int32_t* __restrict__ tile_coff, const int32_t* __restrict__ tile_cams,
-    const int32_t* __restrict__ tile_cseg, const int32_t* __restrict__ pt_off,
-    const uint32_t* __restrict__ obs_slot, const T* __restrict__ F, const T* __restrict__ E, int64_t stride,
-    const T* __restrict__ Cinv, const T* __restrict__ x, T* __restrict__ y, T* __restrict__ part, int n_tiles,
-    const int* __restrict__ done) {
-  if (done && *done) return;
-  constexpr bool lds_atomics = sizeof(T) == 8 && !DET;
-  __shared__ T xs[TILE_SLOTS * 9];
-  __shared__ T ys[lds_atomics ? TILE_SLOTS * 9 : 1];
-  // E^T F x terms [3][TILE_OBS]; FP32 then the camera terms [TILE_OBS][9]
-  __shared__ T buf[lds_atomics ? 3 * TILE_OBS : 9 * TILE_OBS];
-  __shared__ T us[(TILE_OBS / 2) * 3];
-  __shared__ int segs[lds_atomics ? 1 : TILE_OBS + 1];
-  const int t = xcd_block(blockIdx.x, n_tiles);
-  if (t >= n_tiles) return;
-  const int o0 = tile_obs[t], o1 = tile_obs[t + 1];
-  const int q0 = tile_pt[t], np = tile_pt[t + 1] - q0;
-  const int c0 = tile_coff[t], nc = tile_coff[t + 1] - c0;
-  const int ncs = nc < TILE_SLOTS ? nc : TILE_SLOTS;
-  const bool big = o1 - o0 > TILE_OBS;
-  const int o = o0 + threadIdx.x;
-  const bool act = o < o1;
-  T f[18], e[6];
-  uint32_t w = 0;
-  if (act) {
-    w = obs_slot[o];
-#pragma unroll
-    for (int k = 0; k < 18; ++k) f[k] = F[k * stride + o];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) e[k] = E[k * stride + o];
-  }
-  T ci[6];
-  int l0 = 0, l1 = 0;
-  if (threadIdx.x < np) {
-    const int q = q0 + threadIdx.x;
-#pragma unroll
-    for (int k = 0; k < 6; ++k) ci[k] = Cinv[(size_t)q * 6 + k];
-    l0 = pt_off[q] - o0;
-    l1 = pt_off[q + 1] - o0;
-  }
-  if (!lds_atomics && !big)
-    for (int i = threadIdx.x; i <= nc; i += 256) segs[i] = i < nc ? tile_cseg[c0 + i] : o1 - o0;
-  for (int i = threadIdx.x; i < ncs * 9; i += 256) {
-    const int sl = i / 9, k = i - sl * 9;
-    xs[i] = x[(size_t)tile_cams[c0 + sl] * 9 + k];
-    if (lds_atomics) ys[i] = T(0);
-  }
-  __syncthreads();
+template <class T>
+struct TileRegs {
+  T f[18], e[6];   // this thread's observation
+  uint32_t w;      // its slot word: group slot | point slot << 16 | camera-sorted rank << 24
+  T ci[6];         // this thread's point (threads below the tile's point count)
+  int l0, l1;      //   and its observation range within the tile
+  int seg, cslot;  // this thread's tile camera: first rank, group slot (run sums)
+};
 
-  const int slot = (int)(w & 0xffffu), pl = (int)((w >> 16) & 0xffu), rank = (int)(w >> 24);
-  T z0 = 0, z1 = 0, z2 = 0;
-  if (act) {
-    const T* xv = slot < TILE_SLOTS ? &xs[slot * 9] : &x[(size_t)tile_cams[c0 + slot] * 9];
-    T s0 = 0, s1 = 0;
+template <class T, bool RUNS>
+__device__ __forceinline__ void load_tile(int t, const int32_t* __restrict__ tile_obs,
+                                          const int32_t* __restrict__ tile_pt,
+                                          const int32_t* __restrict__ tile_coff,
+                                          const int32_t* __restrict__ tile_cseg,
+                                          const int32_t* __restrict__ tile_cslot,
+                                          const int32_t* __restrict__ pt_off,
+                                          const uint32_t* __restrict__ obs_slot, const T* __restrict__ F,
+                                          const T* __restrict__ E, int64_t stride, const T* __restrict__ Cinv,
+                                          TileRegs<T>& r) {
+  const int tid = threadIdx.x;
+  const int o0 = tile_obs[t], o = o0 + tid;
+  r.w = 0;
+  if (o < tile_obs[t + 1]) {
+    r.w = obs_slot[o];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) { s0 += f[k] * xv[k]; s1 += f[9 + k] * xv[k]; }
-    z0 = e[0] * s0 + e[3] * s1;
-    z1 = e[1] * s0 + e[4] * s1;
-    z2 = e[2] * s0 + e[5] * s1;
-  }
-  for (int oo = o0 + 256 + threadIdx.x; oo < o1; oo += 256) {
-    const uint32_t ww = obs_slot[oo];
-    const int sl = (int)(ww & 0xffffu);
-    const T* xv = sl < TILE_SLOTS ? &xs[sl * 9] : &x[(size_t)tile_cams[c0 + sl] * 9];
-    T s0 = 0, s1 = 0;
-    for (int k = 0; k < 9; ++k) { s0 += F[k * stride + oo] * xv[k]; s1 += F[(9 + k) * stride + oo] * xv[k]; }
-    z0 += E[0 * stride + oo] * s0 + E[3 * stride + oo] * s1;
-    z1 += E[1 * stride + oo] * s0 + E[4 * stride + oo] * s1;
-    z2 += E[2 * stride + oo] * s0 + E[5 * stride + oo] * s1;
-  }
-  buf[0 * TILE_OBS + threadIdx.x] = z0;
-  buf[1 * TILE_OBS + threadIdx.x] = z1;
-  buf[2 * TILE_OBS + threadIdx.x] = z2;
-  __syncthreads();
-  if (threadIdx.x < np) {
-    if (l1 - l0 > TILE_OBS) { l0 = 0; l1 = TILE_OBS; }
-    T a0 = 0, a1 = 0, a2 = 0;
-    for (int l = l0; l < l1; ++l) { a0 += buf[l]; a1 += buf[TILE_OBS + l]; a2 += buf[2 * TILE_OBS + l]; }
-    us[threadIdx.x * 3 + 0] = ci[0] * a0 + ci[1] * a1 + ci[2] * a2;
-    us[threadIdx.x * 3 + 1] = ci[1] * a0 + ci[3] * a1 + ci[4] * a2;
-    us[threadIdx.x * 3 + 2] = ci[2] * a0 + ci[4] * a1 + ci[5] * a2;
-  }
-  __syncthreads();
-  if (big) {
-    for (int oo = o0 + threadIdx.x; oo < o1; oo += 256) {
-      const uint32_t ww = obs_slot[oo];
-      const int sl = (int)(ww & 0xffffu), pq = (int)((ww >> 16) & 0xffu);
-      const T u0 = us[pq * 3], u1 = us[pq * 3 + 1], u2 = us[pq * 3 + 2];
-      const T w0 = E[0 * stride + oo] * u0 + E[1 * stride + oo] * u1 + E[2 * stride + oo] * u2;
-      const T w1 = E[3 * stride + oo] * u0 + E[4 * stride + oo] * u1 + E[5 * stride + oo] * u2;
-      if (DET) {
-        T* pv = part + (size_t)(c0 + sl) * 9;
-        for (int k = 0; k < 9; ++k) pv[k] = -(F[k * stride + oo] * w0 + F[(9 + k) * stride + oo] * w1);
-      } else {
-        T* yv = y + (size_t)tile_cams[c0 + sl] * 9;
-        for (int k = 0; k < 9; ++k) unsafeAtomicAdd(&yv[k], -(F[k * stride + oo] * w0 + F[(9 + k) * stride + oo] * w1));
-      }
-    }
-    return;
-  }
-  if (lds_atomics) {
-    if (act) {
-      const T u0 = us[pl * 3], u1 = us[pl * 3 + 1], u2 = us[pl * 3 + 2];
-      const T w0 = e[0] * u0 + e[1] * u1 + e[2] * u2;
-      const T w1 = e[3] * u0 + e[4] * u1 + e[5] * u2;
-      if (slot < TILE_SLOTS) {
+    for (int k = 0; k < 18; ++k) r.f[k] = F[k * stride + o];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) atomicAdd(&ys[slot * 9 + k], -(f[k] * w0 + f[9 + k] * w1));
-      } else {
-        T* yv = y + (size_t)tile_cams[c0 + slot] * 9;
+    for (int k = 0; k < 6; ++k) r.e[k] = E[k * stride + o];
+  }
+  const int q0 = tile_pt[t];
+  r.l0 = r.l1 = 0;
+  if (tid < tile_pt[t + 1] - q0) {
+    const int q = q0 + tid;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) unsafeAtomicAdd(&yv[k], -(f[k] * w0 + f[9 + k] * w1));
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < ncs * 9; i += 256) {
-      const int sl = i / 9, k = i - sl * 9;
-      unsafeAtomicAdd(&y[(size_t)tile_cams[c0 + sl] * 9 + k], ys[i]);
-    }
-  } else {
-    if (act) {
-      const T u0 = us[pl * 3], u1 = us[pl * 3 + 1], u2 = us[pl * 3 + 2];
-      const T w0 = e[0] * u0 + e[1] * u1 + e[2] * u2;
-      const T w1 = e[3] * u0 + e[4] * u1 + e[5] * u2;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) buf[rank * 9 + k] = -(f[k] * w0 + f[9 + k] * w1);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < nc * 9; i += 256) {
-      const int sl = i / 9, k = i - sl * 9;
-      T acc = 0;
-      for (int l = segs[sl]; l < segs[sl + 1]; ++l) acc += buf[l * 9 + k];
-      if (DET) part[(size_t)(c0 + sl) * 9 + k] = acc;
-      else unsafeAtomicAdd(&y[(size_t)tile_cams[c0 + sl] * 9 + k], acc);
+    for (int k = 0; k < 6; ++k) r.ci[k] = Cinv[(size_t)q * 6 + k];
+    r.l0 = pt_off[q] - o0;
+    r.l1 = pt_off[q + 1] - o0;
+  }
+  if (RUNS) {
+    const int c0 = tile_coff[t];
+    if (tid < tile_coff[t + 1] - c0) {
+      r.seg = tile_cseg[c0 + tid];
+      r.cslot = tile_cslot[c0 + tid];
     }
   }
 }
 
+template <class T, bool DET>
+__global__ __launch_bounds__(256) void k_schur_groups(
+    const int32_t* __restrict__ grp_tile, const int32_t* __restrict__ grp_coff,
+    const int32_t* __restrict__ grp_cams, const int32_t* __restrict__ tile_obs,
+    const int32_t* __restrict__ tile_pt, const int32_t* __restrict__ tile_coff,
+    const int32_t* __restrict__ tile_cseg, const int32_t* __restrict__ tile_cslot,
+    const int32_t* __restrict__ pt_off, const uint32_t* __restrict__ obs_slot, const T* __restrict__ F,
+    const T* __restrict__ E, int64_t stride, const T* __restrict__ Cinv, const T* __restrict__ x,
+    T* __restrict__ y, T* __restrict__ part, int n_groups, const int* __restrict__ done) {
+  if (done && *done) return;
+  constexpr bool RUNS = sizeof(T) == 4 || DET;
+  __shared__ T xs[GROUP_SLOTS * 9];
+  __shared__ T ys[GROUP_SLOTS * 9];
+  // E^T F x terms [3][TILE_OBS]; with RUNS then the camera terms [TILE_OBS][9]
+  __shared__ T buf[RUNS ? 9 * TILE_OBS : 3 * TILE_OBS];
+  __shared__ T us[(TILE_OBS / 2) * 3];
+  __shared__ int segs[RUNS ? TILE_OBS + 1 : 1];
+  __shared__ int cslots[RUNS ? TILE_OBS : 1];
+  const int g = xcd_block(blockIdx.x, n_groups);
+  if (g >= n_groups) return;
+  const int tid = threadIdx.x;
+  const int t0 = grp_tile[g], t1 = grp_tile[g + 1];
+  const bool single = t1 == t0 + 1;
+  const int gc0 = grp_coff[g];
+  const int gns = min(grp_coff[g + 1] - gc0, GROUP_SLOTS);
+
+  if (tile_obs[t0 + 1] - tile_obs[t0] > TILE_OBS) {
+    // one point seen by more than TILE_OBS cameras (one camera per observation)
+    const int o0 = tile_obs[t0], o1 = tile_obs[t0 + 1];
+    const int q = tile_pt[t0];
+    T z0 = 0, z1 = 0, z2 = 0;
+    for (int oo = o0 + tid; oo < o1; oo += 256) {
+      const int sl = (int)(obs_slot[oo] & 0xffffu);
+      const T* xv = &x[(size_t)grp_cams[gc0 + sl] * 9];
+      T s0 = 0, s1 = 0;
+      for (int k = 0; k < 9; ++k) { s0 += F[k * stride + oo] * xv[k]; s1 += F[(9 + k) * stride + oo] * xv[k]; }
+      z0 += E[0 * stride + oo] * s0 + E[3 * stride + oo] * s1;
+      z1 += E[1 * stride + oo] * s0 + E[4 * stride + oo] * s1;
+      z2 += E[2 * stride + oo] * s0 + E[5 * stride + oo] * s1;
+    }
+    buf[tid] = z0;
+    buf[TILE_OBS + tid] = z1;
+    buf[2 * TILE_OBS + tid] = z2;
+    __syncthreads();
+    if (tid == 0) {
+      T a0 = 0, a1 = 0, a2 = 0;
+      for (int l = 0; l < 256; ++l) { a0 += buf[l]; a1 += buf[TILE_OBS + l]; a2 += buf[2 * TILE_OBS + l]; }
+      const T* ci = Cinv + (size_t)q * 6;
+      us[0] = ci[0] * a0 + ci[1] * a1 + ci[2] * a2;
+      us[1] = ci[1] * a0 + ci[3] * a1 + ci[4] * a2;
+      us[2] = ci[2] * a0 + ci[4] * a1 + ci[5] * a2;
+    }
+    __syncthreads();
+    const T u0 = us[0], u1 = us[1], u2 = us[2];
+    for (int oo = o0 + tid; oo < o1; oo += 256) {
+      const int sl = (int)(obs_slot[oo] & 0xffffu);
+      const T w0 = E[0 * stride + oo] * u0 + E[1 * stride + oo] * u1 + E[2 * stride + oo] * u2;
+      const T w1 = E[3 * stride + oo] * u0 + E[4 * stride + oo] * u1 + E[5 * stride + oo] * u2;
+      for (int k = 0; k < 9; ++k) {
+        const T v = -(F[k * stride + oo] * w0 + F[(9 + k) * stride + oo] * w1);
+        if (DET) part[(size_t)(gc0 + sl) * 9 + k] = v;
+        else unsafeAtomicAdd(&y[(size_t)grp_cams[gc0 + sl] * 9 + k], v);
+      }
+    }
+    return;
+  }
+
+  for (int i = tid; i < gns * 9; i += 256) {
+    const int sl = i / 9;
+    xs[i] = x[(size_t)grp_cams[gc0 + sl] * 9 + (i - sl * 9)];
+    if (!(RUNS && single)) ys[i] = T(0);
+  }
+  TileRegs<T> cur;
+  for (int t = t0; t < t1; ++t) {
+    const int n = tile_obs[t + 1] - tile_obs[t];
+    const int np = tile_pt[t + 1] - tile_pt[t];
+    const int nc = tile_coff[t + 1] - tile_coff[t];
+    load_tile<T, RUNS>(t, tile_obs, tile_pt, tile_coff, tile_cseg, tile_cslot, pt_off, obs_slot, F, E, stride,
+                       Cinv, cur);
+    __syncthreads();   // x staged; the previous tile's LDS reads are done
+    if (RUNS) {
+      if (tid < nc) {
+        segs[tid] = cur.seg;
+        cslots[tid] = cur.cslot;
+      }
+      if (tid == 0) segs[nc] = n;
+    }
+    const bool act = tid < n;
+    const int slot = (int)(cur.w & 0xffffu), pl = (int)((cur.w >> 16) & 0xffu), rank = (int)(cur.w >> 24);
+    T z0 = 0, z1 = 0, z2 = 0;
+    if (act) {
+      const T* xv = slot < GROUP_SLOTS ? &xs[slot * 9] : &x[(size_t)grp_cams[gc0 + slot] * 9];
+      T s0 = 0, s1 = 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) { s0 += cur.f[k] * xv[k]; s1 += cur.f[9 + k] * xv[k]; }
+      z0 = cur.e[0] * s0 + cur.e[3] * s1;
+      z1 = cur.e[1] * s0 + cur.e[4] * s1;
+      z2 = cur.e[2] * s0 + cur.e[5] * s1;
+    }
+    buf[tid] = z0;
+    buf[TILE_OBS + tid] = z1;
+    buf[2 * TILE_OBS + tid] = z2;
+    __syncthreads();
+    if (tid < np) {
+      T a0 = 0, a1 = 0, a2 = 0;
+      for (int l = cur.l0; l < cur.l1; ++l) { a0 += buf[l]; a1 += buf[TILE_OBS + l]; a2 += buf[2 * TILE_OBS + l]; }
+      us[tid * 3 + 0] = cur.ci[0] * a0 + cur.ci[1] * a1 + cur.ci[2] * a2;
+      us[tid * 3 + 1] = cur.ci[1] * a0 + cur.ci[3] * a1 + cur.ci[4] * a2;
+      us[tid * 3 + 2] = cur.ci[2] * a0 + cur.ci[4] * a1 + cur.ci[5] * a2;
+    }
+    __syncthreads();
+    T w0 = 0, w1 = 0;
+    if (act) {
+      const T u0 = us[pl * 3], u1 = us[pl * 3 + 1], u2 = us[pl * 3 + 2];
+      w0 = cur.e[0] * u0 + cur.e[1] * u1 + cur.e[2] * u2;
+      w1 = cur.e[3] * u0 + cur.e[4] * u1 + cur.e[5] * u2;
+    }
+    if (!RUNS) {
+      if (act) {
+        if (slot < GROUP_SLOTS) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) atomicAdd(&ys[slot * 9 + k], -(cur.f[k] * w0 + cur.f[9 + k] * w1));
+        } else {
+          T* yv = y + (size_t)grp_cams[gc0 + slot] * 9;
+#pragma unroll
+          for (int k = 0; k < 9; ++k) unsafeAtomicAdd(&yv[k], -(cur.f[k] * w0 + cur.f[9 + k] * w1));
+        }
+      }
+    } else {
+      if (act) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) buf[rank * 9 + k] = -(cur.f[k] * w0 + cur.f[9 + k] * w1);
+      }
+      __syncthreads();
+      for (int i = tid; i < nc * 9; i += 256) {
+        const int j = i / 9, k = i - j * 9;
+        T acc = 0;
+        for (int l = segs[j]; l < segs[j + 1]; ++l) acc += buf[l * 9 + k];
+        const int sl = cslots[j];
+        // a group of one tile flushes its sums directly
+        if (sl < GROUP_SLOTS && !single) ys[sl * 9 + k] += acc;
+        else if (DET) part[(size_t)(gc0 + sl) * 9 + k] = acc;
+        else unsafeAtomicAdd(&y[(size_t)grp_cams[gc0 + sl] * 9 + k], acc);
+      }
+    }
+  }
+  if (RUNS && single) return;
+  __syncthreads();
+  for (int i = tid; i < gns * 9; i += 256) {
+    const int sl = i / 9, k = i - sl * 9;
+    if (DET) part[(size_t)(gc0 + sl) * 9 + k] = ys[i];
+    else unsafeAtomicAdd(&y[(size_t)grp_cams[gc0 + sl] * 9 + k], ys[i]);
+  }
+}
+
 // Deterministic completion of the product: y_c += the partial sums of camera
-// c's (tile, camera) entries in tile order (te_ptr/te list them per camera).
-// One thread per (camera, component).
+// c's (group, camera) entries (te_ptr/te list them per camera in group
+// order). One wave per camera: lane l adds entries l, l + 64, ... in order,
+// then the lanes' sums are combined by a fixed butterfly, so the result does
+// not depend on timing.
 template <class T>
 __global__ __launch_bounds__(256) void k_schur_gather(int n_cam, const int32_t* __restrict__ te_ptr,
                                                       const int32_t* __restrict__ te, const T* __restrict__ part,
                                                       T* __restrict__ y, const int* __restrict__ done) {
   if (done && *done) return;
-  const int gid = blockIdx.x * 252 + threadIdx.x;
-  const int c = gid / 9, k = gid % 9;
-  if (threadIdx.x >= 252 || c >= n_cam) return;
-  T acc = 0;
-  for (int i = te_ptr[c]; i < te_ptr[c + 1]; ++i) acc += part[(size_t)te[i] * 9 + k];
-  y[(size_t)c * 9 + k] += acc;
+  const int c = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (c >= n_cam) return;
+  T acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = 0;
+  for (int i = te_ptr[c] + lane; i < te_ptr[c + 1]; i += 64) {
+    const T* pv = part + (size_t)te[i] * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] += pv[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane < 9) {
+    T v = acc[0];
+#pragma unroll
+    for (int k = 1; k < 9; ++k) v = lane == k ? acc[k] : v;
+    y[(size_t)c * 9 + lane] += v;
+  }
 }
 
-#define BAMG_SCHUR_INST(T, DET)                                                                              \
-  template __global__ void k_schur_tiles<T, DET>(const int32_t*, const int32_t*, const int32_t*, const int32_t*, \
-                                                 const int32_t*, const int32_t*, const uint32_t*, const T*,       \
-                                                 const T*, int64_t, const T*, const T*, T*, T*, int, const int*);
+#define BAMG_SCHUR_INST(T, DET)                                                                               \
+  template __global__ void k_schur_groups<T, DET>(const int32_t*, const int32_t*, const int32_t*, const int32_t*, \
+                                                  const int32_t*, const int32_t*, const int32_t*, const int32_t*, \
+                                                  const int32_t*, const uint32_t*, const T*, const T*, int64_t,   \
+                                                  const T*, const T*, T*, T*, int, const int*);
 BAMG_SCHUR_INST(double, false)
 BAMG_SCHUR_INST(double, true)
 BAMG_SCHUR_INST(float, false)

@@ -16,13 +16,14 @@ static size_t plan_bytes(const ba_plan* P) {
   b += P->obs_cam.bytes() + P->obs_pt.bytes() + P->obs_orig.bytes() + P->pt_off.bytes() + P->pt_orig.bytes();
   b += P->pt_new.bytes() + P->cam_off.bytes() + P->cam_obs.bytes() + P->obs_rank.bytes();
   b += P->tile_obs.bytes() + P->tile_pt.bytes() + P->tile_coff.bytes() + P->tile_cams.bytes() + P->tile_cseg.bytes() + P->obs_slot.bytes();
+  b += P->tile_cslot.bytes() + P->grp_tile.bytes() + P->grp_coff.bytes() + P->grp_cams.bytes();
   b += P->s0_ptr.bytes() + P->s0_q.bytes() + P->cam_q.bytes() + P->s0_chunk_e.bytes() +
        P->s0_chunk_beg.bytes();
   b += P->campre.bytes() + P->F.bytes() + P->E.bytes() + P->fres.bytes() + P->F32.bytes() + P->E32.bytes();
   b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
   b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->Scc.bytes() + P->prec.bytes();
   b += P->Sinv.bytes() + P->Sinv32.bytes() + P->wsq.bytes() + P->cj_off.bytes() + P->cj_inv.bytes();
-  b += P->s0_blk_e.bytes() + P->s0_blk_beg.bytes() + P->cam_te_ptr.bytes() + P->cam_te.bytes() + P->te_part.bytes() +
+  b += P->s0_blk_e.bytes() + P->s0_blk_ch.bytes() + P->s0_part.bytes() + P->cam_te_ptr.bytes() + P->cam_te.bytes() + P->te_part.bytes() +
        P->te_part32.bytes();
   for (const Level& L : P->levels) {
     b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
@@ -593,14 +594,15 @@ static void assemble_s0(ba_plan* P, hipStream_t s) {
   Level& L0 = P->levels[0];
   hipLaunchKernelGGL(k_s0_init, dim3(grid_of<double>(L0.nnz * 81)), dim3(256), 0, s, (int64_t)L0.nnz * 81,
                      L0.row_of.p, L0.col.p, P->Scc.p, L0.S.p);
-  if (P->det && P->s0_blocks > 0)
-    hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_blocks), dim3(64), 0, s, 1, P->s0_blk_e.p, P->s0_blk_beg.p,
-                       L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
-                       P->pt_off.p, P->obs_cam.p, P->robust ? P->wsq.p : nullptr, L0.S.p);
-  else if (!P->det && P->s0_chunks > 0)
-    hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, 0, P->s0_chunk_e.p, P->s0_chunk_beg.p,
-                       L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
-                       P->pt_off.p, P->obs_cam.p, P->robust ? P->wsq.p : nullptr, L0.S.p);
+  if (P->s0_chunks == 0) return;
+  if (P->det && !P->s0_part.p) P->s0_part.alloc((size_t)P->s0_chunks * 81);
+  double* part = P->det ? P->s0_part.p : nullptr;
+  hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, part, P->s0_chunk_e.p, P->s0_chunk_beg.p,
+                     L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
+                     P->pt_off.p, P->obs_cam.p, P->robust ? P->wsq.p : nullptr, L0.S.p);
+  if (P->det)
+    hipLaunchKernelGGL(k_s0_gather, dim3(ceil_div((int64_t)P->s0_blocks * 81, 243)), dim3(256), 0, s, P->s0_blocks,
+                       P->s0_blk_e.p, P->s0_blk_ch.p, L0.trans_pos.p, (const double*)P->s0_part.p, L0.S.p);
 }
 
 // Visibility-based block Jacobi: the level-0 aggregates' blocks of S, inverted.
