@@ -6,16 +6,32 @@
  * Conventions for every entry point:
  *   - Array pointers are DEVICE memory (hipMalloc / torch CUDA tensors) unless
  *     the comment says (host). Arrays are dense, row-major, FP64 unless noted.
- *   - The caller owns every input and output buffer; the library never frees
- *     caller memory. A plan owns the device memory it allocates for itself
- *     (layout, per-step buffers, hierarchy) until ba_plan_destroy.
+ *   - The caller owns every input, output and workspace buffer; the library
+ *     never frees caller memory. Device memory the library needs comes from
+ *     two places:
+ *       * the plan's persistent arrays (the integer structure of one
+ *         visibility graph, built by ba_plan_create) come through the
+ *         allocation callbacks given to ba_plan_create (hipMalloc/hipFree when
+ *         they are NULL) and are released by ba_plan_destroy;
+ *       * everything one LM step computes (Jacobian planes, normal blocks, the
+ *         multigrid hierarchy's numeric data, PCG vectors) lives in a
+ *         workspace of ba_workspace_bytes() bytes that the caller passes to the
+ *         calls that start a step (ws, ws_bytes). A workspace too small for
+ *         the options is BA_ERR_WORKSPACE. The prepared step stays in that
+ *         workspace: the stage calls that use it (ba_step_solve,
+ *         ba_schur_apply, ...) need it untouched since the call that prepared
+ *         it. With ws == NULL the plan keeps a workspace of its own, allocated
+ *         through its callbacks when first needed (and grown when options
+ *         need more).
+ *     Memory returned by the callbacks and workspaces must be aligned to 256
+ *     bytes (BA_ERR_ARG otherwise).
  *   - `stream` is a hipStream_t passed as void*; all device work is enqueued on
- *     it (the multigrid setup also uses a side stream of the plan, forked from
+ *     it (the multigrid setup also uses side streams of the plan, forked from
  *     and joined back into `stream` with events, so ordering on `stream` is
  *     kept). Calls that return step results block until those results are ready
- *     (the solver reads its convergence test back to the host); the two
- *     operator applications (ba_schur_apply, ba_schur_offdiag_apply,
- *     ba_precond_apply) do not block.
+ *     (the solver reads its convergence test back to the host); the operator
+ *     applications (ba_schur_apply, ba_schur_offdiag_apply, ba_precond_apply)
+ *     do not block.
  *   - A negative status means nothing was written to the outputs; a message is
  *     available from ba_last_error() on the calling thread. BA_NOT_CONVERGED
  *     means the outputs hold the last iterate and the statistics are valid.
@@ -49,7 +65,8 @@ typedef enum {
   BA_ERR_GEOMETRY = -4,   /* non-finite input, or a point at/behind an observing camera (x_cam.z >= 0) */
   BA_ERR_NOT_SPD = -5,    /* a 3x3 point block, a 9x9/16x16 smoother block or the coarse matrix
                              is not positive definite, or PCG broke down (p'Sp <= 0, r'z <= 0) */
-  BA_ERR_HIP = -7,        /* a HIP runtime call failed */
+  BA_ERR_WORKSPACE = -6,  /* the workspace is smaller than ba_workspace_bytes() for the options */
+  BA_ERR_HIP = -7,        /* a HIP runtime call failed, or an allocation callback returned NULL */
   BA_ERR_LIMIT = -8       /* a documented size limit was exceeded */
 } ba_status;
 
@@ -123,6 +140,15 @@ typedef struct {            /* (host) */
   int32_t reserved_stats;
 } ba_stats;
 
+/* Allocation callbacks of a plan: alloc returns `bytes` bytes of device memory
+ * aligned to 256 bytes (or NULL on failure), release frees what alloc
+ * returned; ctx is passed through. */
+typedef void* (*ba_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*ba_free_fn)(void* ptr, void* ctx);
+
+/* What a workspace has to hold beyond one LM step (ba_workspace_bytes). */
+enum { BA_USE_STEP = 0, BA_USE_BACKWARD = 1, BA_USE_LM = 2 };
+
 /* Defaults listed above. (host) o. */
 ba_status ba_opts_default(ba_opts* o);
 
@@ -136,12 +162,24 @@ ba_status ba_opts_default(ba_opts* o);
  *   point seen by more than 65535 cameras), BA_ERR_HIP.
  *   *out (host) receives the plan. */
 ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32_t* obs_cam,
-                         const int32_t* obs_pt, const ba_opts* o, void* stream, ba_plan** out);
+                         const int32_t* obs_pt, const ba_opts* o, ba_alloc_fn alloc, ba_free_fn release,
+                         void* ctx, void* stream, ba_plan** out);
 
 void ba_plan_destroy(ba_plan* p);
 
-/* Device bytes held by the plan (host). */
+/* Device bytes held by the plan (host): its persistent arrays, plus its own
+ * workspace if it allocated one. */
 size_t ba_plan_bytes(const ba_plan* p);
+
+/* Bytes of the workspace a step with options o needs on this plan (host):
+ * the step itself (Jacobian planes, normal blocks, PCG vectors), plus the
+ * FP32 copies of BA_MIXED, the hierarchy of BA_PC_MULTIGRID, the cluster
+ * blocks of BA_PC_CLUSTER_JACOBI, the weights of a robust loss and the partial
+ * sums of deterministic mode, as o selects. `uses` adds BA_USE_BACKWARD (the
+ * adjoint's per-observation terms, for ba_lm_step_backward) and/or BA_USE_LM
+ * (candidate parameters and scalars, for ba_cost and ba_lm_solve). Returns 0
+ * (and sets ba_last_error) on a bad argument. */
+size_t ba_workspace_bytes(const ba_plan* p, const ba_opts* o, int32_t uses);
 
 /* One LM step (Section 2.1): solve (J^T J + D) delta = -J^T f for
  * delta = [delta_cam; delta_pt] by PCG on the Schur complement
@@ -150,11 +188,12 @@ size_t ba_plan_bytes(const ba_plan* p);
  * delta_pt = -C^-1 (g_p + E^T F delta_cam).
  *   cams [n_cam][9], pts [n_pt][3], uv [n_obs][2] (observation order as given
  *   to ba_plan_create); D: optional explicit damping diagonal [9 n_cam + 3 n_pt]
- *   (camera entries first), NULL for D = lambda diag(J^T J).
+ *   (camera entries first), NULL for D = lambda diag(J^T J). ws: workspace of
+ *   ws_bytes >= ba_workspace_bytes(p, o, BA_USE_STEP) bytes, or NULL.
  *   Outputs delta_cam [n_cam][9], delta_pt [n_pt][3]; st (host) may be NULL. */
 ba_status ba_lm_step(ba_plan* p, const ba_opts* o, const double* cams, const double* pts,
-                     const double* uv, const double* D, double* delta_cam, double* delta_pt,
-                     ba_stats* st, void* stream);
+                     const double* uv, const double* D, void* ws, size_t ws_bytes, double* delta_cam,
+                     double* delta_pt, ba_stats* st, void* stream);
 
 /* Gradient of a scalar loss L(delta) of one LM step with respect to the step's
  * inputs, given gd_cam = dL/d delta_cam [n_cam][9] and gd_pt = dL/d delta_pt
@@ -166,13 +205,14 @@ ba_status ba_lm_step(ba_plan* p, const ba_opts* o, const double* cams, const dou
  * the damping's own dependence on x is included). D: the explicit damping
  * diagonal the forward step was taken with (as in ba_lm_step; a constant, so it
  * contributes no term of its own), or NULL for D = lambda diag(J^T J).
- * delta_cam/delta_pt are the forward outputs.
+ * delta_cam/delta_pt are the forward outputs. ws: workspace of
+ * ba_workspace_bytes(p, o, BA_USE_BACKWARD) bytes, or NULL.
  * Outputs g_cams [n_cam][9], g_pts [n_pt][3], g_uv [n_obs][2]. */
 ba_status ba_lm_step_backward(ba_plan* p, const ba_opts* o, const double* cams,
                               const double* pts, const double* uv, const double* D,
                               const double* delta_cam, const double* delta_pt, const double* gd_cam,
-                              const double* gd_pt, double* g_cams, double* g_pts, double* g_uv,
-                              ba_stats* st, void* stream);
+                              const double* gd_pt, void* ws, size_t ws_bytes, double* g_cams,
+                              double* g_pts, double* g_uv, ba_stats* st, void* stream);
 
 /* ------------------------------------------------------------------------
  * Stage-level entry points. ba_lm_step = ba_step_prepare + ba_step_solve.
@@ -182,20 +222,23 @@ ba_status ba_lm_step_backward(ba_plan* p, const ba_opts* o, const double* cams,
 /* Residual and Jacobian blocks per observation (Section 2.1):
  * f [n_obs][2], F [n_obs][2][9] = d pi/d camera, E [n_obs][2][3] = d pi/d point,
  * in the caller's observation order, without any robust weighting. Any output
- * may be NULL. The plan's per-observation buffers are reused, so a step
+ * may be NULL. ws as for ba_lm_step (BA_USE_STEP with default options suffices).
+ * The workspace's per-observation buffers are reused, so a step
  * prepared earlier must be prepared again before ba_step_solve,
  * ba_schur_apply, ba_schur_offdiag_apply or ba_precond_apply (they return
  * BA_ERR_ARG until then). */
 ba_status ba_eval_jacobian(ba_plan* p, const double* cams, const double* pts, const double* uv,
-                           double* f, double* F, double* E, void* stream);
+                           void* ws, size_t ws_bytes, double* f, double* F, double* E, void* stream);
 
 /* Evaluate J, the damped normal blocks (Section 2.1), C^-1, the reduced
  * right-hand side b = -g_c + W C^-1 g_p, the block-Jacobi blocks and, for
  * BA_PC_MULTIGRID, the numeric multigrid setup (near-nullspace QR,
  * Galerkin operators, smoothers, coarse factorization), keeping them in the
- * plan for ba_step_solve / ba_schur_apply / ba_precond_apply. */
+ * workspace (ws as for ba_lm_step) for ba_step_solve / ba_schur_apply /
+ * ba_precond_apply. */
 ba_status ba_step_prepare(ba_plan* p, const ba_opts* o, const double* cams, const double* pts,
-                          const double* uv, const double* D, ba_stats* st, void* stream);
+                          const double* uv, const double* D, void* ws, size_t ws_bytes, ba_stats* st,
+                          void* stream);
 
 /* PCG on S dc = b and back-substitution using the prepared step. */
 ba_status ba_step_solve(ba_plan* p, const ba_opts* o, double* delta_cam, double* delta_pt,
@@ -308,10 +351,12 @@ ba_status ba_lm_opts_default(ba_lm_opts* lo);
 /* Cost 1/2 sum_o rho(|pi_o - u_o|^2) at (cams, pts), rho the loss of o (NULL:
  * the squared loss, rho(s) = s), and the number of observations whose point is
  * at or behind the camera (x_cam.z >= 0) or whose residual is not finite
- * (those are left out of the sum). cost, n_invalid (host); n_invalid may be
- * NULL. Blocks until the values are ready. */
+ * (those are left out of the sum). ws: ba_workspace_bytes(p, o, BA_USE_LM)
+ * bytes, or NULL; it is bound as a step's workspace, so a prepared step in a
+ * different workspace is no longer available afterwards. cost, n_invalid
+ * (host); n_invalid may be NULL. Blocks until the values are ready. */
 ba_status ba_cost(ba_plan* p, const ba_opts* o, const double* cams, const double* pts, const double* uv,
-                  double* cost, int64_t* n_invalid, void* stream);
+                  void* ws, size_t ws_bytes, double* cost, int64_t* n_invalid, void* stream);
 
 /* Levenberg-Marquardt from (cams, pts), updated in place [n_cam][9], [n_pt][3].
  * Each iteration solves one step (as ba_lm_step, with lambda = 1 / radius; the
@@ -321,14 +366,16 @@ ba_status ba_cost(ba_plan* p, const ba_opts* o, const double* cams, const double
  * that reaches max_iter is used as it stands; a step whose damped system is
  * not numerically positive definite (BA_ERR_NOT_SPD from the step) is a failed
  * step, recorded with an infinite candidate cost and handled as a rejection. o: the linear solver's options;
- * lo: the loop's. history (host) holds lo->max_iters entries or is NULL;
+ * lo: the loop's. ws: ba_workspace_bytes(p, o, BA_USE_LM) bytes, or NULL.
+ * history (host) holds lo->max_iters entries or is NULL;
  * summary (host) may be NULL. Returns BA_OK whatever the termination rule.
  * Errors: BA_ERR_GEOMETRY if the initial parameters put a point at or behind
  * an observing camera or are not finite; the errors of ba_lm_step. After an
  * error cams and pts hold the last accepted parameters. Afterwards the plan
  * holds the step prepared at the last iteration's parameters. Blocks. */
 ba_status ba_lm_solve(ba_plan* p, const ba_opts* o, const ba_lm_opts* lo, double* cams, double* pts,
-                      const double* uv, ba_lm_iter* history, ba_lm_summary* summary, void* stream);
+                      const double* uv, void* ws, size_t ws_bytes, ba_lm_iter* history,
+                      ba_lm_summary* summary, void* stream);
 
 const char* ba_status_str(ba_status e);
 const char* ba_last_error(void);

@@ -93,9 +93,38 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+class _TorchMemory:
+    """Device memory the library asks for through its allocation callbacks,
+    handed out as torch uint8 tensors and kept alive until released."""
+
+    def __init__(self, device):
+        self.device = device
+        self.live = {}
+        self.alloc_cb = _lib.ALLOC_FN(self._alloc)
+        self.free_cb = _lib.FREE_FN(self._free)
+
+    def _alloc(self, nbytes, ctx):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except RuntimeError:        # out of memory: the library reports the NULL
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, ctx):
+        self.live.pop(ptr, None)
+
+    @property
+    def bytes(self):
+        return sum(t.numel() for t in self.live.values())
+
+
 class Plan:
     """Integer structure of one visibility graph (observation layout, tiles and
-    the multigrid hierarchy pattern), reusable across LM steps."""
+    the multigrid hierarchy pattern), reusable across LM steps. All device
+    memory is torch's: the plan's persistent arrays come through the
+    library's allocation callbacks, and each step runs in a workspace tensor
+    of ba_workspace_bytes() bytes that this object keeps (and grows)."""
 
     def __init__(self, n_cam, n_pt, obs_cam, obs_pt, opts: Options | None = None):
         self.opts = opts or Options()
@@ -103,21 +132,41 @@ class Plan:
         obs_cam = obs_cam.to(torch.int32).contiguous()
         obs_pt = obs_pt.to(torch.int32).contiguous()
         self.n_obs = int(obs_cam.numel())
+        self._mem = _TorchMemory(obs_cam.device)
+        self._ws = None
         self._h = ctypes.c_void_p()
         o = self.opts.to_c()
         _lib.check(_lib.LIB.ba_plan_create(self.n_cam, self.n_pt, self.n_obs, _ptr(obs_cam),
-                                           _ptr(obs_pt), ctypes.byref(o), _stream(),
-                                           ctypes.byref(self._h)))
+                                           _ptr(obs_pt), ctypes.byref(o), self._mem.alloc_cb,
+                                           self._mem.free_cb, None, _stream(), ctypes.byref(self._h)))
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and _lib is not None and _lib.LIB is not None:
             _lib.LIB.ba_plan_destroy(h)
             self._h = None
 
+    def workspace_bytes(self, opts: Options | None = None, uses: int = _lib.USE_STEP) -> int:
+        o = self._opts(opts)
+        n = int(_lib.LIB.ba_workspace_bytes(self._h, ctypes.byref(o), uses))
+        if n == 0:
+            raise _lib.BAError(-1, "BA_ERR_ARG", _lib.LIB.ba_last_error().decode())
+        return n
+
+    def _workspace(self, o, uses):
+        """(pointer, bytes) of a workspace tensor large enough for the options."""
+        need = int(_lib.LIB.ba_workspace_bytes(self._h, ctypes.byref(o), uses))
+        if need == 0:
+            raise _lib.BAError(-1, "BA_ERR_ARG", _lib.LIB.ba_last_error().decode())
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self._mem.device)
+        return ctypes.c_void_p(self._ws.data_ptr()), ctypes.c_size_t(self._ws.numel())
+
     @property
     def device_bytes(self) -> int:
-        return int(_lib.LIB.ba_plan_bytes(self._h))
+        """Device bytes of the plan's persistent arrays plus its workspace."""
+        return int(_lib.LIB.ba_plan_bytes(self._h)) + (self._ws.numel() if self._ws is not None else 0)
 
     def _opts(self, opts):
         return (opts or self.opts).to_c()
@@ -130,8 +179,10 @@ class Plan:
         dp = torch.empty((self.n_pt, 3), dtype=torch.float64, device=cams.device)
         st = _lib._Stats()
         o = self._opts(opts)
+        ws, wsb = self._workspace(o, _lib.USE_STEP)
         status = _lib.check(_lib.LIB.ba_lm_step(self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv),
-                                                _ptr(D), _ptr(dc), _ptr(dp), ctypes.byref(st), _stream()))
+                                                _ptr(D), ws, wsb, _ptr(dc), _ptr(dp), ctypes.byref(st),
+                                                _stream()))
         if status == _lib.BA_NOT_CONVERGED:
             warnings.warn("PCG did not reach rtol within max_iter", NotConverged)
         return dc, dp, _stats(st, status)
@@ -147,10 +198,11 @@ class Plan:
         o = self._opts(opts)
         if D is not None:
             D = _f64(D, (9 * self.n_cam + 3 * self.n_pt,), "D")
+        ws, wsb = self._workspace(o, _lib.USE_BACKWARD)
         status = _lib.check(_lib.LIB.ba_lm_step_backward(
             self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv), _ptr(D) if D is not None else None,
             _ptr(delta_cam.contiguous()), _ptr(delta_pt.contiguous()), _ptr(gd_cam.contiguous()),
-            _ptr(gd_pt.contiguous()), _ptr(g_c), _ptr(g_p), _ptr(g_u), ctypes.byref(st), _stream()))
+            _ptr(gd_pt.contiguous()), ws, wsb, _ptr(g_c), _ptr(g_p), _ptr(g_u), ctypes.byref(st), _stream()))
         if status == _lib.BA_NOT_CONVERGED:
             warnings.warn("adjoint PCG did not reach rtol within max_iter", NotConverged)
         return g_c, g_p, g_u, _stats(st, status)
@@ -163,8 +215,9 @@ class Plan:
         c = ctypes.c_double()
         bad = ctypes.c_int64()
         o = self._opts(opts)
-        _lib.check(_lib.LIB.ba_cost(self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv), ctypes.byref(c),
-                                    ctypes.byref(bad), _stream()))
+        ws, wsb = self._workspace(o, _lib.USE_LM)
+        _lib.check(_lib.LIB.ba_cost(self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv), ws, wsb,
+                                    ctypes.byref(c), ctypes.byref(bad), _stream()))
         return c.value, bad.value
 
     def lm_solve(self, cams, pts, uv, opts: Options | None = None, lm_opts: LMOptions | None = None):
@@ -175,8 +228,10 @@ class Plan:
         o = self._opts(opts)
         hist = (_lib._LMIter * max(lo.max_iters, 1))()
         sm = _lib._LMSummary()
+        ws, wsb = self._workspace(o, _lib.USE_LM)
         _lib.check(_lib.LIB.ba_lm_solve(self._h, ctypes.byref(o), ctypes.byref(lo), _ptr(cams), _ptr(pts),
-                                        _ptr(uv), hist, ctypes.byref(sm), _stream()), allow_not_converged=False)
+                                        _ptr(uv), ws, wsb, hist, ctypes.byref(sm), _stream()),
+                   allow_not_converged=False)
         h = [LMIteration(r.cost, r.cost_candidate, r.model_decrease, r.rho, r.radius, r.step_norm,
                          bool(r.accepted), r.pcg_iters, r.t_ms) for r in hist[: sm.iters]]
         return LMSummary(sm.iters, sm.accepted, _TERM[sm.termination], sm.pcg_iters, sm.cost0, sm.cost,
@@ -189,7 +244,8 @@ class Plan:
         f = torch.empty((self.n_obs, 2), dtype=torch.float64, device=dev)
         F = torch.empty((self.n_obs, 2, 9), dtype=torch.float64, device=dev)
         E = torch.empty((self.n_obs, 2, 3), dtype=torch.float64, device=dev)
-        _lib.check(_lib.LIB.ba_eval_jacobian(self._h, _ptr(cams), _ptr(pts), _ptr(uv), _ptr(f), _ptr(F),
+        ws, wsb = self._workspace(self._opts(None), _lib.USE_STEP)
+        _lib.check(_lib.LIB.ba_eval_jacobian(self._h, _ptr(cams), _ptr(pts), _ptr(uv), ws, wsb, _ptr(f), _ptr(F),
                                              _ptr(E), _stream()))
         return f, F, E
 
@@ -197,8 +253,9 @@ class Plan:
         self._check_inputs(cams, pts, uv)
         st = _lib._Stats()
         o = self._opts(opts)
+        ws, wsb = self._workspace(o, _lib.USE_STEP)
         _lib.check(_lib.LIB.ba_step_prepare(self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv),
-                                            _ptr(D), ctypes.byref(st), _stream()))
+                                            _ptr(D), ws, wsb, ctypes.byref(st), _stream()))
         return _stats(st, 0)
 
     def solve(self, opts=None, device="cuda"):

@@ -20,6 +20,11 @@ OP_AUTO, OP_IMPLICIT, OP_EXPLICIT = 0, 1, 2
 STOP_RESIDUAL, STOP_NASH_SOFER = 0, 1
 LOSS_SQUARED, LOSS_HUBER = 0, 1
 TERM_MAX_ITERS, TERM_FUNCTION, TERM_PARAMETER, TERM_RADIUS = 0, 1, 2, 3
+USE_STEP, USE_BACKWARD, USE_LM = 0, 1, 2
+BA_ERR_WORKSPACE = -6
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
 
 class BAError(RuntimeError):
@@ -152,15 +157,17 @@ def _load():
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     I32, I64, F64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    SZ = ctypes.c_size_t
     sig = {
         "ba_opts_default": [P],
-        "ba_plan_create": [I32, I32, I64, P, P, P, P, P],
+        "ba_plan_create": [I32, I32, I64, P, P, P, P, P, P, P, P],
         "ba_plan_destroy": [P],
         "ba_plan_bytes": [P],
-        "ba_lm_step": [P, P, P, P, P, P, P, P, P, P],
-        "ba_lm_step_backward": [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P],
-        "ba_eval_jacobian": [P, P, P, P, P, P, P, P],
-        "ba_step_prepare": [P, P, P, P, P, P, P, P],
+        "ba_workspace_bytes": [P, P, I32],
+        "ba_lm_step": [P, P, P, P, P, P, P, SZ, P, P, P, P],
+        "ba_lm_step_backward": [P, P, P, P, P, P, P, P, P, P, P, SZ, P, P, P, P, P],
+        "ba_eval_jacobian": [P, P, P, P, P, SZ, P, P, P, P],
+        "ba_step_prepare": [P, P, P, P, P, P, P, SZ, P, P],
         "ba_step_solve": [P, P, P, P, P, P],
         "ba_schur_apply": [P, I32, P, P, P],
         "ba_schur_offdiag_apply": [P, I32, P, P, P],
@@ -172,8 +179,8 @@ def _load():
         "ba_mg_level_data": [P, I32, I32, P, P],
         "ba_selftest_tile_mma": [P, P, P, I32, P],
         "ba_lm_opts_default": [P],
-        "ba_cost": [P, P, P, P, P, P, P, P],
-        "ba_lm_solve": [P, P, P, P, P, P, P, P, P],
+        "ba_cost": [P, P, P, P, P, P, SZ, P, P, P],
+        "ba_lm_solve": [P, P, P, P, P, P, P, SZ, P, P, P],
         "ba_status_str": [I32],
         "ba_last_error": [],
     }
@@ -183,6 +190,7 @@ def _load():
         fn.restype = ctypes.c_int32
     lib.ba_plan_destroy.restype = None
     lib.ba_plan_bytes.restype = ctypes.c_size_t
+    lib.ba_workspace_bytes.restype = ctypes.c_size_t
     lib.ba_status_str.restype = ctypes.c_char_p
     lib.ba_last_error.restype = ctypes.c_char_p
     return lib
@@ -190,8 +198,9 @@ def _load():
 
 LIB = _load()
 
-# The C ABI's exported symbols, as declared in include/bamg.h.
-EXPORTED = ["ba_opts_default", "ba_plan_create", "ba_plan_destroy", "ba_plan_bytes", "ba_lm_step",
+# The C ABI's exported symbols, as declared in include/*.h.
+EXPORTED = ["ba_opts_default", "ba_plan_create", "ba_plan_destroy", "ba_plan_bytes", "ba_workspace_bytes",
+            "ba_lm_step",
             "ba_lm_step_backward", "ba_eval_jacobian", "ba_step_prepare", "ba_step_solve",
             "ba_schur_apply", "ba_schur_offdiag_apply", "ba_precond_apply", "ba_step_blocks", "ba_mg_levels",
             "ba_mg_aggregates", "ba_mg_covisibility", "ba_mg_level_data", "ba_selftest_tile_mma",

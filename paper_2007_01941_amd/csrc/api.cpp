@@ -16,7 +16,27 @@ void set_error(const char* fmt, ...) {
   va_end(ap);
 }
 
-// PCG and refinement workspace of a plan.
+thread_local const Allocator* tl_alloc = nullptr;
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (tl_alloc && tl_alloc->alloc) {
+    p = tl_alloc->alloc(bytes, tl_alloc->ctx);
+    BA_CHECK(p, BA_ERR_HIP, "the allocation callback returned NULL for %zu bytes", bytes);
+    BA_CHECK(((uintptr_t)p & 255) == 0, BA_ERR_ARG, "the allocation callback returned memory not aligned to 256 bytes");
+  } else {
+    BA_HIP(hipMalloc(&p, bytes));
+  }
+  return p;
+}
+
+void dev_free(void* p, const Allocator* a) {
+  if (a && a->release) a->release(p, a->ctx);
+  else if (!a || !a->alloc) (void)hipFree(p);
+}
+
+// PCG and refinement vectors of a step (views into the workspace) and the
+// pinned host copy of the PCG scalars (owned by the plan).
 struct Scratch {
   int n = 0;  // 9 * n_cam
   DBuf<double> x, r, z, p, q, t, bref, e;
@@ -26,20 +46,29 @@ struct Scratch {
   DBuf<double> dots;     // plain dot results
   DBuf<double> pt_a, pt_b;
   PcgScal* h_scal = nullptr;
-  void init(int ncam, int npt) {
-    n = 9 * ncam;
-    for (DBuf<double>* b : {&x, &r, &z, &p, &q, &t, &bref, &e}) b->alloc(n);
-    for (DBuf<float>* b : {&fx, &fr, &fz, &fp, &fq, &fb}) b->alloc(n);
-    partial.alloc(RED_BLOCKS);
-    scal.alloc(2);
-    dots.alloc(8);
-    pt_a.alloc((size_t)3 * npt);
-    pt_b.alloc((size_t)3 * npt);
-    BA_HIP(hipMemset(scal.p, 0, 2 * sizeof(PcgScal)));
-    BA_HIP(hipHostMalloc((void**)&h_scal, 2 * sizeof(PcgScal), hipHostMallocDefault));
-  }
   ~Scratch() {
     if (h_scal) (void)hipHostFree(h_scal);
+  }
+};
+
+// Adjoint buffers of a step (workspace views).
+struct Backward {
+  DBuf<double> mu_p;   // [n_pt][3] caller order
+  DBuf<double> tcam;   // [9][stride]
+  DBuf<double> tpt;    // [3][stride]
+};
+
+// Levenberg-Marquardt loop buffers (workspace views) and pinned host scalars.
+struct LmWork {
+  DBuf<double> dc, dp;            // step
+  DBuf<double> cams_new, pts_new; // candidate
+  DBuf<double> campre;            // camera precomputation of the candidate
+  DBuf<LmScal> scal;
+  LmScal* h_scal = nullptr;       // pinned copy of scal and the four norms
+  double* h_dots = nullptr;
+  ~LmWork() {
+    if (h_scal) (void)hipHostFree(h_scal);
+    if (h_dots) (void)hipHostFree(h_dots);
   }
 };
 
@@ -211,7 +240,8 @@ static void validate_opts(const ba_opts* o) {
 }
 
 ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32_t* obs_cam,
-                         const int32_t* obs_pt, const ba_opts* o, void* stream, ba_plan** out) {
+                         const int32_t* obs_pt, const ba_opts* o, ba_alloc_fn alloc, ba_free_fn release,
+                         void* ctx, void* stream, ba_plan** out) {
   BA_API_BEGIN
   BA_CHECK(out, BA_ERR_ARG, "out is NULL");
   *out = nullptr;
@@ -219,9 +249,14 @@ ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32
   BA_CHECK(n_cam >= 2 && n_pt >= 1 && n_obs >= 2, BA_ERR_ARG, "need n_cam >= 2, n_pt >= 1, n_obs >= 2");
   BA_CHECK(n_obs < (int64_t)INT32_MAX - 1024, BA_ERR_LIMIT, "n_obs must be below 2^31");
   BA_CHECK(obs_cam && obs_pt, BA_ERR_ARG, "observation index arrays are NULL");
+  BA_CHECK((alloc == nullptr) == (release == nullptr), BA_ERR_ARG, "give both allocation callbacks or neither");
   hipStream_t s = (hipStream_t)stream;
   ba_plan* P = new ba_plan();
+  P->alloc.alloc = alloc;
+  P->alloc.release = release;
+  P->alloc.ctx = ctx;
   try {
+    AllocScope scope(&P->alloc);
     P->n_cam = n_cam;
     P->n_pt = n_pt;
     P->n_obs = n_obs;
@@ -234,7 +269,8 @@ ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32
     BA_HIP(hipStreamSynchronize(s));
     build_observation_layout(P, oc, op, s);
     build_hierarchy(P, o, s);
-    allocate_step(P);
+    create_runtime(P);
+    BA_HIP(hipStreamSynchronize(s));
     *out = P;
   } catch (...) {
     delete P;
@@ -243,8 +279,20 @@ ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32
   BA_API_END
 }
 
+size_t ba_workspace_bytes(const ba_plan* P, const ba_opts* o, int32_t uses) {
+  try {
+    BA_CHECK(P, BA_ERR_ARG, "plan is NULL");
+    validate_opts(o);
+    BA_CHECK(uses >= 0 && uses <= (BA_USE_BACKWARD | BA_USE_LM), BA_ERR_ARG, "bad `uses`");
+    return layout_ws(const_cast<ba_plan*>(P), ws_key(o, uses), nullptr);
+  } catch (const Fail&) {
+    return 0;
+  }
+}
+
 void ba_plan_destroy(ba_plan* p) {
   if (!p) return;
+  (void)hipDeviceSynchronize();   // no work of the plan may still use its memory
   for (hipStream_t st : {p->side, p->side2}) {
     if (!st) continue;
     (void)hipStreamSynchronize(st);
@@ -265,11 +313,13 @@ size_t ba_plan_bytes(const ba_plan* P) {
   return plan_bytes(P);
 }
 
-ba_status ba_eval_jacobian(ba_plan* P, const double* cams, const double* pts, const double* uv,
-                           double* f, double* F, double* E, void* stream) {
+ba_status ba_eval_jacobian(ba_plan* P, const double* cams, const double* pts, const double* uv, void* ws,
+                           size_t ws_bytes, double* f, double* F, double* E, void* stream) {
   BA_API_BEGIN
   BA_CHECK(P && cams && pts && uv, BA_ERR_ARG, "null argument");
   hipStream_t s = (hipStream_t)stream;
+  AllocScope scope(&P->alloc);
+  bind_ws(P, 0u, ws, ws_bytes, s);
   eval_jacobian(P, cams, pts, uv, s);
   hipLaunchKernelGGL(k_scatter_jacobian, dim3(ceil_div(P->n_obs, 256)), dim3(256), 0, s, (int)P->n_obs,
                      P->obs_orig.p, P->n_obs_pad, P->F.p, P->E.p, P->fres.p, f, F, E);
@@ -283,10 +333,13 @@ ba_status ba_eval_jacobian(ba_plan* P, const double* cams, const double* pts, co
 }
 
 ba_status ba_step_prepare(ba_plan* P, const ba_opts* o, const double* cams, const double* pts,
-                          const double* uv, const double* D, ba_stats* st, void* stream) {
+                          const double* uv, const double* D, void* ws, size_t ws_bytes, ba_stats* st,
+                          void* stream) {
   BA_API_BEGIN
   BA_CHECK(P && cams && pts && uv, BA_ERR_ARG, "null argument");
   validate_opts(o);
+  AllocScope scope(&P->alloc);
+  bind_ws(P, ws_key(o, 0), ws, ws_bytes, (hipStream_t)stream);
   prepare(P, o, cams, pts, uv, D, st, (hipStream_t)stream);
   BA_API_END
 }
@@ -302,13 +355,15 @@ ba_status ba_step_solve(ba_plan* P, const ba_opts* o, double* delta_cam, double*
 }
 
 ba_status ba_lm_step(ba_plan* P, const ba_opts* o, const double* cams, const double* pts,
-                     const double* uv, const double* D, double* delta_cam, double* delta_pt,
-                     ba_stats* st, void* stream) {
+                     const double* uv, const double* D, void* ws, size_t ws_bytes, double* delta_cam,
+                     double* delta_pt, ba_stats* st, void* stream) {
   BA_API_BEGIN
   BA_CHECK(P && cams && pts && uv && delta_cam && delta_pt, BA_ERR_ARG, "null argument");
   validate_opts(o);
   hipStream_t s = (hipStream_t)stream;
   if (st) std::memset(st, 0, sizeof(*st));
+  AllocScope scope(&P->alloc);
+  bind_ws(P, ws_key(o, 0), ws, ws_bytes, s);
   prepare(P, o, cams, pts, uv, D, st, s);
   return solve(P, o, delta_cam, delta_pt, st, s);
   BA_API_END
@@ -421,13 +476,15 @@ ba_status ba_mg_level_data(const ba_plan* P, int32_t level, int32_t what, double
 
 ba_status ba_lm_step_backward(ba_plan* P, const ba_opts* o, const double* cams, const double* pts,
                               const double* uv, const double* D, const double* delta_cam, const double* delta_pt,
-                              const double* gd_cam, const double* gd_pt, double* g_cams, double* g_pts,
-                              double* g_uv, ba_stats* st, void* stream) {
+                              const double* gd_cam, const double* gd_pt, void* ws, size_t ws_bytes,
+                              double* g_cams, double* g_pts, double* g_uv, ba_stats* st, void* stream) {
   BA_API_BEGIN
   BA_CHECK(P && cams && pts && uv && delta_cam && delta_pt && gd_cam && gd_pt && g_cams && g_pts && g_uv,
            BA_ERR_ARG, "null argument");
   validate_opts(o);
   BA_CHECK(o->loss == BA_LOSS_SQUARED, BA_ERR_ARG, "the backward pass supports the squared loss only");
+  AllocScope scope(&P->alloc);
+  bind_ws(P, ws_key(o, BA_USE_BACKWARD), ws, ws_bytes, (hipStream_t)stream);
   return backward(P, o, cams, pts, uv, D, delta_cam, delta_pt, gd_cam, gd_pt, g_cams, g_pts, g_uv, st,
                   (hipStream_t)stream);
   BA_API_END
@@ -447,11 +504,13 @@ ba_status ba_lm_opts_default(ba_lm_opts* lo) {
 }
 
 ba_status ba_cost(ba_plan* P, const ba_opts* o, const double* cams, const double* pts, const double* uv,
-                  double* cost, int64_t* n_invalid, void* stream) {
+                  void* ws, size_t ws_bytes, double* cost, int64_t* n_invalid, void* stream) {
   BA_API_BEGIN
   BA_CHECK(P && cams && pts && uv && cost, BA_ERR_ARG, "null argument");
   if (o) validate_opts(o);
   hipStream_t s = (hipStream_t)stream;
+  AllocScope scope(&P->alloc);
+  bind_ws(P, o ? ws_key(o, BA_USE_LM) : (uint32_t)WS_LM, ws, ws_bytes, s);
   LmWork& L = lm_work(P);
   enqueue_cost(P, L, o, cams, pts, uv, s);
   read_scalars(L, nullptr, s);
@@ -461,10 +520,13 @@ ba_status ba_cost(ba_plan* P, const ba_opts* o, const double* cams, const double
 }
 
 ba_status ba_lm_solve(ba_plan* P, const ba_opts* o, const ba_lm_opts* lo, double* cams, double* pts,
-                      const double* uv, ba_lm_iter* history, ba_lm_summary* summary, void* stream) {
+                      const double* uv, void* ws, size_t ws_bytes, ba_lm_iter* history, ba_lm_summary* summary,
+                      void* stream) {
   BA_API_BEGIN
   BA_CHECK(P && lo && cams && pts && uv, BA_ERR_ARG, "null argument");
   validate_opts(o);
+  AllocScope scope(&P->alloc);
+  bind_ws(P, ws_key(o, BA_USE_LM), ws, ws_bytes, (hipStream_t)stream);
   BA_CHECK(lo->max_iters >= 0 && lo->radius0 > 0.0 && lo->max_radius >= lo->radius0 && lo->min_radius >= 0.0 &&
                lo->function_tol >= 0.0 && lo->parameter_tol >= 0.0 && lo->min_relative_decrease >= 0.0,
            BA_ERR_ARG, "bad LM options");
@@ -491,6 +553,7 @@ const char* ba_status_str(ba_status e) {
     case BA_ERR_STRUCTURE: return "BA_ERR_STRUCTURE";
     case BA_ERR_GEOMETRY: return "BA_ERR_GEOMETRY";
     case BA_ERR_NOT_SPD: return "BA_ERR_NOT_SPD";
+    case BA_ERR_WORKSPACE: return "BA_ERR_WORKSPACE";
     case BA_ERR_HIP: return "BA_ERR_HIP";
     case BA_ERR_LIMIT: return "BA_ERR_LIMIT";
   }

@@ -3,12 +3,6 @@
 // dL/du = J mu and dL/dx from the first- and second-order terms.
 namespace bamg {
 
-struct Backward {
-  DBuf<double> mu_p;   // [n_pt][3] caller order
-  DBuf<double> tcam;   // [9][stride]
-  DBuf<double> tpt;    // [3][stride]
-};
-
 static ba_status backward(ba_plan* P, const ba_opts* o, const double* cams, const double* pts, const double* uv,
                           const double* D, const double* delta_cam, const double* delta_pt, const double* gd_cam,
                           const double* gd_pt, double* g_cams, double* g_pts, double* g_uv, ba_stats* st,
@@ -16,13 +10,7 @@ static ba_status backward(ba_plan* P, const ba_opts* o, const double* cams, cons
   if (st) std::memset(st, 0, sizeof(*st));
   prepare(P, o, cams, pts, uv, D, st, s);
   Scratch& W = *P->scratch;
-  if (!P->bwd) P->bwd = new Backward();
   Backward& B = *P->bwd;
-  if (!B.mu_p.p) {
-    B.mu_p.alloc((size_t)P->n_pt * 3);
-    B.tcam.alloc(9 * P->n_obs_pad);
-    B.tpt.alloc(3 * P->n_obs_pad);
-  }
   Timer ts(s);
   // right-hand side of the Schur system for H [mu_c; mu_p] = [gd_cam; gd_pt]
   hipLaunchKernelGGL(k_point_solve, dim3(grid_of<double>(P->n_pt)), dim3(256), 0, s, P->n_pt, P->pt_orig.p,

@@ -53,20 +53,54 @@ enum : uint32_t {
 
 // ------------------------------------------------------------ device memory
 
-// A device buffer owned by the plan.
+// Where a plan's persistent device memory comes from: the caller's callbacks
+// (ba_plan_create), or hipMalloc / hipFree when they are NULL.
+struct Allocator {
+  ba_alloc_fn alloc = nullptr;
+  ba_free_fn release = nullptr;
+  void* ctx = nullptr;
+};
+
+// The allocator of the plan the calling thread is working on (set for the
+// duration of an API call by AllocScope); nullptr means hipMalloc.
+extern thread_local const Allocator* tl_alloc;
+
+struct AllocScope {
+  const Allocator* prev;
+  explicit AllocScope(const Allocator* a) : prev(tl_alloc) { tl_alloc = a; }
+  ~AllocScope() { tl_alloc = prev; }
+};
+
+void* dev_alloc(size_t bytes);
+void dev_free(void* p, const Allocator* a);
+
+// A device buffer of the plan: either owned (allocated through the plan's
+// allocator, freed with it) or a view into a workspace (never freed here).
 template <class T>
 struct DBuf {
   T* p = nullptr;
   size_t n = 0;
+  const Allocator* al = nullptr;
+  bool own = false;
   void alloc(size_t count) {
     free();
+    if (count) {
+      p = static_cast<T*>(dev_alloc(count * sizeof(T)));
+      al = tl_alloc;
+      own = true;
+    }
     n = count;
-    if (count) BA_HIP(hipMalloc(&p, count * sizeof(T)));
+  }
+  void view(T* ptr, size_t count) {
+    free();
+    p = count ? ptr : nullptr;
+    n = count;
   }
   void free() {
-    if (p) (void)hipFree(p);
+    if (p && own) dev_free(p, al);
     p = nullptr;
     n = 0;
+    own = false;
   }
   size_t bytes() const { return n * sizeof(T); }
   void upload(const std::vector<T>& h, hipStream_t s) {
@@ -85,10 +119,37 @@ struct DBuf {
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
-  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), al(o.al), own(o.own) {
+    o.p = nullptr;
+    o.n = 0;
+    o.own = false;
+  }
   DBuf& operator=(DBuf&& o) noexcept {
-    if (this != &o) { free(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      free();
+      p = o.p;
+      n = o.n;
+      al = o.al;
+      own = o.own;
+      o.p = nullptr;
+      o.n = 0;
+      o.own = false;
+    }
     return *this;
+  }
+};
+
+// Carves the per-step buffers out of one workspace: each take() places a
+// buffer at the next 256-byte boundary. With base == nullptr it only counts
+// the bytes (ba_workspace_bytes).
+struct Carve {
+  char* base = nullptr;
+  size_t off = 0;
+  template <class T>
+  void take(DBuf<T>& b, size_t count) {
+    off = (off + 255) / 256 * 256;
+    if (base) b.view(reinterpret_cast<T*>(base + off), count);
+    off += count * sizeof(T);
   }
 };
 

@@ -13,37 +13,7 @@
 // 1/2 sum rho(|f_o|^2) and the model that of the reweighted step.
 namespace bamg {
 
-struct LmWork {
-  DBuf<double> dc, dp;            // step
-  DBuf<double> cams_new, pts_new; // candidate
-  DBuf<double> campre;            // camera precomputation of the candidate
-  DBuf<LmScal> scal;
-  LmScal* h_scal = nullptr;       // pinned copy of scal and the four norms
-  double* h_dots = nullptr;
-  void init(int ncam, int npt) {
-    dc.alloc((size_t)9 * ncam);
-    dp.alloc((size_t)3 * npt);
-    cams_new.alloc((size_t)9 * ncam);
-    pts_new.alloc((size_t)3 * npt);
-    campre.alloc((size_t)24 * ncam);
-    scal.alloc(1);
-    BA_HIP(hipMemset(scal.p, 0, sizeof(LmScal)));
-    BA_HIP(hipHostMalloc((void**)&h_scal, sizeof(LmScal), hipHostMallocDefault));
-    BA_HIP(hipHostMalloc((void**)&h_dots, 4 * sizeof(double), hipHostMallocDefault));
-  }
-  ~LmWork() {
-    if (h_scal) (void)hipHostFree(h_scal);
-    if (h_dots) (void)hipHostFree(h_dots);
-  }
-};
-
-static LmWork& lm_work(ba_plan* P) {
-  if (!P->lm) {
-    P->lm = new LmWork();
-    P->lm->init(P->n_cam, P->n_pt);
-  }
-  return *P->lm;
-}
+static LmWork& lm_work(ba_plan* P) { return *P->lm; }
 
 // Enqueue the cost at (cams, pts) into L.scal (cost, invalid, camflag).
 static void enqueue_cost(ba_plan* P, LmWork& L, const ba_opts* o, const double* cams, const double* pts,

@@ -68,6 +68,7 @@ struct LmWork;    // defined in lm.cpp
 }  // namespace bamg
 
 struct ba_plan {
+  bamg::Allocator alloc;          // where the persistent arrays come from (declared first: freed last)
   int32_t n_cam = 0, n_pt = 0;
   int64_t n_obs = 0;
   int64_t n_obs_pad = 0;     // plane stride of the observation SoA arrays
@@ -142,6 +143,7 @@ struct ba_plan {
   bamg::DBuf<int64_t> cj_off;     // [n_agg0 + 1] offsets of the cluster blocks in cj_inv
   bamg::DBuf<double> cj_inv;      // cluster blocks of S, inverted (visibility-based block Jacobi)
   int cj_max_n = 0;               // largest cluster block dimension (9 x members)
+  int64_t cj_total = 0;           // doubles of all cluster blocks
   bool prepared_cj = false;
   bamg::DBuf<float> Sinv32;
   bamg::DBuf<uint32_t> errflag;   // device error bits
@@ -151,6 +153,11 @@ struct ba_plan {
   bool have_mixed = false;
   bool det = false;               // the prepared step runs without floating-point atomics
   double lambda = 1e-4;
+  // ---- workspace binding: the per-step buffers above are views into it
+  bamg::DBuf<char> own_ws;        // the plan's own workspace (callers passing ws == NULL)
+  uint32_t own_key = 0;           // what own_ws is laid out for
+  const void* ws_base = nullptr;  // workspace the views point into
+  uint32_t ws_key = 0;            // its layout
   bamg::Scratch* scratch = nullptr;
   // side stream of the multigrid setup (default priority), forked from and
   // joined back into the caller's stream with these events

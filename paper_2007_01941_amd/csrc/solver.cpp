@@ -11,52 +11,220 @@ namespace bamg {
 template <class T>
 static int grid_of(int64_t n, int per = 256) { return std::max(1, ceil_div(n, per)); }
 
+// Device bytes the plan owns: its persistent arrays and its own workspace.
 static size_t plan_bytes(const ba_plan* P) {
   size_t b = 0;
   b += P->obs_cam.bytes() + P->obs_pt.bytes() + P->obs_orig.bytes() + P->pt_off.bytes() + P->pt_orig.bytes();
   b += P->pt_new.bytes() + P->cam_off.bytes() + P->cam_obs.bytes() + P->obs_rank.bytes();
   b += P->tile_obs.bytes() + P->tile_pt.bytes() + P->tile_coff.bytes() + P->tile_cams.bytes() + P->tile_cseg.bytes() + P->obs_slot.bytes();
   b += P->tile_cslot.bytes() + P->grp_tile.bytes() + P->grp_coff.bytes() + P->grp_cams.bytes();
-  b += P->s0_ptr.bytes() + P->s0_q.bytes() + P->cam_q.bytes() + P->s0_chunk_e.bytes() +
-       P->s0_chunk_beg.bytes();
-  b += P->campre.bytes() + P->F.bytes() + P->E.bytes() + P->fres.bytes() + P->F32.bytes() + P->E32.bytes();
-  b += P->Cinv.bytes() + P->Cinv32.bytes() + P->vgp.bytes() + P->gp.bytes() + P->Dp.bytes();
-  b += P->A.bytes() + P->A32.bytes() + P->Dc.bytes() + P->b.bytes() + P->Scc.bytes() + P->prec.bytes();
-  b += P->Sinv.bytes() + P->Sinv32.bytes() + P->wsq.bytes() + P->cj_off.bytes() + P->cj_inv.bytes();
-  b += P->s0_blk_e.bytes() + P->s0_blk_ch.bytes() + P->s0_part.bytes() + P->cam_te_ptr.bytes() + P->cam_te.bytes() + P->te_part.bytes() +
-       P->te_part32.bytes();
+  b += P->s0_ptr.bytes() + P->s0_q.bytes() + P->cam_q.bytes() + P->s0_chunk_e.bytes() + P->s0_chunk_beg.bytes();
+  b += P->s0_blk_e.bytes() + P->s0_blk_ch.bytes() + P->cam_te_ptr.bytes() + P->cam_te.bytes() + P->cj_off.bytes();
+  b += P->errflag.bytes() + P->own_ws.bytes();
   for (const Level& L : P->levels) {
     b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
     b += L.diag_pos.bytes() + L.trans_pos.bytes() + L.row_of.bytes() + L.agg.bytes() + L.agg_ptr.bytes();
     b += L.agg_mem.bytes() + L.agg_pos.bytes() + L.slot_of.bytes() + L.gal_ptr.bytes() + L.gal_fine.bytes();
-    b += L.vpart.bytes() + L.fpart.bytes();
-    b += L.S.bytes() + L.S32.bytes() + L.K.bytes() + L.P.bytes() + L.P32.bytes() + L.Dinv.bytes() + L.Dinv32.bytes();
-    b += L.dense.bytes() + L.inv.bytes();
-    b += L.vb.bytes() + L.vx.bytes() + L.vr.bytes() + L.vd.bytes() + L.vt.bytes() + L.vd2.bytes() + L.vx2.bytes();
-    b += L.fd2.bytes() + L.fx2.bytes();
-    b += L.fb.bytes() + L.fx.bytes() + L.fr.bytes() + L.fd.bytes() + L.ft.bytes();
   }
   return b;
 }
 
-static void allocate_step(ba_plan* P) {
+// ---------------------------------------------------------------- workspace
+
+// What a workspace holds beyond the plain FP64 step.
+enum : uint32_t {
+  WS_MIXED = 1u, WS_ROBUST = 2u, WS_DET = 4u, WS_MG = 8u, WS_CJ = 16u, WS_BWD = 32u, WS_LM = 64u,
+};
+
+static uint32_t ws_key(const ba_opts* o, int32_t uses) {
+  uint32_t k = 0;
+  if (o->precision == BA_MIXED) k |= WS_MIXED;
+  if (o->loss != BA_LOSS_SQUARED) k |= WS_ROBUST;
+  if (o->deterministic) k |= WS_DET;
+  if (o->precond == BA_PC_MULTIGRID) k |= WS_MG;
+  if (o->precond == BA_PC_CLUSTER_JACOBI) k |= WS_CJ;
+  if (uses & BA_USE_BACKWARD) k |= WS_BWD;
+  if (uses & BA_USE_LM) k |= WS_LM;
+  return k;
+}
+
+// Places every per-step buffer of `key` in the workspace at `base` (or, with
+// base == nullptr, only adds up the bytes). Buffers a key does not need are
+// left empty.
+static size_t layout_ws(ba_plan* P, uint32_t key, char* base) {
+  Carve c;
+  c.base = base;
   const int64_t st = P->n_obs_pad;
-  P->campre.alloc((size_t)P->n_cam * 24);
-  P->F.alloc(18 * st);
-  P->E.alloc(6 * st);
-  P->fres.alloc(2 * st);
-  P->Cinv.alloc((size_t)P->n_pt * 6);
-  P->vgp.alloc((size_t)P->n_pt * 3);
-  P->gp.alloc((size_t)P->n_pt * 3);
-  P->Dp.alloc((size_t)P->n_pt * 3);
-  P->A.alloc((size_t)P->n_cam * 45);
-  P->Dc.alloc((size_t)P->n_cam * 9);
-  P->b.alloc((size_t)P->n_cam * 9);
-  P->prec.alloc((size_t)P->n_pt * PREC);
-  P->Scc.alloc((size_t)P->n_cam * 81);
-  P->Sinv.alloc((size_t)P->n_cam * 81);
+  const size_t nc = P->n_cam, np = P->n_pt, n = 9 * nc;
+  const bool mixed = key & WS_MIXED, mg = key & WS_MG, cj = key & WS_CJ, det = key & WS_DET;
+  if (base) {
+    // drop the views a key may leave out, so that they are empty
+    for (DBuf<float>* v : {&P->F32, &P->E32, &P->Cinv32, &P->A32, &P->Sinv32, &P->te_part32}) v->view(nullptr, 0);
+    for (DBuf<double>* v : {&P->wsq, &P->te_part, &P->s0_part, &P->cj_inv}) v->view(nullptr, 0);
+  }
+  c.take(P->campre, nc * 24);
+  c.take(P->F, 18 * st);
+  c.take(P->E, 6 * st);
+  c.take(P->fres, 2 * st);
+  c.take(P->Cinv, np * 6);
+  c.take(P->vgp, np * 3);
+  c.take(P->gp, np * 3);
+  c.take(P->Dp, np * 3);
+  c.take(P->A, nc * 45);
+  c.take(P->Dc, nc * 9);
+  c.take(P->b, nc * 9);
+  c.take(P->prec, np * PREC);
+  c.take(P->Scc, nc * 81);
+  c.take(P->Sinv, nc * 81);
+  Scratch& W = *P->scratch;
+  for (DBuf<double>* v : {&W.x, &W.r, &W.z, &W.p, &W.q, &W.t, &W.bref, &W.e}) c.take(*v, n);
+  c.take(W.partial, RED_BLOCKS);
+  c.take(W.scal, 2);
+  c.take(W.dots, 8);
+  c.take(W.pt_a, 3 * np);
+  c.take(W.pt_b, 3 * np);
+  if (mixed) {
+    c.take(P->F32, 18 * st);
+    c.take(P->E32, 6 * st);
+    c.take(P->Cinv32, np * 6);
+    c.take(P->A32, nc * 45);
+    c.take(P->Sinv32, nc * 81);
+    for (DBuf<float>* v : {&W.fx, &W.fr, &W.fz, &W.fp, &W.fq, &W.fb}) c.take(*v, n);
+  } else {
+    for (DBuf<float>* v : {&W.fx, &W.fr, &W.fz, &W.fp, &W.fq, &W.fb}) if (base) v->view(nullptr, 0);
+  }
+  if (key & WS_ROBUST) c.take(P->wsq, st);
+  if (det) {
+    c.take(P->te_part, (size_t)P->n_te * 9);
+    if (mixed) c.take(P->te_part32, (size_t)P->n_te * 9);
+    if (mg || cj) c.take(P->s0_part, (size_t)P->s0_chunks * 81);
+  }
+  const int nl = (int)P->levels.size();
+  for (int l = 0; l < nl; ++l) {
+    Level& L = P->levels[l];
+    const size_t nv = (size_t)L.n * L.bs;
+    const bool last = l + 1 == nl;
+    const bool use = mg || (cj && l == 0);   // the cluster blocks come from the explicit level-0 S
+    if (base) {
+      for (DBuf<double>* v : {&L.S, &L.K, &L.P, &L.Dinv, &L.dense, &L.inv, &L.gj_scale, &L.gj_piv, &L.vb, &L.vx,
+                              &L.vr, &L.vd, &L.vt, &L.vpart, &L.vd2, &L.vx2, &L.lz_u, &L.lz_v, &L.lz_up, &L.lz_vp,
+                              &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw, &L.lz_s})
+        v->view(nullptr, 0);
+      for (DBuf<float>* v : {&L.S32, &L.P32, &L.Dinv32, &L.fb, &L.fx, &L.fr, &L.fd, &L.ft, &L.fpart, &L.fd2, &L.fx2})
+        v->view(nullptr, 0);
+    }
+    if (!use) continue;
+    c.take(L.S, (size_t)L.nnz * L.bs * L.bs);
+    if (!mg) continue;
+    c.take(L.K, nv * NS);
+    if (!last) {
+      c.take(L.P, nv * NS);
+      if (l > 0) c.take(L.Dinv, (size_t)L.n * L.bs * L.bs);
+      c.take(L.vpart, (size_t)L.n * NS);
+      c.take(L.vd2, nv);
+      c.take(L.vx2, nv);
+      for (DBuf<double>* v : {&L.lz_u, &L.lz_v, &L.lz_up, &L.lz_vp, &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw})
+        c.take(*v, nv);
+      c.take(L.lz_s, 68);
+    } else {
+      L.nd = (int)((nv + GJB - 1) / GJB * GJB);
+      c.take(L.dense, (size_t)L.nd * L.nd);
+      c.take(L.inv, (size_t)L.nd * L.nd);
+      c.take(L.gj_scale, L.nd);
+      c.take(L.gj_piv, GJB * GJB);
+    }
+    for (DBuf<double>* v : {&L.vb, &L.vx, &L.vr, &L.vd, &L.vt}) c.take(*v, nv);
+    if (mixed && l == 0) {
+      // the FP32 V-cycle runs level 0 in FP32 and the coarse levels in FP64
+      c.take(L.S32, (size_t)L.nnz * L.bs * L.bs);
+      if (!last) {
+        c.take(L.P32, nv * NS);
+        c.take(L.fpart, (size_t)L.n * NS);
+        c.take(L.fd2, nv);
+        c.take(L.fx2, nv);
+      }
+      for (DBuf<float>* v : {&L.fb, &L.fx, &L.fr, &L.fd, &L.ft}) c.take(*v, nv);
+    } else if (mixed && l == 1) {
+      // level 1 in FP32: the restricted residual and the coarse correction as
+      // level 0's FP32 V-cycle hands them over (widened to / narrowed from FP64)
+      c.take(L.fb, nv);
+      c.take(L.fx, nv);
+    }
+  }
+  if (cj && nl > 1) c.take(P->cj_inv, (size_t)P->cj_total);
+  if (key & WS_BWD) {
+    Backward& B = *P->bwd;
+    c.take(B.mu_p, np * 3);
+    c.take(B.tcam, 9 * st);
+    c.take(B.tpt, 3 * st);
+  }
+  if (key & WS_LM) {
+    LmWork& L = *P->lm;
+    c.take(L.dc, 9 * nc);
+    c.take(L.dp, 3 * np);
+    c.take(L.cams_new, 9 * nc);
+    c.take(L.pts_new, 3 * np);
+    c.take(L.campre, 24 * nc);
+    c.take(L.scal, 1);
+  }
+  return (c.off + 255) / 256 * 256;
+}
+
+static void invalidate_step(ba_plan* P) {
+  P->prepared = false;
+  P->prepared_mg = false;
+  P->prepared_cj = false;
+  P->inspectable_mg = false;
+  P->have_mixed = false;
+}
+
+// Binds the step buffers of options `key` to the caller's workspace (ws) or
+// to the plan's own (ws == NULL, allocated through the plan's callbacks and
+// only ever grown). Rebinding drops the prepared step; binding the same
+// workspace with the same key keeps it.
+static void bind_ws(ba_plan* P, uint32_t key, void* ws, size_t ws_bytes, hipStream_t s) {
+  char* base;
+  uint32_t k;
+  if (ws) {
+    // the same workspace, already laid out for these options and more
+    if (ws == P->ws_base && (P->ws_key & key) == key) return;
+    BA_CHECK(((uintptr_t)ws & 255) == 0, BA_ERR_ARG, "the workspace is not aligned to 256 bytes");
+    const size_t need = layout_ws(P, key, nullptr);
+    BA_CHECK(ws_bytes >= need, BA_ERR_WORKSPACE, "workspace of %zu bytes; these options need %zu", ws_bytes, need);
+    base = static_cast<char*>(ws);
+    k = key;
+  } else {
+    k = P->own_key | key;
+    if (!P->own_ws.p || k != P->own_key) {
+      const size_t need = layout_ws(P, k, nullptr);
+      if (P->own_ws.p) BA_HIP(hipStreamSynchronize(s));
+      P->ws_base = nullptr;
+      P->own_ws.alloc(need);
+      P->own_key = k;
+    }
+    base = P->own_ws.p;
+  }
+  if (P->ws_base == base && P->ws_key == k) return;
+  BA_HIP(hipStreamSynchronize(s));
+  invalidate_step(P);
+  layout_ws(P, k, base);
+  P->ws_base = base;
+  P->ws_key = k;
+  // the reduction counters in the scalar blocks start at zero
+  BA_HIP(hipMemsetAsync(P->scratch->scal.p, 0, 2 * sizeof(PcgScal), s));
+  if (k & WS_LM) BA_HIP(hipMemsetAsync(P->lm->scal.p, 0, sizeof(LmScal), s));
+}
+
+// Host-side runtime of a plan: side streams, events, pinned scalar copies and
+// the work structs whose device buffers are workspace views.
+static void create_runtime(ba_plan* P) {
   P->scratch = new Scratch();
-  P->scratch->init(P->n_cam, P->n_pt);
+  P->scratch->n = 9 * P->n_cam;
+  BA_HIP(hipHostMalloc((void**)&P->scratch->h_scal, 2 * sizeof(PcgScal), hipHostMallocDefault));
+  P->bwd = new Backward();
+  P->lm = new LmWork();
+  BA_HIP(hipHostMalloc((void**)&P->lm->h_scal, sizeof(LmScal), hipHostMallocDefault));
+  BA_HIP(hipHostMalloc((void**)&P->lm->h_dots, 4 * sizeof(double), hipHostMallocDefault));
   BA_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
   BA_HIP(hipStreamCreateWithFlags(&P->side2, hipStreamNonBlocking));
   BA_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
@@ -65,59 +233,23 @@ static void allocate_step(ba_plan* P) {
   P->ev_lvl.assign(P->levels.size(), nullptr);
   for (hipEvent_t& e : P->ev_qr) BA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   for (hipEvent_t& e : P->ev_lvl) BA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  const int nl = (int)P->levels.size();
-  for (int l = 0; l < nl; ++l) {
-    Level& L = P->levels[l];
-    const size_t nv = (size_t)L.n * L.bs;
-    L.S.alloc((size_t)L.nnz * L.bs * L.bs);
-    L.K.alloc(nv * NS);
-    if (l + 1 < nl) {
-      L.P.alloc(nv * NS);
-      if (l > 0) L.Dinv.alloc((size_t)L.n * L.bs * L.bs);
+  // offsets of the cluster blocks (visibility-based block Jacobi): level-0
+  // aggregates of 9 m dofs hold (9 m)^2 doubles each
+  if (P->levels.size() > 1) {
+    const Level& L0 = P->levels[0];
+    std::vector<int32_t> cnt(L0.n_agg, 0);
+    for (int i = 0; i < L0.n; ++i) ++cnt[L0.h_agg[i]];
+    std::vector<int64_t> off((size_t)L0.n_agg + 1, 0);
+    int max_n = 0;
+    for (int a = 0; a < L0.n_agg; ++a) {
+      const int m = 9 * cnt[a];
+      off[a + 1] = off[a] + (int64_t)m * m;
+      max_n = std::max(max_n, m);
     }
-    for (DBuf<double>* v : {&L.vb, &L.vx, &L.vr, &L.vd, &L.vt}) v->alloc(nv);
-    if (l + 1 < nl) {
-      L.vpart.alloc((size_t)L.n * NS);
-      L.vd2.alloc(nv);
-      L.vx2.alloc(nv);
-    }
-    if (l + 1 == nl) {
-      L.nd = (int)((nv + GJB - 1) / GJB * GJB);
-      L.dense.alloc((size_t)L.nd * L.nd);
-      L.inv.alloc((size_t)L.nd * L.nd);
-      L.gj_scale.alloc(L.nd);
-      L.gj_piv.alloc(GJB * GJB);
-    } else {
-      for (DBuf<double>* v : {&L.lz_u, &L.lz_v, &L.lz_up, &L.lz_vp, &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw})
-        v->alloc(nv);
-      L.lz_s.alloc(68);
-    }
-  }
-}
-
-static void ensure_mixed(ba_plan* P) {
-  if (P->F32.p) return;
-  const int64_t st = P->n_obs_pad;
-  P->F32.alloc(18 * st);
-  P->E32.alloc(6 * st);
-  P->Cinv32.alloc((size_t)P->n_pt * 6);
-  P->A32.alloc((size_t)P->n_cam * 45);
-  P->Sinv32.alloc((size_t)P->n_cam * 81);
-  const int nl = (int)P->levels.size();
-  for (int l = 0; l < nl; ++l) {
-    Level& L = P->levels[l];
-    const size_t nv = (size_t)L.n * L.bs;
-    L.S32.alloc((size_t)L.nnz * L.bs * L.bs);
-    if (l + 1 < nl) {
-      L.P32.alloc(nv * NS);
-      if (l > 0) L.Dinv32.alloc((size_t)L.n * L.bs * L.bs);
-    }
-    for (DBuf<float>* v : {&L.fb, &L.fx, &L.fr, &L.fd, &L.ft}) v->alloc(nv);
-    if (l + 1 < nl) {
-      L.fpart.alloc((size_t)L.n * NS);
-      L.fd2.alloc(nv);
-      L.fx2.alloc(nv);
-    }
+    P->cj_max_n = max_n;
+    P->cj_total = off.back();
+    P->cj_off.upload(off, nullptr);
+    BA_HIP(hipStreamSynchronize(nullptr));
   }
 }
 
@@ -595,7 +727,6 @@ static void assemble_s0(ba_plan* P, hipStream_t s) {
   hipLaunchKernelGGL(k_s0_init, dim3(grid_of<double>(L0.nnz * 81)), dim3(256), 0, s, (int64_t)L0.nnz * 81,
                      L0.row_of.p, L0.col.p, P->Scc.p, L0.S.p);
   if (P->s0_chunks == 0) return;
-  if (P->det && !P->s0_part.p) P->s0_part.alloc((size_t)P->s0_chunks * 81);
   double* part = P->det ? P->s0_part.p : nullptr;
   hipLaunchKernelGGL(k_explicit_s0, dim3(P->s0_chunks), dim3(64), 0, s, part, P->s0_chunk_e.p, P->s0_chunk_beg.p,
                      L0.row_of.p, L0.col.p, L0.trans_pos.p, P->s0_ptr.p, P->s0_q.p, P->campre.p, P->prec.p,
@@ -614,21 +745,8 @@ static void cluster_setup(ba_plan* P, hipStream_t s) {
     return;
   }
   Level& L0 = P->levels[0];
-  if (!P->cj_off.p) {
-    const std::vector<int32_t> aptr = L0.agg_ptr.download(s);
-    std::vector<int64_t> off((size_t)L0.n_agg + 1, 0);
-    int max_n = 0;
-    for (int a = 0; a < L0.n_agg; ++a) {
-      const int n = 9 * (aptr[a + 1] - aptr[a]);
-      off[a + 1] = off[a] + (int64_t)n * n;
-      max_n = std::max(max_n, n);
-    }
-    BA_CHECK((size_t)max_n * sizeof(double) <= 64 * 1024, BA_ERR_LIMIT,
-             "a cluster of %d cameras exceeds the cluster kernel's LDS", max_n / 9);
-    P->cj_off.upload(off, s);
-    P->cj_inv.alloc((size_t)off.back());
-    P->cj_max_n = max_n;
-  }
+  BA_CHECK((size_t)P->cj_max_n * sizeof(double) <= 64 * 1024, BA_ERR_LIMIT,
+           "a cluster of %d cameras exceeds the cluster kernel's LDS", P->cj_max_n / 9);
   assemble_s0(P, s);
   hipLaunchKernelGGL(k_cj_gather, dim3(L0.n_agg), dim3(256), 0, s, L0.agg_ptr.p, L0.agg_mem.p, L0.rowptr32.p,
                      L0.col.p, L0.S.p, P->cj_off.p, P->cj_inv.p);
@@ -727,17 +845,12 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
 static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const double* pts, const double* uv,
                     const double* D, ba_stats* st, hipStream_t s) {
   const bool mixed = o->precision == BA_MIXED;
-  if (mixed) ensure_mixed(P);
-  P->prepared = false;
-  P->prepared_mg = false;
-  P->prepared_cj = false;
-  P->inspectable_mg = false;
+  const uint32_t need = ws_key(o, 0);
+  BA_CHECK((P->ws_key & need) == need, BA_ERR_ARG, "internal: the bound workspace does not fit the options");
+  invalidate_step(P);
   P->lambda = o->lambda;
   P->det = o->deterministic != 0;
-  if (P->det && !P->te_part.p) P->te_part.alloc((size_t)P->n_te * 9);
-  if (P->det && mixed && !P->te_part32.p) P->te_part32.alloc((size_t)P->n_te * 9);
   P->robust = o->loss != BA_LOSS_SQUARED;
-  if (P->robust && !P->wsq.p) P->wsq.alloc((size_t)P->n_obs_pad);
   double* wsq = P->robust ? P->wsq.p : nullptr;
   Timer tj(s);
   hipLaunchKernelGGL(k_campre, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,

@@ -45,9 +45,19 @@ def test_host_side_calls_without_gpu():
     assert _lib.LIB.ba_opts_default(None) == -1
     assert _lib.LIB.ba_status_str(-2) == b"BA_ERR_INDEX"
     # argument validation happens before any device call
+    assert _lib.LIB.ba_status_str(-6) == b"BA_ERR_WORKSPACE"
     h = ctypes.c_void_p()
-    st = _lib.LIB.ba_plan_create(0, 0, 0, None, None, ctypes.byref(o), None, ctypes.byref(h))
+    st = _lib.LIB.ba_plan_create(0, 0, 0, None, None, ctypes.byref(o), None, None, None, None,
+                                 ctypes.byref(h))
     assert st == -1 and b"n_cam" in _lib.LIB.ba_last_error()
+    # one allocation callback without the other is refused before any device call
+    cb = _lib.ALLOC_FN(lambda n, ctx: None)
+    st = _lib.LIB.ba_plan_create(4, 4, 8, ctypes.c_void_p(256), ctypes.c_void_p(256), ctypes.byref(o), cb, None,
+                                 None, None, ctypes.byref(h))
+    assert st == -1 and b"callbacks" in _lib.LIB.ba_last_error()
+    # the workspace size of no plan is 0, with a message
+    assert _lib.LIB.ba_workspace_bytes(None, ctypes.byref(o), 0) == 0
+    assert b"plan" in _lib.LIB.ba_last_error()
 
 
 def _c_layout(tmp_path, types):
@@ -96,8 +106,9 @@ def test_lm_host_side_without_gpu():
     _lib.LIB.ba_opts_default(ctypes.byref(o))
     assert o.stop_rule == _lib.STOP_RESIDUAL and o.forcing == _lib.Options().forcing
     # null plan: rejected before any device work
-    assert _lib.LIB.ba_lm_solve(None, ctypes.byref(o), ctypes.byref(lo), None, None, None, None, None, None) == -1
-    assert _lib.LIB.ba_cost(None, None, None, None, None, None, None, None) == -1
+    assert _lib.LIB.ba_lm_solve(None, ctypes.byref(o), ctypes.byref(lo), None, None, None, None, 0, None, None,
+                                None) == -1
+    assert _lib.LIB.ba_cost(None, None, None, None, None, None, 0, None, None, None) == -1
     assert o.loss == _lib.LOSS_SQUARED and o.loss_scale == _lib.Options().loss_scale == 1.0
 
 
