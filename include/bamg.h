@@ -358,6 +358,17 @@ ba_status ba_lm_opts_default(ba_lm_opts* lo);
 ba_status ba_cost(ba_plan* p, const ba_opts* o, const double* cams, const double* pts, const double* uv,
                   void* ws, size_t ws_bytes, double* cost, int64_t* n_invalid, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): ba_cost
+ * without a workspace. Its kernels' scratch (camera records, reduction
+ * partials and counters) is a static device array of about 6.3 MB that each
+ * GPU the library runs on holds until the process ends, which takes plans of
+ * at most 32768 cameras (BA_ERR_LIMIT beyond). Every call on one GPU shares
+ * that array, so calls that overlap on one GPU (other streams or threads)
+ * race. Allocates nothing; otherwise as ba_cost. Blocks. */
+ba_status ba_cost_noalloc(ba_plan* p, const ba_opts* o, const double* cams, const double* pts,
+                          const double* uv, double* cost, int64_t* n_invalid, void* stream);
+
 /* Levenberg-Marquardt from (cams, pts), updated in place [n_cam][9], [n_pt][3].
  * Each iteration solves one step (as ba_lm_step, with lambda = 1 / radius; the
  * lambda of o is ignored and D = lambda diag(J^T J)), evaluates the model

@@ -220,6 +220,17 @@ class Plan:
                                     ctypes.byref(c), ctypes.byref(bad), _stream()))
         return c.value, bad.value
 
+    def cost_noalloc(self, cams, pts, uv, opts: Options | None = None):
+        """As cost(), through ba_cost_noalloc: no workspace, no allocation
+        (a static device scratch array shared by all calls on the GPU)."""
+        self._check_inputs(cams, pts, uv)
+        c = ctypes.c_double()
+        bad = ctypes.c_int64()
+        o = self._opts(opts)
+        _lib.check(_lib.LIB.ba_cost_noalloc(self._h, ctypes.byref(o), _ptr(cams), _ptr(pts), _ptr(uv),
+                                            ctypes.byref(c), ctypes.byref(bad), _stream()))
+        return c.value, bad.value
+
     def lm_solve(self, cams, pts, uv, opts: Options | None = None, lm_opts: LMOptions | None = None):
         """Levenberg-Marquardt from (cams, pts), which are updated in place.
         Returns an LMSummary with the per-iteration history."""

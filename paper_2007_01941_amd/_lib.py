@@ -180,6 +180,7 @@ def _load():
         "ba_selftest_tile_mma": [P, P, P, I32, P],
         "ba_lm_opts_default": [P],
         "ba_cost": [P, P, P, P, P, P, SZ, P, P, P],
+        "ba_cost_noalloc": [P, P, P, P, P, P, P, P],
         "ba_lm_solve": [P, P, P, P, P, P, P, SZ, P, P, P],
         "ba_status_str": [I32],
         "ba_last_error": [],
@@ -204,7 +205,7 @@ EXPORTED = ["ba_opts_default", "ba_plan_create", "ba_plan_destroy", "ba_plan_byt
             "ba_lm_step_backward", "ba_eval_jacobian", "ba_step_prepare", "ba_step_solve",
             "ba_schur_apply", "ba_schur_offdiag_apply", "ba_precond_apply", "ba_step_blocks", "ba_mg_levels",
             "ba_mg_aggregates", "ba_mg_covisibility", "ba_mg_level_data", "ba_selftest_tile_mma",
-            "ba_lm_opts_default", "ba_cost", "ba_lm_solve", "ba_status_str", "ba_last_error"]
+            "ba_lm_opts_default", "ba_cost", "ba_cost_noalloc", "ba_lm_solve", "ba_status_str", "ba_last_error"]
 
 
 def check(status: int, allow_not_converged=True):

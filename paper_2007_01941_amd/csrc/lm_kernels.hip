@@ -19,6 +19,7 @@ __global__ void k_lm_clear(LmScal* s) {
   if (threadIdx.x == 0) {
     s->invalid = 0u;
     s->camflag = 0u;
+    s->count[0] = s->count[1] = 0u;
   }
 }
 
