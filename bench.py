@@ -66,10 +66,10 @@ def kernel_source_hash():
 
 
 def read_traffic(scene, prec):
-    """HBM bytes per launch of k_schur_tiles<prec> on `scene` from the committed
+    """HBM bytes per launch of k_schur_groups<prec> on `scene` from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy
     kernel), if it was taken on the current kernel source; else None."""
-    path = os.path.join(PROFILE_DIR, f"k_schur_tiles_{scene}_traffic.txt")
+    path = os.path.join(PROFILE_DIR, f"k_schur_groups_{scene}_traffic.txt")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -125,7 +125,7 @@ def time_launches(fn, reps):
 
 def measure_products(bamg, plan, sc, cams, pts, uv, base, reps=50):
     """The implicit Schur product (A x included) per precision, and the tile
-    kernel alone (k_schur_tiles: y -= W C^-1 W^T x, one launch per call) with
+    kernel alone (k_schur_groups: y -= W C^-1 W^T x, one launch per call) with
     its roofline per precision."""
     import torch
     x = torch.randn(sc.n_cam, 9, dtype=torch.float64, device="cuda:0")
@@ -140,7 +140,7 @@ def measure_products(bamg, plan, sc, cams, pts, uv, base, reps=50):
         Bk = kernel_bytes(sc.n_obs, sc.n_pt, sc.n_cam, s)
         a = Bk / tk / 1e9
         kname = "double" if prec == "fp64" else "float"
-        roof[prec] = {"kernel": f"k_schur_tiles<{kname}>: y -= W C^-1 W^T x (implicit Schur product)",
+        roof[prec] = {"kernel": f"k_schur_groups<{kname}>: y -= W C^-1 W^T x (implicit Schur product)",
                       "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                       "frac": a / HBM_PEAK_GBPS, "traffic": read_traffic(sc.name, prec),
                       "algorithmic_bytes": Bk, "s_per_launch": tk}
@@ -228,7 +228,7 @@ def run_leg(bamg, name, cache, steps, warmup):
 
 def kernel_only(bamg, name, cache, reps):
     """Only the tile kernel, for counter collection: reps launches of
-    k_schur_tiles<double>, then of k_schur_tiles<float>, on `name`."""
+    k_schur_groups<double>, then of k_schur_groups<float>, on `name`."""
     import torch
     from scenes import cached_scene
     sc = cached_scene(name, cache)
