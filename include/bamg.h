@@ -75,6 +75,7 @@ enum { BA_FP64 = 0, BA_MIXED = 1 };
 enum { BA_OP_AUTO = 0, BA_OP_IMPLICIT = 1, BA_OP_EXPLICIT = 2 };
 enum { BA_STOP_RESIDUAL = 0, BA_STOP_NASH_SOFER = 1 };
 enum { BA_LOSS_SQUARED = 0, BA_LOSS_HUBER = 1 };
+enum { BA_PROLONG_TENTATIVE = 0, BA_PROLONG_SMOOTHED = 1 };
 
 typedef struct {
   int32_t precond;          /* BA_PC_BLOCK_JACOBI (point block Jacobi, Section 2.2), BA_PC_MULTIGRID,
@@ -112,7 +113,16 @@ typedef struct {
                                of Section 2.1 with a constant forcing sequence, Section 5). FP64 only:
                                BA_MIXED with BA_STOP_NASH_SOFER is BA_ERR_ARG. The backward pass
                                always uses the rtol test. */
-  int32_t reserved0;
+  int32_t prolongator;      /* BA_PROLONG_TENTATIVE (default): the unsmoothed prolongator of Section
+                               3.3, one QR block per node. BA_PROLONG_SMOOTHED: smoothed aggregation,
+                               the alternative Section 3.5 and the scaling experiment of Section 5.2
+                               set against it: P_s = (I - w D^-1 S) P with D the block diagonal of
+                               the level's operator S and w = smooth_omega / lambda_max(D^-1 S)
+                               (the smoother's Lanczos estimate); the coarse operators are
+                               P_s^T S P_s, with wider block rows (fill-in). A plan-time choice:
+                               ba_plan_create builds the coarse block patterns for it, and a
+                               multigrid step whose option differs from the plan's is BA_ERR_ARG.
+                               With BA_PC_MULTIGRID it needs BA_FP64. */
   double forcing;           /* tau of BA_STOP_NASH_SOFER, >= 0, default 0.1 */
   int32_t loss;             /* BA_LOSS_SQUARED (default), or BA_LOSS_HUBER: the robust loss of Section
                                5.4 on s_o = |f_o|^2, rho(s) = s for s <= a^2 and 2 a sqrt(s) - a^2
@@ -123,6 +133,7 @@ typedef struct {
                                ba_lm_step_backward (BA_ERR_ARG). */
   int32_t reserved1;
   double loss_scale;        /* a of BA_LOSS_HUBER, > 0, default 1 (pixels) */
+  double smooth_omega;      /* w * lambda_max of BA_PROLONG_SMOOTHED, in (0, 2), default 4/3 */
 } ba_opts;
 
 typedef struct {            /* (host) */
@@ -155,7 +166,8 @@ ba_status ba_opts_default(ba_opts* o);
 /* Build the integer structure reused by every LM step on the same visibility:
  * observation order, point tiles, the covisibility counts W = V V^T
  * (Section 3.2), greedy aggregation (Algorithm 2) on every level and the
- * block patterns of the coarse operators. Depends only on which camera sees
+ * block patterns of the coarse operators (for o->prolongator; the other
+ * fields of o are read at each step). Depends only on which camera sees
  * which point, never on parameter values.
  *   obs_cam, obs_pt: [n_obs] int32 device arrays, any order.
  *   Errors: BA_ERR_INDEX, BA_ERR_STRUCTURE, BA_ERR_LIMIT (n_obs >= 2^31, a
@@ -294,7 +306,10 @@ ba_status ba_mg_covisibility(const ba_plan* p, int32_t level, int64_t* nnz, int6
  *   what = 2: near-nullspace rows K [nodes][bs][16] of `level`;
  *   what = 3: inverse smoother blocks D^-1 [nodes][bs][bs];
  *   what = 4: lambda_max estimate of D^-1 S (1 value);
- *   what = 5: coarsest level only: inverse of its operator, dense [n][n]. */
+ *   what = 5: coarsest level only: inverse of its operator, dense [n][n];
+ *   what = 6: plans built for BA_PROLONG_SMOOTHED: the smoothed prolongator of
+ *             `level` as dense [nodes*bs][nodes(level+1)*16], only for
+ *             nodes*bs <= 16384. */
 ba_status ba_mg_level_data(const ba_plan* p, int32_t level, int32_t what, double* out,
                            void* stream);
 

@@ -169,7 +169,11 @@ class Plan:
         return int(_lib.LIB.ba_plan_bytes(self._h)) + (self._ws.numel() if self._ws is not None else 0)
 
     def _opts(self, opts):
-        return (opts or self.opts).to_c()
+        # the prolongator is fixed when the plan is built: steps take the plan's
+        o = opts or self.opts
+        if o.prolongator != self.opts.prolongator:
+            o = dataclasses.replace(o, prolongator=self.opts.prolongator)
+        return o.to_c()
 
     # ---- full step
     def lm_step(self, cams, pts, uv, D=None, opts: Options | None = None):
@@ -338,9 +342,10 @@ class Plan:
         n = nodes[level]
         bs = 9 if level == 0 else 16
         nv = n * bs
+        nc = nodes[level + 1] * 16 if level + 1 < len(nodes) else 0
         shapes = {"operator": (nv, nv), "P": (n, bs, 16), "K": (n, bs, 16), "Dinv": (n, bs, bs),
-                  "lmax": (1,), "coarse_inverse": (nv, nv)}
-        codes = {"operator": 0, "P": 1, "K": 2, "Dinv": 3, "lmax": 4, "coarse_inverse": 5}
+                  "lmax": (1,), "coarse_inverse": (nv, nv), "P_smoothed": (nv, nc)}
+        codes = {"operator": 0, "P": 1, "K": 2, "Dinv": 3, "lmax": 4, "coarse_inverse": 5, "P_smoothed": 6}
         out = torch.empty(shapes[what], dtype=torch.float64, device=device)
         _lib.check(_lib.LIB.ba_mg_level_data(self._h, level, codes[what], _ptr(out), _stream()))
         return out

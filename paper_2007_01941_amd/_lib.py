@@ -19,6 +19,7 @@ FP64, MIXED = 0, 1
 OP_AUTO, OP_IMPLICIT, OP_EXPLICIT = 0, 1, 2
 STOP_RESIDUAL, STOP_NASH_SOFER = 0, 1
 LOSS_SQUARED, LOSS_HUBER = 0, 1
+PROLONG_TENTATIVE, PROLONG_SMOOTHED = 0, 1
 TERM_MAX_ITERS, TERM_FUNCTION, TERM_PARAMETER, TERM_RADIUS = 0, 1, 2, 3
 USE_STEP, USE_BACKWARD, USE_LM = 0, 1, 2
 BA_ERR_WORKSPACE = -6
@@ -50,9 +51,9 @@ class _Opts(ctypes.Structure):
                 ("min_coarsen_ratio", ctypes.c_double),
                 ("level0_op", ctypes.c_int32), ("freeze_damping_in_grad", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("deterministic", ctypes.c_int32),
-                ("stop_rule", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("stop_rule", ctypes.c_int32), ("prolongator", ctypes.c_int32),
                 ("forcing", ctypes.c_double), ("loss", ctypes.c_int32), ("reserved1", ctypes.c_int32),
-                ("loss_scale", ctypes.c_double)]
+                ("loss_scale", ctypes.c_double), ("smooth_omega", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -129,6 +130,8 @@ class Options:
     forcing: float = 0.1
     loss: str = "squared"            # "squared" | "huber"
     loss_scale: float = 1.0
+    prolongator: str = "tentative"   # "tentative" | "smoothed" (fixed when the plan is built)
+    smooth_omega: float = 4.0 / 3.0
 
     def to_c(self) -> _Opts:
         o = _Opts()
@@ -147,6 +150,8 @@ class Options:
         o.forcing = self.forcing
         o.loss = {"squared": LOSS_SQUARED, "huber": LOSS_HUBER}[self.loss]
         o.loss_scale = self.loss_scale
+        o.prolongator = {"tentative": PROLONG_TENTATIVE, "smoothed": PROLONG_SMOOTHED}[self.prolongator]
+        o.smooth_omega = self.smooth_omega
         return o
 
 

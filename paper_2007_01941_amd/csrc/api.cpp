@@ -209,6 +209,8 @@ ba_status ba_opts_default(ba_opts* o) {
   o->forcing = 0.1;
   o->loss = BA_LOSS_SQUARED;
   o->loss_scale = 1.0;
+  o->prolongator = BA_PROLONG_TENTATIVE;
+  o->smooth_omega = 4.0 / 3.0;
   return BA_OK;
 }
 
@@ -235,6 +237,12 @@ static void validate_opts(const ba_opts* o) {
            "the Nash-Sofer rule needs forcing >= 0 and BA_FP64");
   BA_CHECK(o->loss == BA_LOSS_SQUARED || o->loss == BA_LOSS_HUBER, BA_ERR_ARG, "bad loss");
   BA_CHECK(o->loss == BA_LOSS_SQUARED || o->loss_scale > 0.0, BA_ERR_ARG, "loss_scale must be > 0");
+  BA_CHECK(o->prolongator == BA_PROLONG_TENTATIVE || o->prolongator == BA_PROLONG_SMOOTHED, BA_ERR_ARG,
+           "bad prolongator");
+  BA_CHECK(o->prolongator == BA_PROLONG_TENTATIVE || (o->smooth_omega > 0.0 && o->smooth_omega < 2.0), BA_ERR_ARG,
+           "smooth_omega must be in (0, 2)");
+  BA_CHECK(o->prolongator == BA_PROLONG_TENTATIVE || o->precond != BA_PC_MULTIGRID || o->precision == BA_FP64,
+           BA_ERR_ARG, "the smoothed prolongator is FP64 only");
   BA_CHECK(o->precision != BA_MIXED || (o->max_refine >= 1 && o->inner_rtol > 0.0 && o->inner_rtol < 1.0),
            BA_ERR_ARG, "bad refinement options");
 }
@@ -261,6 +269,7 @@ ba_status ba_plan_create(int32_t n_cam, int32_t n_pt, int64_t n_obs, const int32
     P->n_pt = n_pt;
     P->n_obs = n_obs;
     P->n_obs_pad = (n_obs + 63) / 64 * 64;
+    P->sa = o->prolongator == BA_PROLONG_SMOOTHED;
     P->errflag.alloc(1);
     BA_HIP(hipMemsetAsync(P->errflag.p, 0, sizeof(uint32_t), s));
     std::vector<int32_t> oc(n_obs), op(n_obs);
@@ -458,10 +467,10 @@ ba_status ba_mg_covisibility(const ba_plan* P, int32_t level, int64_t* nnz, int6
   BA_CHECK(P && nnz, BA_ERR_ARG, "null argument");
   BA_CHECK(level >= 0 && level < (int)P->levels.size(), BA_ERR_ARG, "bad level");
   const Level& L = P->levels[level];
-  *nnz = L.nnz;
-  if (row_ptr) BA_HIP(hipMemcpy(row_ptr, L.rowptr.p, (L.n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice));
-  if (col) BA_HIP(hipMemcpy(col, L.col.p, L.nnz * sizeof(int32_t), hipMemcpyDeviceToDevice));
-  if (val) BA_HIP(hipMemcpy(val, L.wval.p, L.nnz * sizeof(int64_t), hipMemcpyDeviceToDevice));
+  *nnz = L.wnnz;
+  if (row_ptr) BA_HIP(hipMemcpy(row_ptr, L.wrowptr.p, (L.n + 1) * sizeof(int64_t), hipMemcpyDeviceToDevice));
+  if (col) BA_HIP(hipMemcpy(col, L.wcol.p, L.wnnz * sizeof(int32_t), hipMemcpyDeviceToDevice));
+  if (val) BA_HIP(hipMemcpy(val, L.wval.p, L.wnnz * sizeof(int64_t), hipMemcpyDeviceToDevice));
   BA_API_END
 }
 

@@ -7,6 +7,7 @@
 // multigrid level (mg_plan_kernels.hip); the host then derives the block
 // patterns and Galerkin gather lists from the aggregates.
 #include <algorithm>
+#include <array>
 #include <numeric>
 
 #include "kernels.hpp"
@@ -272,21 +273,152 @@ static void build_covisibility(ba_plan* P, Level& L, LaunchPass launch, hipStrea
   std::vector<int32_t> h_nnz = row_nnz.download(s);
   uint32_t e = read_err(P, s);
   BA_CHECK(!(e & ERRF_LIMIT), BA_ERR_LIMIT, "a covisibility row exceeds %d entries", HASH_SLOTS * 3 / 4);
-  L.h_rowptr.assign(n + 1, 0);
-  for (int i = 0; i < n; ++i) L.h_rowptr[i + 1] = L.h_rowptr[i] + h_nnz[i];
-  L.nnz = L.h_rowptr[n];
-  L.rowptr.upload(L.h_rowptr, s);
-  L.col.alloc(L.nnz);
-  L.wval.alloc(L.nnz);
-  L.order.alloc(std::max<int64_t>(1, L.nnz - n));
-  launch(1, row_nnz.p, L.wdiag.p, L.rowptr.p, L.col.p, L.wval.p);
+  L.h_wrowptr.assign(n + 1, 0);
+  for (int i = 0; i < n; ++i) L.h_wrowptr[i + 1] = L.h_wrowptr[i] + h_nnz[i];
+  L.wnnz = L.h_wrowptr[n];
+  L.wrowptr.upload(L.h_wrowptr, s);
+  L.wcol.alloc(L.wnnz);
+  L.wval.alloc(L.wnnz);
+  L.order.alloc(std::max<int64_t>(1, L.wnnz - n));
+  launch(1, row_nnz.p, L.wdiag.p, L.wrowptr.p, L.wcol.p, L.wval.p);
   BA_LAUNCH_CHECK();
-  hipLaunchKernelGGL(k_row_sort, dim3(n), dim3(256), 0, s, L.rowptr.p, L.col.p, L.wval.p, L.wdiag.p,
+  hipLaunchKernelGGL(k_row_sort, dim3(n), dim3(256), 0, s, L.wrowptr.p, L.wcol.p, L.wval.p, L.wdiag.p,
                      L.order.p, P->errflag.p);
   BA_LAUNCH_CHECK();
   e = read_err(P, s);
   BA_CHECK(!(e & ERRF_LIMIT), BA_ERR_LIMIT, "a node is covisible with more than %d others", ROW_SORT_MAX - 1);
-  L.h_col = L.col.download(s);
+  L.h_wcol = L.wcol.download(s);
+}
+
+// The operator's block pattern is W's (level 0, and every level above an
+// unsmoothed prolongator).
+static void op_pattern_from_w(Level& L, hipStream_t s) {
+  L.nnz = L.wnnz;
+  L.h_rowptr = L.h_wrowptr;
+  L.h_col = L.h_wcol;
+  L.col.upload(L.h_col, s);
+  finish_level_pattern(L, s);
+}
+
+// Plan-time gather lists of the smoothed prolongator P_s = (I - w D^-1 S) P_t
+// of level F, of T = S P_s and of the Galerkin product P_s^T T that is C's
+// operator; C's block pattern is that product's (wider than C's covisibility:
+// the fill-in of smoothed aggregation). Every list is in a fixed order, so the
+// products are deterministic.
+static void build_sa_level(Level& F, Level& C, hipStream_t s) {
+  const int n = F.n, na = F.n_agg;
+  const std::vector<int32_t>& agg = F.h_agg;
+  // P_s: row i holds the aggregates of i's operator neighbours, i included;
+  // entry (i, a) sums S_ij P_t[j] over the neighbours j in aggregate a
+  std::vector<int32_t> psp(n + 1, 0), pscol, psrow, psself, srcp, src;
+  src.reserve(F.nnz);
+  {
+    std::vector<std::pair<int32_t, int32_t>> tmp;
+    for (int i = 0; i < n; ++i) {
+      tmp.clear();
+      for (int64_t q = F.h_rowptr[i]; q < F.h_rowptr[i + 1]; ++q) tmp.emplace_back(agg[F.h_col[q]], (int32_t)q);
+      std::sort(tmp.begin(), tmp.end());
+      for (size_t k = 0; k < tmp.size(); ++k) {
+        if (k == 0 || tmp[k].first != tmp[k - 1].first) {
+          pscol.push_back(tmp[k].first);
+          psrow.push_back(i);
+          psself.push_back(tmp[k].first == agg[i]);
+          srcp.push_back((int32_t)src.size());
+        }
+        src.push_back(tmp[k].second);
+      }
+      BA_CHECK(pscol.size() < (size_t)INT32_MAX, BA_ERR_LIMIT, "smoothed prolongator too large");
+      psp[i + 1] = (int32_t)pscol.size();
+    }
+    srcp.push_back((int32_t)src.size());
+  }
+  const int64_t nps = (int64_t)pscol.size();
+  // the entries of every aggregate's column, rows ascending
+  std::vector<int32_t> pstp(na + 1, 0), pste(nps);
+  for (int64_t e = 0; e < nps; ++e) ++pstp[pscol[e] + 1];
+  for (int a = 0; a < na; ++a) pstp[a + 1] += pstp[a];
+  {
+    std::vector<int32_t> cur(pstp.begin(), pstp.end() - 1);
+    for (int64_t e = 0; e < nps; ++e) pste[cur[pscol[e]]++] = (int32_t)e;
+  }
+  // T = S P_s: entry (i, b) sums S[q] P_s[e'] over operator entries q = (i, j)
+  // and P_s entries e' = (j, b)
+  std::vector<int64_t> tp(n + 1, 0);
+  std::vector<int32_t> tcol, tsp, tso, tsps;
+  {
+    std::vector<std::array<int32_t, 3>> tmp;
+    for (int i = 0; i < n; ++i) {
+      tmp.clear();
+      for (int64_t q = F.h_rowptr[i]; q < F.h_rowptr[i + 1]; ++q) {
+        const int j = F.h_col[q];
+        for (int32_t e = psp[j]; e < psp[j + 1]; ++e) tmp.push_back({pscol[e], (int32_t)q, e});
+      }
+      std::sort(tmp.begin(), tmp.end());
+      BA_CHECK(tso.size() + tmp.size() < (size_t)INT32_MAX, BA_ERR_LIMIT, "smoothed Galerkin product too large");
+      for (size_t k = 0; k < tmp.size(); ++k) {
+        if (k == 0 || tmp[k][0] != tmp[k - 1][0]) {
+          tcol.push_back(tmp[k][0]);
+          tsp.push_back((int32_t)tso.size());
+        }
+        tso.push_back(tmp[k][1]);
+        tsps.push_back(tmp[k][2]);
+      }
+      tp[i + 1] = (int64_t)tcol.size();
+    }
+    tsp.push_back((int32_t)tso.size());
+  }
+  const int64_t nt = (int64_t)tcol.size();
+  BA_CHECK(nt < (int64_t)INT32_MAX && (int64_t)tsp.size() == nt + 1, BA_ERR_LIMIT, "S P_s too large");
+  // C = P_s^T T: entry (a, b) sums P_s[e]^T T[t] over rows i with e = (i, a)
+  // and t = (i, b)
+  C.h_rowptr.assign(na + 1, 0);
+  C.h_col.clear();
+  std::vector<int32_t> cgp, cgps, cgt;
+  {
+    std::vector<std::array<int32_t, 3>> tmp;
+    for (int a = 0; a < na; ++a) {
+      tmp.clear();
+      for (int32_t k = pstp[a]; k < pstp[a + 1]; ++k) {
+        const int32_t e = pste[k];
+        const int i = psrow[e];
+        for (int64_t t = tp[i]; t < tp[i + 1]; ++t) tmp.push_back({tcol[t], e, (int32_t)t});
+      }
+      std::sort(tmp.begin(), tmp.end());
+      BA_CHECK(cgps.size() + tmp.size() < (size_t)INT32_MAX, BA_ERR_LIMIT, "smoothed Galerkin product too large");
+      for (size_t k = 0; k < tmp.size(); ++k) {
+        if (k == 0 || tmp[k][0] != tmp[k - 1][0]) {
+          C.h_col.push_back(tmp[k][0]);
+          cgp.push_back((int32_t)cgps.size());
+        }
+        cgps.push_back(tmp[k][1]);
+        cgt.push_back(tmp[k][2]);
+      }
+      C.h_rowptr[a + 1] = (int64_t)C.h_col.size();
+    }
+    cgp.push_back((int32_t)cgps.size());
+  }
+  C.nnz = (int64_t)C.h_col.size();
+  BA_CHECK((int64_t)cgp.size() == C.nnz + 1, BA_ERR_STRUCTURE, "internal: smoothed Galerkin lists");
+  C.col.upload(C.h_col, s);
+  finish_level_pattern(C, s);
+  F.nnz_ps = nps;
+  F.nnz_t = nt;
+  F.ps_ptr.upload(psp, s);
+  F.ps_col.upload(pscol, s);
+  F.ps_row.upload(psrow, s);
+  F.ps_self.upload(psself, s);
+  F.ps_src_ptr.upload(srcp, s);
+  F.ps_src.upload(src, s);
+  F.pst_ptr.upload(pstp, s);
+  F.pst_e.upload(pste, s);
+  F.t_src_ptr.upload(tsp, s);
+  F.t_src_op.upload(tso, s);
+  F.t_src_ps.upload(tsps, s);
+  F.cg_ptr.upload(cgp, s);
+  F.cg_ps.upload(cgps, s);
+  F.cg_t.upload(cgt, s);
+  // the host vectors go out of scope here: the uploads must have completed
+  BA_HIP(hipStreamSynchronize(s));
 }
 
 // Shared points of every upper off-diagonal block of the level-0 pattern: for
@@ -344,12 +476,12 @@ static void aggregate_level(ba_plan* P, Level& L, int cap, hipStream_t s) {
   nagg.alloc(1);
   const size_t lds = (size_t)n * 2 * sizeof(int);
   if (lds <= 150 * 1024) {
-    hipLaunchKernelGGL(k_aggregate_lds, dim3(1), dim3(64), lds, s, n, L.rowptr.p, L.order.p, cap,
+    hipLaunchKernelGGL(k_aggregate_lds, dim3(1), dim3(64), lds, s, n, L.wrowptr.p, L.order.p, cap,
                        agg.p, nagg.p);
   } else {
     DBuf<int32_t> size;
     size.alloc(n);
-    hipLaunchKernelGGL(k_aggregate_global, dim3(1), dim3(64), 0, s, n, L.rowptr.p, L.order.p, cap,
+    hipLaunchKernelGGL(k_aggregate_global, dim3(1), dim3(64), 0, s, n, L.wrowptr.p, L.order.p, cap,
                        agg.p, size.p, nagg.p);
     BA_HIP(hipStreamSynchronize(s));
   }
@@ -376,7 +508,7 @@ static void build_hierarchy(ba_plan* P, const ba_opts* o, hipStream_t s) {
         hipLaunchKernelGGL(k_covis0<1>, dim3(L0.n), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->obs_pt.p,
                            P->pt_off.p, P->obs_cam.p, nnz, wd, rp, col, val, P->errflag.p);
     }, s);
-    finish_level_pattern(L0, s);
+    op_pattern_from_w(L0, s);
     build_s0_pairs(P, L0, s);
   }
   for (;;) {
@@ -413,13 +545,17 @@ static void build_hierarchy(ba_plan* P, const ba_opts* o, hipStream_t s) {
     C.bs = NS;
     build_covisibility(P, C, [&](int pass, int32_t* nnz, int64_t* wd, const int64_t* rp, int32_t* col, int64_t* val) {
       if (pass == 0)
-        hipLaunchKernelGGL(k_covisL<0>, dim3(C.n), dim3(256), 0, s, F.agg_ptr.p, F.agg_mem.p, F.rowptr.p, F.col.p,
+        hipLaunchKernelGGL(k_covisL<0>, dim3(C.n), dim3(256), 0, s, F.agg_ptr.p, F.agg_mem.p, F.wrowptr.p, F.wcol.p,
                            F.wval.p, F.agg.p, nnz, wd, rp, col, val, P->errflag.p);
       else
-        hipLaunchKernelGGL(k_covisL<1>, dim3(C.n), dim3(256), 0, s, F.agg_ptr.p, F.agg_mem.p, F.rowptr.p, F.col.p,
+        hipLaunchKernelGGL(k_covisL<1>, dim3(C.n), dim3(256), 0, s, F.agg_ptr.p, F.agg_mem.p, F.wrowptr.p, F.wcol.p,
                            F.wval.p, F.agg.p, nnz, wd, rp, col, val, P->errflag.p);
     }, s);
-    finish_level_pattern(C, s);
+    if (P->sa) {
+      build_sa_level(F, C, s);
+      continue;
+    }
+    op_pattern_from_w(C, s);
     // Galerkin gather lists: coarse entry (A, B) <- fine entries (i, j), agg(i)=A, agg(j)=B
     std::vector<int32_t> cidx(F.nnz);
     std::vector<int32_t> gptr(C.nnz + 1, 0);

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
     if (EP == EP_CHEB || EP == EP_CHEB_POST) x0 = x_in[k];
   }
   int slot = 0;
-  if (EP == EP_RESID && threadIdx.x < NS) slot = slot_of[row];
+  if (EP == EP_RESID && rpart && threadIdx.x < NS) slot = slot_of[row];
   T acc = 0;
   if (pidx < PARTS) {
     const int e1 = rowptr[row + 1];
@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
   if (EP == EP_STORE) return;
   __syncthreads();
   if (EP == EP_RESID) {
-    if (threadIdx.x < NS) {
+    if (rpart && threadIdx.x < NS) {
       const T* Pi = P + (size_t)row * BS * NS + threadIdx.x;
       T sacc = 0;
 #pragma unroll

@@ -10,17 +10,23 @@ namespace bamg {
 struct Level {
   int n = 0;    // nodes
   int bs = 9;   // dofs per node: 9 on level 0, 16 above
-  // covisibility W of this level: CSR, sorted columns, diagonal included.
-  // Its pattern is also the block pattern of this level's operator.
+  // covisibility W of this level (the aggregation graph): CSR with sorted
+  // columns, diagonal included
+  int64_t wnnz = 0;
+  std::vector<int64_t> h_wrowptr;
+  std::vector<int32_t> h_wcol;
+  DBuf<int64_t> wrowptr;
+  DBuf<int32_t> wcol;
+  DBuf<int64_t> wval;
+  DBuf<int64_t> wdiag;       // W_ii
+  DBuf<int32_t> order;       // neighbours by decreasing strength: row i at [wrowptr[i]-i, wrowptr[i+1]-i-1)
+  // block pattern of this level's operator: W's pattern, except above a
+  // smoothed prolongator, whose Galerkin product fills in (then wider)
   int64_t nnz = 0;
   std::vector<int64_t> h_rowptr;
   std::vector<int32_t> h_col;
-  DBuf<int64_t> rowptr;
-  DBuf<int32_t> rowptr32;    // same as rowptr, int32 (block kernels)
+  DBuf<int32_t> rowptr32;
   DBuf<int32_t> col;
-  DBuf<int64_t> wval;
-  DBuf<int64_t> wdiag;       // W_ii
-  DBuf<int32_t> order;       // neighbours by decreasing strength: row i at [rowptr[i]-i, rowptr[i+1]-i-1)
   DBuf<int32_t> diag_pos;    // CSR position of (i, i)
   DBuf<int32_t> trans_pos;   // CSR position of (j, i) for entry (i, j)
   DBuf<int32_t> row_of;      // row index of every CSR entry
@@ -36,11 +42,26 @@ struct Level {
   // Galerkin map: coarse CSR entry e gathers fine entries gal_fine[gal_ptr[e] .. gal_ptr[e+1])
   DBuf<int32_t> gal_ptr;
   DBuf<int32_t> gal_fine;
+  // smoothed prolongator P_s = (I - w D^-1 S) P_t to the next level (plans
+  // built for it), CSR by node (row pointer ps_ptr): entry e = (node
+  // ps_row[e], aggregate ps_col[e]); its terms S_ij P_t[j] come from the
+  // operator entries ps_src[ps_src_ptr[e] ..), and ps_self[e] marks the
+  // aggregate of the node itself (P_t's own block).
+  int64_t nnz_ps = 0, nnz_t = 0;
+  DBuf<int32_t> ps_ptr, ps_col, ps_row, ps_self, ps_src_ptr, ps_src;
+  DBuf<int32_t> pst_ptr, pst_e;   // P_s entries by aggregate (rows ascending)
+  // T = S P_s (node x aggregate blocks): entry t sums S[t_src_op] P_s[t_src_ps] over t_src_ptr[t] ..
+  DBuf<int32_t> t_src_ptr, t_src_op, t_src_ps;
+  // the next level's operator P_s^T T: its entry c sums P_s[cg_ps]^T T[cg_t]
+  // over cg_ptr[c] ..
+  DBuf<int32_t> cg_ptr, cg_ps, cg_t;
   // ---- numeric, per step
   DBuf<double> S;            // nnz * bs * bs  explicit operator (level 0: explicit Schur S)
   DBuf<float> S32;
   DBuf<double> K;            // n * bs * NS near-nullspace rows
   DBuf<double> P;            // n * bs * NS tentative prolongator blocks (to level + 1)
+  DBuf<double> Ps;           // nnz_ps * bs * NS smoothed prolongator blocks
+  DBuf<double> Tsp;          // nnz_t * bs * NS blocks of S P_s
   DBuf<float> P32;
   DBuf<double> Dinv;         // n * bs * bs inverse diagonal blocks
   DBuf<float> Dinv32;
@@ -152,6 +173,7 @@ struct ba_plan {
   bool inspectable_mg = false;   // hierarchy data readable (also after a failed setup)
   bool have_mixed = false;
   bool det = false;               // the prepared step runs without floating-point atomics
+  bool sa = false;                // hierarchy built for the smoothed prolongator (Section 3.5)
   double lambda = 1e-4;
   // ---- workspace binding: the per-step buffers above are views into it
   bamg::DBuf<char> own_ws;        // the plan's own workspace (callers passing ws == NULL)

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <string>
 #include <thread>
+#include <type_traits>
 
 namespace bamg {
 
@@ -22,9 +23,13 @@ static size_t plan_bytes(const ba_plan* P) {
   b += P->s0_blk_e.bytes() + P->s0_blk_ch.bytes() + P->cam_te_ptr.bytes() + P->cam_te.bytes() + P->cj_off.bytes();
   b += P->errflag.bytes() + P->own_ws.bytes();
   for (const Level& L : P->levels) {
-    b += L.rowptr.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() + L.order.bytes();
+    b += L.wrowptr.bytes() + L.wcol.bytes() + L.rowptr32.bytes() + L.col.bytes() + L.wval.bytes() + L.wdiag.bytes() +
+         L.order.bytes();
     b += L.diag_pos.bytes() + L.trans_pos.bytes() + L.row_of.bytes() + L.agg.bytes() + L.agg_ptr.bytes();
     b += L.agg_mem.bytes() + L.agg_pos.bytes() + L.slot_of.bytes() + L.gal_ptr.bytes() + L.gal_fine.bytes();
+    for (const DBuf<int32_t>* v : {&L.ps_ptr, &L.ps_col, &L.ps_row, &L.ps_self, &L.ps_src_ptr, &L.ps_src, &L.pst_ptr,
+                                   &L.pst_e, &L.t_src_ptr, &L.t_src_op, &L.t_src_ps, &L.cg_ptr, &L.cg_ps, &L.cg_t})
+      b += v->bytes();
   }
   return b;
 }
@@ -108,7 +113,7 @@ static size_t layout_ws(ba_plan* P, uint32_t key, char* base) {
     if (base) {
       for (DBuf<double>* v : {&L.S, &L.K, &L.P, &L.Dinv, &L.dense, &L.inv, &L.gj_scale, &L.gj_piv, &L.vb, &L.vx,
                               &L.vr, &L.vd, &L.vt, &L.vpart, &L.vd2, &L.vx2, &L.lz_u, &L.lz_v, &L.lz_up, &L.lz_vp,
-                              &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw, &L.lz_s})
+                              &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw, &L.lz_s, &L.Ps, &L.Tsp})
         v->view(nullptr, 0);
       for (DBuf<float>* v : {&L.S32, &L.P32, &L.Dinv32, &L.fb, &L.fx, &L.fr, &L.fd, &L.ft, &L.fpart, &L.fd2, &L.fx2})
         v->view(nullptr, 0);
@@ -126,6 +131,10 @@ static size_t layout_ws(ba_plan* P, uint32_t key, char* base) {
       for (DBuf<double>* v : {&L.lz_u, &L.lz_v, &L.lz_up, &L.lz_vp, &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw})
         c.take(*v, nv);
       c.take(L.lz_s, 68);
+      if (P->sa) {
+        c.take(L.Ps, (size_t)L.nnz_ps * L.bs * NS);
+        c.take(L.Tsp, (size_t)L.nnz_t * L.bs * NS);
+      }
     } else {
       L.nd = (int)((nv + GJB - 1) / GJB * GJB);
       c.take(L.dense, (size_t)L.nd * L.nd);
@@ -420,6 +429,30 @@ void coarse_correction<float>(ba_plan* P, const ba_opts* o, int l, float* bc, fl
   convert((size_t)C.n * C.bs, (const double*)C.vx.p, xc, s);
 }
 
+// Restriction and prolongation with the smoothed prolongator of level l
+// (FP64 only: plans built for it reject BA_MIXED multigrid steps).
+template <int BS, class T>
+static void sa_restrict(ba_plan* P, int l, const T* r, const T* t, T* bc, const int* done, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    const Level& L = P->levels[l];
+    hipLaunchKernelGGL((k_sa_restrict<BS>), dim3(grid_of<double>((int64_t)L.n_agg * NS)), dim3(256), 0, s, L.n_agg,
+                       L.pst_ptr.p, L.pst_e.p, L.ps_row.p, (const double*)L.Ps.p, r, t, bc, done);
+  } else {
+    BA_CHECK(false, BA_ERR_ARG, "the smoothed prolongator is FP64 only");
+  }
+}
+
+template <int BS, class T>
+static void sa_prolong(ba_plan* P, int l, const T* xc, T* x, const int* done, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    const Level& L = P->levels[l];
+    hipLaunchKernelGGL((k_sa_prolong<BS>), dim3(grid_of<double>((int64_t)L.n * BS)), dim3(256), 0, s, L.n,
+                       L.ps_ptr.p, L.ps_col.p, (const double*)L.Ps.p, xc, x, done);
+  } else {
+    BA_CHECK(false, BA_ERR_ARG, "the smoothed prolongator is FP64 only");
+  }
+}
+
 // One V-cycle level (Algorithm 1) with the explicit level operator: every
 // Chebyshev step after the first is one fused block-row launch (product and
 // update), with the direction d and, in post-smoothing, the iterate
@@ -444,11 +477,11 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, 
   double rho = 1.0 / sigma1;
   hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, pend.part ? 2 : 0, Dinv, b,
                      (const T*)nullptr, r, dA, x, (T)(1.0 / theta), pend.agg_ptr, pend.part, done);
-  T* part = LvVec<T>::part(L);
+  T* part = P->sa ? nullptr : LvVec<T>::part(L);
   for (int k = 0; k < m; ++k) {
     if (k == m - 1) {
       // last pre-smoothing residual update r -= S d (the V-cycle residual),
-      // with each node's restriction partial P_i^T r_i
+      // with each node's restriction partial P_i^T r_i (unsmoothed P)
       row_op<BS, T, EP_RESID>(P, l, dA, nullptr, r, nullptr, nullptr, nullptr, nullptr, 0.0, 0.0, part, done, s);
       break;
     }
@@ -457,15 +490,21 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, 
     std::swap(dA, dB);
     rho = rn;
   }
-  // the coarse right-hand side is summed from the partials by the next level
   T* bc = LvVec<T>::b(C);
   T* xc = LvVec<T>::x(C);
-  Pending<T> next;
-  next.agg_ptr = L.agg_ptr.p;
-  next.part = part;
-  coarse_correction<T>(P, o, l, bc, xc, next, done, s);
-  hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
-                     lvP<T>(L), (const T*)xc, x, done);
+  if (P->sa) {
+    sa_restrict<BS, T>(P, l, r, nullptr, bc, done, s);
+    coarse_correction<T>(P, o, l, bc, xc, Pending<T>(), done, s);
+    sa_prolong<BS, T>(P, l, xc, x, done, s);
+  } else {
+    // the coarse right-hand side is summed from the partials by the next level
+    Pending<T> next;
+    next.agg_ptr = L.agg_ptr.p;
+    next.part = part;
+    coarse_correction<T>(P, o, l, bc, xc, next, done, s);
+    hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
+                       lvP<T>(L), (const T*)xc, x, done);
+  }
   // post-smoothing from x: r = b - S x, d = D^-1 r / theta, iterate -> x2
   rho = 1.0 / sigma1;
   row_op<BS, T, EP_CHEB_POST>(P, l, x, b, r, nullptr, dA, x, x2, 0.0, 1.0 / theta, nullptr, done, s);
@@ -517,14 +556,20 @@ static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pendin
   // restriction of the pre-smoother's residual r - t
   T* bc = LvVec<T>::b(C);
   T* xc = LvVec<T>::x(C);
-  T* part = LvVec<T>::part(L);
-  hipLaunchKernelGGL((k_restrict_nodes<BS, T>), dim3(grid_of<T>((int64_t)L.n * NS)), dim3(256), 0, s, L.n,
-                     L.slot_of.p, lvP<T>(L), (const T*)r, (const T*)t, part, done);
-  hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n, L.agg_ptr.p,
-                     (const T*)part, bc, done);
-  coarse_correction<T>(P, o, l, bc, xc, Pending<T>(), done, s);
-  hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
-                     lvP<T>(L), (const T*)xc, x, done);
+  if (P->sa) {
+    sa_restrict<BS, T>(P, l, r, t, bc, done, s);
+    coarse_correction<T>(P, o, l, bc, xc, Pending<T>(), done, s);
+    sa_prolong<BS, T>(P, l, xc, x, done, s);
+  } else {
+    T* part = LvVec<T>::part(L);
+    hipLaunchKernelGGL((k_restrict_nodes<BS, T>), dim3(grid_of<T>((int64_t)L.n * NS)), dim3(256), 0, s, L.n,
+                       L.slot_of.p, lvP<T>(L), (const T*)r, (const T*)t, part, done);
+    hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n,
+                       L.agg_ptr.p, (const T*)part, bc, done);
+    coarse_correction<T>(P, o, l, bc, xc, Pending<T>(), done, s);
+    hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
+                       lvP<T>(L), (const T*)xc, x, done);
+  }
   // post-smoothing from x
   op_apply<T>(P, l, x, t, done, s);
   rho = 1.0 / sigma1;
@@ -757,6 +802,60 @@ static void cluster_setup(ba_plan* P, hipStream_t s) {
   P->prepared_cj = true;
 }
 
+// Numeric setup with the smoothed prolongator, level by level on one stream:
+// each level's P_s needs lambda_max of that level's operator (read back to the
+// host), and the next level's operator needs P_s. Per level: QR (P_t and the
+// coarse K), Lanczos, P_s = (I - w/lambda D^-1 S) P_t, T = S P_s, C = P_s^T T
+// and C's smoother blocks; then the coarsest level's dense inverse.
+static void mg_setup_sa(ba_plan* P, const ba_opts* o, const double* cams, hipStream_t s) {
+  const int nl = (int)P->levels.size();
+  Level& L0 = P->levels[0];
+  hipLaunchKernelGGL(k_nullspace0, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
+                     L0.K.p);
+  assemble_s0(P, s);
+  L0.explicit_op = level0_explicit(P, o, 8);
+  std::vector<double> h(68);
+  for (int l = 0; l + 1 < nl; ++l) {
+    Level& F = P->levels[l];
+    Level& C = P->levels[l + 1];
+    const size_t lds = (size_t)2 * F.max_agg * F.bs * NS * sizeof(double);
+    BA_CHECK(lds <= 160 * 1024, BA_ERR_LIMIT, "aggregate with %d nodes exceeds the QR kernel's LDS", F.max_agg);
+    hipLaunchKernelGGL(k_qr_aggregates, dim3(F.n_agg), dim3(64), lds, s, F.bs, F.agg_ptr.p, F.agg_mem.p, F.K.p,
+                       F.P.p, C.K.p);
+    lanczos_launch(P, o, l, s);
+    BA_HIP(hipMemcpyAsync(h.data(), F.lz_s.p, 68 * sizeof(double), hipMemcpyDeviceToHost, s));
+    check_errflag(P, s, "multigrid setup (QR, smoother blocks)");
+    F.lmax = lanczos_finish(h.data(), o->lanczos_steps);
+    const double c = o->smooth_omega / F.lmax;
+    const double* Dinv = lvDinv<double>(P, l);
+    if (F.bs == 9) {
+      hipLaunchKernelGGL((k_sa_product<9, true>), dim3((unsigned)F.nnz_ps), dim3(256), 0, s, F.ps_src_ptr.p,
+                         F.ps_src.p, F.col.p, F.S.p, F.P.p, F.ps_row.p, F.ps_self.p, F.P.p, Dinv, c, F.Ps.p);
+      hipLaunchKernelGGL((k_sa_product<9, false>), dim3((unsigned)F.nnz_t), dim3(256), 0, s, F.t_src_ptr.p,
+                         F.t_src_op.p, F.t_src_ps.p, F.S.p, F.Ps.p, (const int32_t*)nullptr,
+                         (const int32_t*)nullptr, (const double*)nullptr, (const double*)nullptr, 0.0, F.Tsp.p);
+      hipLaunchKernelGGL((k_sa_galerkin<9>), dim3((unsigned)C.nnz), dim3(256), 0, s, F.cg_ptr.p, F.cg_ps.p,
+                         F.cg_t.p, F.Ps.p, F.Tsp.p, C.S.p);
+    } else {
+      hipLaunchKernelGGL((k_sa_product<16, true>), dim3((unsigned)F.nnz_ps), dim3(256), 0, s, F.ps_src_ptr.p,
+                         F.ps_src.p, F.col.p, F.S.p, F.P.p, F.ps_row.p, F.ps_self.p, F.P.p, Dinv, c, F.Ps.p);
+      hipLaunchKernelGGL((k_sa_product<16, false>), dim3((unsigned)F.nnz_t), dim3(256), 0, s, F.t_src_ptr.p,
+                         F.t_src_op.p, F.t_src_ps.p, F.S.p, F.Ps.p, (const int32_t*)nullptr,
+                         (const int32_t*)nullptr, (const double*)nullptr, (const double*)nullptr, 0.0, F.Tsp.p);
+      hipLaunchKernelGGL((k_sa_galerkin<16>), dim3((unsigned)C.nnz), dim3(256), 0, s, F.cg_ptr.p, F.cg_ps.p,
+                         F.cg_t.p, F.Ps.p, F.Tsp.p, C.S.p);
+    }
+    if (l + 1 < nl - 1)
+      hipLaunchKernelGGL(k_diag_inverse16, dim3(C.n), dim3(64), 0, s, C.diag_pos.p, C.S.p, C.Dinv.p, P->errflag.p);
+    BA_LAUNCH_CHECK();
+  }
+  coarse_inverse(P, o, s);
+  BA_LAUNCH_CHECK();
+  P->inspectable_mg = true;
+  check_errflag(P, s, "multigrid setup (smoothed prolongator, Galerkin, coarse inverse)");
+  P->prepared_mg = true;
+}
+
 static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixed, hipStream_t s) {
   const int nl = (int)P->levels.size();
   Level& L0 = P->levels[0];
@@ -847,6 +946,8 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   const bool mixed = o->precision == BA_MIXED;
   const uint32_t need = ws_key(o, 0);
   BA_CHECK((P->ws_key & need) == need, BA_ERR_ARG, "internal: the bound workspace does not fit the options");
+  BA_CHECK(o->precond != BA_PC_MULTIGRID || (o->prolongator == BA_PROLONG_SMOOTHED) == P->sa, BA_ERR_ARG,
+           "the plan was built for the %s prolongator", P->sa ? "smoothed" : "tentative");
   invalidate_step(P);
   P->lambda = o->lambda;
   P->det = o->deterministic != 0;
@@ -870,7 +971,10 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   P->have_mixed = mixed;
   P->prepared = true;
   Timer ts(s);
-  if (o->precond == BA_PC_MULTIGRID) mg_setup(P, o, cams, mixed, s);
+  if (o->precond == BA_PC_MULTIGRID) {
+    if (P->sa) mg_setup_sa(P, o, cams, s);
+    else mg_setup(P, o, cams, mixed, s);
+  }
   if (o->precond == BA_PC_CLUSTER_JACOBI) cluster_setup(P, s);
   const double tset = ts.ms();
   if (st) {
@@ -1066,6 +1170,16 @@ static void level_data(const ba_plan* Pc, int l, int what, double* out, hipStrea
       BA_HIP(hipMemcpy2DAsync(out, nv * sizeof(double), L.inv.p, (size_t)L.nd * sizeof(double), nv * sizeof(double),
                               nv, hipMemcpyDeviceToDevice, s));
       break;
+    case 6: {
+      BA_CHECK(P->sa, BA_ERR_ARG, "the plan was not built for the smoothed prolongator");
+      BA_CHECK(l + 1 < nl, BA_ERR_ARG, "the coarsest level has no prolongator");
+      BA_CHECK(nv <= 16384, BA_ERR_LIMIT, "level too large for a dense copy");
+      const int ncols = P->levels[l + 1].n * NS;
+      BA_HIP(hipMemsetAsync(out, 0, nv * ncols * sizeof(double), s));
+      hipLaunchKernelGGL(k_sa_to_dense, dim3(grid_of<double>(L.nnz_ps * L.bs * NS)), dim3(256), 0, s, L.nnz_ps,
+                         L.bs, ncols, L.ps_row.p, L.ps_col.p, L.Ps.p, out);
+      break;
+    }
     default:
       BA_CHECK(false, BA_ERR_ARG, "bad `what`");
   }
