@@ -269,6 +269,11 @@ def main():
                          "long-range error instead of the benchmark (one JSON line per run, then a summary)")
     ap.add_argument("--scaling-lm", action="store_true",
                     help="with --scaling: time whole LM runs (Nash-Sofer tau 0.01) to a common final cost")
+    ap.add_argument("--scaling-lambda", type=float, default=1e-4,
+                    help="Marquardt damping of the --scaling linear solves (smaller: closer to the late LM "
+                         "iterations, whose large trust radius leaves the long-range modes nearly undamped)")
+    ap.add_argument("--scaling-loss", default="huber", choices=["huber", "squared"],
+                    help="loss of the --scaling-lm runs (Huber, as in the paper's LM experiment)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device-to-device 5 times (reference kernel for HBM counters)")
     args = ap.parse_args()
@@ -300,9 +305,9 @@ def main():
     if args.scaling:
         ks = [int(k) for k in args.scaling.split(",")]
         if args.scaling_lm:
-            run_scaling_lm(ks, args.lm_iters)
+            run_scaling_lm(ks, args.lm_iters, args.scaling_loss)
         else:
-            run_scaling(ks, max(1, args.steps), args.warmup)
+            run_scaling(ks, max(1, args.steps), args.warmup, args.scaling_lambda)
         return
 
     dev = torch.device("cuda:0")
@@ -357,6 +362,18 @@ def main():
             vms, _, s2, vdc, _ = time_steps(plan, cams, pts, uv, opts, max(2, args.steps // 2), 1)
             var[name] = step_entry(vms, s2, vdc, dc)
             log(f"[bench] {name}: {vms:.2f} ms/step, iters {s2.iters}, rel_res {s2.rel_res:.2e}")
+        # smoothed aggregation needs a plan built for it (its coarse patterns fill in)
+        t0 = time.time()
+        sa_opts = bamg.Options(precond="mg", precision="fp64", prolongator="smoothed", **base)
+        sa_plan = bamg.Plan(sc.n_cam, sc.n_pt, oc, op, sa_opts)
+        torch.cuda.synchronize()
+        sa_plan_s = time.time() - t0
+        vms, _, s2, vdc, _ = time_steps(sa_plan, cams, pts, uv, sa_opts, max(2, args.steps // 2), 1)
+        var["mg_fp64_smoothed"] = dict(step_entry(vms, s2, vdc, dc), plan_s=sa_plan_s,
+                                       device_bytes=sa_plan.device_bytes)
+        log(f"[bench] mg_fp64_smoothed: {vms:.2f} ms/step, iters {s2.iters}, setup {s2.t_setup_ms:.2f} ms, "
+            f"solve {s2.t_solve_ms:.2f} ms, plan {sa_plan_s:.2f} s, {sa_plan.device_bytes / 2**30:.2f} GiB")
+        del sa_plan
         result["variants"] = var
 
     # ---- differentiation form: the adjoint of the step (loss |delta|^2, so dL/d delta = 2 delta)
@@ -412,15 +429,50 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def run_scaling(ks, steps, warmup):
-    """Solve time and PCG iterations of one LM linear solve (FP64, rtol 1e-6) with
-    multigrid, point block Jacobi and visibility-based block Jacobi on k x k
-    city grids whose initial values carry a sine-wave long-range error (the
-    growing-diameter problems of the paper's scaling experiment); the summary
-    fits time ~ n_cam^e per preconditioner."""
+SCALING_PRECONDS = ("mg", "sa", "bj", "cj")
+
+
+def scaling_plans(sc, dev):
+    """One plan per hierarchy kind on a scene: the unsmoothed one (serves mg,
+    bj and cj) and one built for the smoothed prolongator (sa)."""
     import numpy as np
     import torch
     import paper_2007_01941_amd as bamg
+    T = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int32, device=dev)
+    plain = bamg.Plan(sc.n_cam, sc.n_pt, T(sc.obs_cam), T(sc.obs_pt), bamg.Options(precond="mg"))
+    smooth = bamg.Plan(sc.n_cam, sc.n_pt, T(sc.obs_cam), T(sc.obs_pt),
+                       bamg.Options(precond="mg", prolongator="smoothed"))
+    return {"mg": plain, "bj": plain, "cj": plain, "sa": smooth}
+
+
+def scaling_opts(pc, **kw):
+    import paper_2007_01941_amd as bamg
+    if pc == "sa":
+        return bamg.Options(precond="mg", prolongator="smoothed", **kw)
+    return bamg.Options(precond=pc, **kw)
+
+
+def fit_exponents(rows, keys):
+    import numpy as np
+    fits = {}
+    for pc in SCALING_PRECONDS:
+        r = [x for x in rows if x["precond"] == pc]
+        if len(r) >= 2:
+            n = np.log([x["n_cam"] for x in r])
+            fits[pc] = {k: float(np.polyfit(n, np.log([max(x[k], 1e-9) for x in r]), 1)[0]) for k in keys}
+    return fits
+
+
+def run_scaling(ks, steps, warmup, lam=1e-4):
+    """Fig. 6's experiment: one LM linear solve (FP64, rtol 1e-6) with
+    multigrid (unsmoothed and smoothed aggregation), point block Jacobi and
+    visibility-based block Jacobi on k x k city grids whose initial values carry
+    a sine-wave long-range error (problems of growing diameter). Reported per
+    solve: the linear solve time without the preconditioner setup (the
+    figure's quantity, also per camera), the setup time, and the whole step;
+    the summary fits time ~ n_cam^e per preconditioner."""
+    import numpy as np
+    import torch
     from scenes import make_scene
 
     dev = torch.device("cuda:0")
@@ -429,44 +481,44 @@ def run_scaling(ks, steps, warmup):
         sc = make_scene(f"sine{k}")
         T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
         cams, pts, uv = T(sc.cams), T(sc.pts), T(sc.uv)
-        plan = bamg.Plan(sc.n_cam, sc.n_pt, T(sc.obs_cam, torch.int32), T(sc.obs_pt, torch.int32),
-                         bamg.Options(precond="mg"))
-        for pc in ("mg", "bj", "cj"):
-            o = bamg.Options(precond=pc, rtol=1e-6, max_iter=50000)
+        plans = scaling_plans(sc, dev)
+        for pc in SCALING_PRECONDS:
+            plan = plans[pc]
+            o = scaling_opts(pc, rtol=1e-6, max_iter=50000, lam=lam)
             for _ in range(warmup):
                 plan.lm_step(cams, pts, uv, opts=o)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            solve = setup = 0.0
             e0.record()
             for _ in range(steps):
                 _, _, st = plan.lm_step(cams, pts, uv, opts=o)
+                solve += st.t_solve_ms
+                setup += st.t_setup_ms
             e1.record()
             torch.cuda.synchronize()
-            row = {"k": k, "n_cam": sc.n_cam, "n_pt": sc.n_pt, "n_obs": sc.n_obs, "precond": pc,
-                   "ms_per_solve": e0.elapsed_time(e1) / steps, "pcg_iters": st.iters, "levels": st.nodes,
-                   "rel_res": st.rel_res}
+            row = {"k": k, "n_cam": sc.n_cam, "n_pt": sc.n_pt, "n_obs": sc.n_obs, "precond": pc, "lambda": lam,
+                   "ms_per_solve": e0.elapsed_time(e1) / steps, "solve_ms": solve / steps,
+                   "setup_ms": setup / steps, "solve_us_per_cam": 1e3 * solve / steps / sc.n_cam,
+                   "pcg_iters": st.iters, "levels": st.nodes, "rel_res": st.rel_res}
             rows.append(row)
-            log(f"[scaling] k={k} n_cam={sc.n_cam} {pc}: {row['ms_per_solve']:.2f} ms, {st.iters} iterations")
+            log(f"[scaling] k={k} n_cam={sc.n_cam} {pc}: solve {row['solve_ms']:.2f} ms "
+                f"({row['solve_us_per_cam']:.2f} us/camera), setup {row['setup_ms']:.2f} ms, "
+                f"{st.iters} iterations")
             print(json.dumps(row), flush=True)
-        del plan
-    fits = {}
-    for pc in ("mg", "bj", "cj"):
-        r = [x for x in rows if x["precond"] == pc]
-        if len(r) >= 2:
-            n = np.log([x["n_cam"] for x in r])
-            fits[pc] = {"time_exponent": float(np.polyfit(n, np.log([x["ms_per_solve"] for x in r]), 1)[0]),
-                        "iteration_exponent": float(np.polyfit(n, np.log([x["pcg_iters"] for x in r]), 1)[0])}
+        del plans
     print(json.dumps({"metric": "scaling: LM linear solve to rtol 1e-6 vs n_cam, sine-wave long-range error",
-                      "fits": fits}), flush=True)
+                      "lambda": lam, "fits": fit_exponents(rows, ("solve_ms", "setup_ms", "ms_per_solve", "pcg_iters"))}),
+          flush=True)
 
 
-def run_scaling_lm(ks, lm_iters):
-    """The paper's scaling protocol: for each k x k sine-noise city grid, LM runs
-    (Nash-Sofer rule, constant tau = 0.01, FP64) with multigrid, point block
-    Jacobi and visibility-based block Jacobi; every run is timed up to the
-    first iteration at which its cost reaches the highest final cost of the
-    three (so that all end at the same objective), summing the iterations'
-    times (linear solve, setup, cost evaluations)."""
+def run_scaling_lm(ks, lm_iters, loss):
+    """Fig. 7's protocol over the grids of Fig. 6: for each k x k sine-noise
+    city grid, LM runs (Nash-Sofer rule, constant tau = 0.01, FP64, the given
+    loss) with every preconditioner; each run is timed up to the first
+    iteration at which its cost reaches the highest final cost of all runs (so
+    that all end at the same objective), summing the iterations' times (linear
+    solve, setup, cost evaluations)."""
     import numpy as np
     import torch
     import paper_2007_01941_amd as bamg
@@ -478,13 +530,12 @@ def run_scaling_lm(ks, lm_iters):
         sc = make_scene(f"sine{k}")
         T = lambda a, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
         cams, pts, uv = T(sc.cams), T(sc.pts), T(sc.uv)
-        plan = bamg.Plan(sc.n_cam, sc.n_pt, T(sc.obs_cam, torch.int32), T(sc.obs_pt, torch.int32),
-                         bamg.Options(precond="mg"))
+        plans = scaling_plans(sc, dev)
         runs = {}
-        for pc in ("mg", "bj", "cj"):
-            o = bamg.Options(precond=pc, rtol=1e-10, max_iter=5000, stop_rule="nash_sofer", forcing=0.01)
-            out = plan.lm_solve(cams.clone(), pts.clone(), uv, opts=o, lm_opts=bamg.LMOptions(max_iters=lm_iters))
-            runs[pc] = out
+        for pc in SCALING_PRECONDS:
+            o = scaling_opts(pc, rtol=1e-10, max_iter=5000, stop_rule="nash_sofer", forcing=0.01, loss=loss)
+            runs[pc] = plans[pc].lm_solve(cams.clone(), pts.clone(), uv, opts=o,
+                                          lm_opts=bamg.LMOptions(max_iters=lm_iters))
         target = max(r.cost for r in runs.values())
         for pc, out in runs.items():
             t, cost, n_it, pcg = 0.0, out.cost0, 0, 0
@@ -496,23 +547,18 @@ def run_scaling_lm(ks, lm_iters):
                     cost = h.cost_candidate
                 if cost <= target * (1 + 1e-12):
                     break
-            row = {"k": k, "n_cam": sc.n_cam, "n_obs": sc.n_obs, "precond": pc, "ms_to_target": t,
-                   "lm_iters_to_target": n_it, "pcg_iters_to_target": pcg, "target_cost": target,
-                   "cost0": out.cost0, "final_cost": out.cost, "lm_iters": out.iters}
+            row = {"k": k, "n_cam": sc.n_cam, "n_obs": sc.n_obs, "precond": pc, "loss": loss,
+                   "ms_to_target": t, "lm_iters_to_target": n_it, "pcg_iters_to_target": pcg,
+                   "target_cost": target, "cost0": out.cost0, "final_cost": out.cost, "lm_iters": out.iters,
+                   "costs": [h.cost_candidate if h.accepted else None for h in out.history]}
             rows.append(row)
             log(f"[scaling-lm] k={k} n_cam={sc.n_cam} {pc}: {t:.1f} ms to cost {target:.6e} "
-                f"({n_it} LM iterations, {pcg} PCG)")
+                f"({n_it} LM iterations, {pcg} PCG; final cost {out.cost:.6e})")
             print(json.dumps(row), flush=True)
-        del plan
-    fits = {}
-    for pc in ("mg", "bj", "cj"):
-        r = [x for x in rows if x["precond"] == pc]
-        if len(r) >= 2:
-            n = np.log([x["n_cam"] for x in r])
-            fits[pc] = {"time_exponent": float(np.polyfit(n, np.log([x["ms_to_target"] for x in r]), 1)[0]),
-                        "pcg_exponent": float(np.polyfit(n, np.log([x["pcg_iters_to_target"] for x in r]), 1)[0])}
+        del plans
     print(json.dumps({"metric": "scaling: LM time to a common cost vs n_cam (tau 0.01, sine-wave long-range error)",
-                      "fits": fits}), flush=True)
+                      "loss": loss, "fits": fit_exponents(rows, ("ms_to_target", "pcg_iters_to_target"))}),
+          flush=True)
 
 
 def subsample_points(sc, every):
