@@ -149,6 +149,9 @@ typedef struct {            /* (host) */
                                exceeded its smallest eigenvalues) and the solve was finished by
                                FP64 PCG on the FP64 residual */
   int32_t reserved_stats;
+  int32_t agg_min[16];      /* aggregate sizes of every level that has aggregates (Section 3.2 reports */
+  int32_t agg_max[16];      /* 3 to 8, mean a little over 3, on its street scenes): smallest, largest */
+  double agg_mean[16];      /* and mean number of nodes per aggregate; 0 on the coarsest level */
 } ba_stats;
 
 /* Allocation callbacks of a plan: alloc returns `bytes` bytes of device memory

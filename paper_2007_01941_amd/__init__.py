@@ -34,12 +34,15 @@ class Stats:
     t_solve_ms: float
     converged: bool = True
     fallback_fp64: bool = False
+    agg_sizes: list = dataclasses.field(default_factory=list)   # (min, mean, max) per aggregated level
 
 
 def _stats(st: _lib._Stats, status) -> Stats:
-    return Stats(st.iters, st.refine_steps, st.levels, list(st.nodes[: max(st.levels, 0)]),
+    nl = max(st.levels, 0)
+    return Stats(st.iters, st.refine_steps, st.levels, list(st.nodes[:nl]),
                  st.rel_res, st.t_jacobian_ms, st.t_setup_ms, st.t_solve_ms,
-                 status == _lib.BA_OK, bool(st.fallback_fp64))
+                 status == _lib.BA_OK, bool(st.fallback_fp64),
+                 [(st.agg_min[l], st.agg_mean[l], st.agg_max[l]) for l in range(max(nl - 1, 0))])
 
 
 @dataclasses.dataclass

@@ -61,7 +61,9 @@ class _Stats(ctypes.Structure):
                 ("levels", ctypes.c_int32), ("nodes", ctypes.c_int32 * 16),
                 ("rel_res", ctypes.c_double), ("t_jacobian_ms", ctypes.c_double),
                 ("t_setup_ms", ctypes.c_double), ("t_solve_ms", ctypes.c_double),
-                ("fallback_fp64", ctypes.c_int32), ("reserved_stats", ctypes.c_int32)]
+                ("fallback_fp64", ctypes.c_int32), ("reserved_stats", ctypes.c_int32),
+                ("agg_min", ctypes.c_int32 * 16), ("agg_max", ctypes.c_int32 * 16),
+                ("agg_mean", ctypes.c_double * 16)]
 
 
 class _LMOpts(ctypes.Structure):

@@ -347,6 +347,7 @@ ba_status ba_step_prepare(ba_plan* P, const ba_opts* o, const double* cams, cons
   BA_API_BEGIN
   BA_CHECK(P && cams && pts && uv, BA_ERR_ARG, "null argument");
   validate_opts(o);
+  if (st) std::memset(st, 0, sizeof(*st));
   AllocScope scope(&P->alloc);
   bind_ws(P, ws_key(o, 0), ws, ws_bytes, (hipStream_t)stream);
   prepare(P, o, cams, pts, uv, D, st, (hipStream_t)stream);

@@ -531,7 +531,12 @@ static void build_hierarchy(ba_plan* P, const ba_opts* o, hipStream_t s) {
       for (int i = 0; i < L.n; ++i) { apos[i] = cur[L.h_agg[i]] - aptr[L.h_agg[i]]; amem[cur[L.h_agg[i]]++] = i; }
     }
     L.max_agg = 0;
-    for (int a = 0; a < L.n_agg; ++a) L.max_agg = std::max(L.max_agg, aptr[a + 1] - aptr[a]);
+    L.min_agg = L.n;
+    for (int a = 0; a < L.n_agg; ++a) {
+      L.max_agg = std::max(L.max_agg, aptr[a + 1] - aptr[a]);
+      L.min_agg = std::min(L.min_agg, aptr[a + 1] - aptr[a]);
+    }
+    L.mean_agg = (double)L.n / L.n_agg;
     L.agg_ptr.upload(aptr, s);
     L.agg_mem.upload(amem, s);
     L.agg_pos.upload(apos, s);

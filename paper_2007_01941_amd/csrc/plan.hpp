@@ -39,6 +39,8 @@ struct Level {
   DBuf<int32_t> agg_pos;     // position of node i inside its aggregate
   DBuf<int32_t> slot_of;     // node i's position in aggregate order: agg_ptr[agg[i]] + agg_pos[i]
   int max_agg = 0;           // largest aggregate
+  int min_agg = 0;           // smallest aggregate
+  double mean_agg = 0.0;     // nodes per aggregate
   // Galerkin map: coarse CSR entry e gathers fine entries gal_fine[gal_ptr[e] .. gal_ptr[e+1])
   DBuf<int32_t> gal_ptr;
   DBuf<int32_t> gal_fine;
@@ -180,6 +182,7 @@ struct ba_plan {
   uint32_t own_key = 0;           // what own_ws is laid out for
   const void* ws_base = nullptr;  // workspace the views point into
   uint32_t ws_key = 0;            // its layout
+  size_t ws_span = 0;             // bytes that layout spans
   bamg::Scratch* scratch = nullptr;
   // side stream of the multigrid setup (default priority), forked from and
   // joined back into the caller's stream with these events

@@ -195,11 +195,12 @@ static void bind_ws(ba_plan* P, uint32_t key, void* ws, size_t ws_bytes, hipStre
   char* base;
   uint32_t k;
   if (ws) {
-    // the same workspace, already laid out for these options and more
-    if (ws == P->ws_base && (P->ws_key & key) == key) return;
     BA_CHECK(((uintptr_t)ws & 255) == 0, BA_ERR_ARG, "the workspace is not aligned to 256 bytes");
     const size_t need = layout_ws(P, key, nullptr);
     BA_CHECK(ws_bytes >= need, BA_ERR_WORKSPACE, "workspace of %zu bytes; these options need %zu", ws_bytes, need);
+    // the same workspace, already laid out for these options and more, and
+    // still holding all of that layout
+    if (ws == P->ws_base && (P->ws_key & key) == key && ws_bytes >= P->ws_span) return;
     base = static_cast<char*>(ws);
     k = key;
   } else {
@@ -216,7 +217,7 @@ static void bind_ws(ba_plan* P, uint32_t key, void* ws, size_t ws_bytes, hipStre
   if (P->ws_base == base && P->ws_key == k) return;
   BA_HIP(hipStreamSynchronize(s));
   invalidate_step(P);
-  layout_ws(P, k, base);
+  P->ws_span = layout_ws(P, k, base);
   P->ws_base = base;
   P->ws_key = k;
   // the reduction counters in the scalar blocks start at zero
@@ -981,7 +982,14 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
     st->t_jacobian_ms = tjac;
     st->t_setup_ms = tset;
     st->levels = (int)P->levels.size();
-    for (size_t l = 0; l < P->levels.size() && l < 16; ++l) st->nodes[l] = P->levels[l].n;
+    for (size_t l = 0; l < P->levels.size() && l < 16; ++l) {
+      const Level& L = P->levels[l];
+      st->nodes[l] = L.n;
+      const bool has = l + 1 < P->levels.size();
+      st->agg_min[l] = has ? L.min_agg : 0;
+      st->agg_max[l] = has ? L.max_agg : 0;
+      st->agg_mean[l] = has ? L.mean_agg : 0.0;
+    }
   }
 }
 

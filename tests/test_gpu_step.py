@@ -361,6 +361,25 @@ def test_prolongator_and_coarse_operator_match_oracle():
     assert n_cmp >= len(full)
 
 
+def test_aggregate_size_statistics():
+    """The step's statistics report each aggregated level's smallest, mean and
+    largest aggregate (Section 3.2 quotes these sizes), equal to the sizes of
+    the oracle's aggregates."""
+    sc = scene("city200")
+    plan, opts = plan_for(sc, precond="mg", coarse_max_nodes=16)
+    _, _, st = plan.lm_step(*inputs(sc))
+    nrm = ostep.normal_for(sc.cams, sc.pts, sc.obs_cam, sc.obs_pt, sc.uv)
+    lev = ostep.hierarchy_for(nrm, sc.cams, sc.obs_cam, sc.obs_pt, omg.MGOptions(coarse_max_nodes=16))
+    ref = []
+    for L in lev[:-1]:
+        sizes = np.bincount(L.agg, minlength=L.n_agg)
+        ref.append((int(sizes.min()), len(L.agg) / L.n_agg, int(sizes.max())))
+    print(f"[gpu] aggregate sizes (min, mean, max) per level: {st.agg_sizes}", flush=True)
+    assert len(st.agg_sizes) == len(ref)
+    for got, want in zip(st.agg_sizes, ref):
+        assert got[0] == want[0] and got[2] == want[2] and abs(got[1] - want[1]) <= 1e-12 * want[1]
+
+
 def test_exact_tie_aggregation_on_gpu():
     """The hand-worked exact tie (tests/golden: case exact_tie), built as a
     visibility graph of points each seen by two cameras: the GPU's integer
