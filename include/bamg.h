@@ -307,8 +307,8 @@ ba_status ba_mg_covisibility(const ba_plan* p, int32_t level, int64_t* nnz, int6
  *             the explicit S), only for n <= 16384;
  *   what = 1: tentative prolongator blocks P [nodes][bs][16] of `level`;
  *   what = 2: near-nullspace rows K [nodes][bs][16] of `level`;
- *   what = 3: inverse smoother blocks D^-1 [nodes][bs][bs];
- *   what = 4: lambda_max estimate of D^-1 S (1 value);
+ *   what = 3: inverse smoother blocks D^-1 [nodes][bs][bs] (not on the coarsest level);
+ *   what = 4: lambda_max estimate of D^-1 S (1 value; not on the coarsest level);
  *   what = 5: coarsest level only: inverse of its operator, dense [n][n];
  *   what = 6: plans built for BA_PROLONG_SMOOTHED: the smoothed prolongator of
  *             `level` as dense [nodes*bs][nodes(level+1)*16], only for

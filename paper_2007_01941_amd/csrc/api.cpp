@@ -311,6 +311,8 @@ void ba_plan_destroy(ba_plan* p) {
   for (hipEvent_t e : p->ev_lvl) if (e) (void)hipEventDestroy(e);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  for (hipEvent_t e : p->ev_t) if (e) (void)hipEventDestroy(e);
+  if (p->h_err) (void)hipHostFree(p->h_err);
   delete p->scratch;
   delete p->bwd;
   delete p->lm;
@@ -351,6 +353,8 @@ ba_status ba_step_prepare(ba_plan* P, const ba_opts* o, const double* cams, cons
   AllocScope scope(&P->alloc);
   bind_ws(P, ws_key(o, 0), ws, ws_bytes, (hipStream_t)stream);
   prepare(P, o, cams, pts, uv, D, st, (hipStream_t)stream);
+  check_errflag(P, (hipStream_t)stream, "normal blocks or preconditioner setup");
+  prepare_times(P, st);
   BA_API_END
 }
 
@@ -375,7 +379,9 @@ ba_status ba_lm_step(ba_plan* P, const ba_opts* o, const double* cams, const dou
   AllocScope scope(&P->alloc);
   bind_ws(P, ws_key(o, 0), ws, ws_bytes, s);
   prepare(P, o, cams, pts, uv, D, st, s);
-  return solve(P, o, delta_cam, delta_pt, st, s);
+  const ba_status r = solve(P, o, delta_cam, delta_pt, st, s);
+  prepare_times(P, st);
+  return r;
   BA_API_END
 }
 

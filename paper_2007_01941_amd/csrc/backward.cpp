@@ -34,6 +34,7 @@ static ba_status backward(ba_plan* P, const ba_opts* o, const double* cams, cons
   BA_LAUNCH_CHECK();
   const double t = ts.ms();
   if (st) st->t_solve_ms = t;
+  prepare_times(P, st);
   return status;
 }
 

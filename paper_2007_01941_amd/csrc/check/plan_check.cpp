@@ -241,7 +241,7 @@ int main(int argc, char** argv) {
           case 0: n = nv * nv; valid = nv <= 16384; break;
           case 1: case 2: n = nv * 16; valid = what == 2 || l + 1 < nl; break;
           case 3: n = (size_t)nodes[l] * bs * bs; valid = l + 1 < nl; break;
-          case 4: n = 1; break;
+          case 4: n = 1; valid = l + 1 < nl; break;
           case 5: n = nv * nv; valid = l + 1 == nl; break;
           case 6: n = nv * nc; valid = smooth && l + 1 < nl && nv <= 16384; break;
         }

@@ -7,7 +7,9 @@
 
 namespace bamg {
 
-// Epilogues of the block-row product t = (S v)_i (one node i per workgroup):
+// Epilogues of the block-row product t = (S v)_i (one node i per workgroup).
+// The Chebyshev coefficient c2 is given for lambda_max = 1 and scaled by
+// *ilmax = 1 / lambda_max, which stays on the device:
 enum RowEpilogue {
   EP_STORE = 0,     // out_i = t
   EP_RESID = 1,     // r_i -= t;  part_{slot(i)} = P_i^T r_i (restriction partial)
@@ -16,13 +18,16 @@ enum RowEpilogue {
 };
 
 // Block-sparse product with the explicit level operator (BS x BS blocks, CSR
-// of blocks), one workgroup of 256 threads per block row: thread (part, comp)
-// accumulates component comp over the row's blocks part, part + PARTS, ...
-// (PARTS = 256 / BS; consecutive threads read consecutive rows of a block),
-// the parts are summed in LDS, and the row's Chebyshev update (EP_CHEB,
-// EP_CHEB_POST) or residual update (EP_RESID) is applied in place: the
-// workgroup owns all of node i. The product's input v is never written here
-// (d_in, d_out and x_in, x_out are different buffers where v is one of them).
+// of blocks), one workgroup of 256 threads per block row. A row's blocks are
+// contiguous, and the workgroup streams them NB = 256 / BS^2 blocks at a time
+// (3 of 9 x 9, 1 of 16 x 16): thread t keeps entry (r, c) of block t / BS^2
+// of each group, so that consecutive threads read consecutive scalars, and
+// accumulates S_rc v_c; the sums over c (and the NB blocks) give the row's
+// component r (16 x 16: a 16-lane butterfly; 9 x 9: 27 partials in LDS). The
+// row's Chebyshev update (EP_CHEB, EP_CHEB_POST) or residual update (EP_RESID)
+// is then applied in place: the workgroup owns all of node i. The product's
+// input v is never written here (d_in, d_out and x_in, x_out are different
+// buffers where v is one of them).
 template <int BS, class T, int EP>
 __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restrict__ rowptr,
                                                  const int32_t* __restrict__ col, const T* __restrict__ S,
@@ -31,14 +36,16 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
                                                  T* __restrict__ r, const T* __restrict__ d_in,
                                                  T* __restrict__ d_out, const T* __restrict__ x_in,
                                                  T* __restrict__ x_out, T c1, T c2,
+                                                 const double* __restrict__ ilmax,
                                                  const T* __restrict__ P, const int32_t* __restrict__ slot_of,
                                                  T* __restrict__ rpart, const int* done) {
   if (done && *done) return;
-  constexpr int PARTS = 256 / BS;
+  constexpr int BB = BS * BS;
+  constexpr int NB = 256 / BB;
   __shared__ T red[256];
   __shared__ T rs[BS];
   const int row = blockIdx.x;
-  const int pidx = threadIdx.x / BS, comp = threadIdx.x % BS;
+  const int comp = threadIdx.x % BS;
   const bool own = threadIdx.x < BS;
   const size_t k = (size_t)row * BS + comp;
   // the epilogue's operands are loaded first, so that their latency overlaps
@@ -51,23 +58,58 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
   }
   int slot = 0;
   if (EP == EP_RESID && rpart && threadIdx.x < NS) slot = slot_of[row];
-  T acc = 0;
-  if (pidx < PARTS) {
-    const int e1 = rowptr[row + 1];
-#pragma unroll 2
-    for (int e = rowptr[row] + pidx; e < e1; e += PARTS) {
-      const T* blk = S + (size_t)e * BS * BS + comp * BS;
-      const T* xv = v + (size_t)col[e] * BS;
+  // and so are the epilogue's matrix rows: D_i^-1 row comp (Chebyshev) or
+  // column threadIdx.x of P_i (restriction)
+  T mrow[BS];
+  if ((EP == EP_CHEB || EP == EP_CHEB_POST) && own) {
 #pragma unroll
-      for (int k2 = 0; k2 < BS; ++k2) acc += blk[k2] * xv[k2];
+    for (int k2 = 0; k2 < BS; ++k2) mrow[k2] = Dinv[(size_t)row * BS * BS + comp * BS + k2];
+  }
+  if (EP == EP_RESID && rpart && threadIdx.x < NS) {
+#pragma unroll
+    for (int k2 = 0; k2 < BS; ++k2) mrow[k2] = P[(size_t)row * BS * NS + k2 * NS + threadIdx.x];
+  }
+  T acc = 0;
+  const int blk = threadIdx.x / BB, rc = threadIdx.x % BB;
+  if (blk < NB) {
+    const int e1 = rowptr[row + 1];
+    const int c = rc % BS;
+    // batches of U blocks per thread: the U column indices, then the U operator
+    // entries and v entries, are all in flight together
+    constexpr int U = 8;
+    for (int e = rowptr[row] + blk; e < e1; e += NB * U) {
+      int cj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) cj[u] = e + u * NB < e1 ? col[e + u * NB] : -1;
+      T sv[U], vv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        sv[u] = cj[u] >= 0 ? S[(size_t)(e + u * NB) * BB + rc] : T(0);
+        vv[u] = cj[u] >= 0 ? v[(size_t)cj[u] * BS + c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc += sv[u] * vv[u];
     }
   }
-  red[threadIdx.x] = acc;
+  if (BS == 16) {
+    // lanes 16 r .. 16 r + 15 hold row r's terms
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 15) == 0) red[threadIdx.x >> 4] = acc;
+  } else {
+    red[threadIdx.x] = acc;
+  }
   __syncthreads();
   if (own) {
     T tsum = 0;
-#pragma unroll 4
-    for (int p = 0; p < PARTS; ++p) tsum += red[p * BS + comp];
+    if (BS == 16) {
+      tsum = red[comp];
+    } else {
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int c = 0; c < BS; ++c) tsum += red[q * BB + comp * BS + c];
+    }
     if (EP == EP_STORE) {
       out[k] = tsum;
     } else {
@@ -80,20 +122,19 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
   __syncthreads();
   if (EP == EP_RESID) {
     if (rpart && threadIdx.x < NS) {
-      const T* Pi = P + (size_t)row * BS * NS + threadIdx.x;
       T sacc = 0;
 #pragma unroll
-      for (int k2 = 0; k2 < BS; ++k2) sacc += Pi[k2 * NS] * rs[k2];
+      for (int k2 = 0; k2 < BS; ++k2) sacc += mrow[k2] * rs[k2];
       rpart[(size_t)slot * NS + threadIdx.x] = sacc;
     }
     return;
   }
   if (!own) return;
-  const T* m = Dinv + (size_t)row * BS * BS + comp * BS;
   T z = 0;
 #pragma unroll
-  for (int k2 = 0; k2 < BS; ++k2) z += m[k2] * rs[k2];
-  const T dv = EP == EP_CHEB ? c1 * d0 + c2 * z : c2 * z;
+  for (int k2 = 0; k2 < BS; ++k2) z += mrow[k2] * rs[k2];
+  const T c2s = c2 * (T)*ilmax;
+  const T dv = EP == EP_CHEB ? c1 * d0 + c2s * z : c2s * z;
   d_out[k] = dv;
   x_out[k] = x0 + dv;
 }
@@ -115,7 +156,8 @@ __global__ __launch_bounds__(256) void k_blockdiag(int n, const T* __restrict__ 
   z[g] = s;
 }
 
-// First Chebyshev step. mode 0 (pre-smoothing from x = 0, r = b):
+// First Chebyshev step (inv_theta for lambda_max = 1, scaled by *ilmax).
+// mode 0 (pre-smoothing from x = 0, r = b):
 //   d = D^-1 b / theta; x = d; r = b.
 // mode 1 (post-smoothing from x, t = S x): r = b - t; d = D^-1 r / theta; x += d.
 // mode 2: as mode 0, with b first formed (and stored) from the finer level's
@@ -125,6 +167,7 @@ __global__ __launch_bounds__(256) void k_cheb_first(int n, int mode, const T* __
                                                     T* __restrict__ b, const T* __restrict__ t,
                                                     T* __restrict__ r, T* __restrict__ d,
                                                     T* __restrict__ x, T inv_theta,
+                                                    const double* __restrict__ ilmax,
                                                     const int32_t* __restrict__ agg_ptr,
                                                     const T* __restrict__ part, const int* done) {
   if (done && *done) return;
@@ -153,16 +196,18 @@ __global__ __launch_bounds__(256) void k_cheb_first(int n, int mode, const T* __
 #pragma unroll
   for (int k2 = 0; k2 < BS; ++k2) s += m[k2] * rs[ln * BS + k2];
   const size_t k = (size_t)i * BS + a;
-  const T dv = s * inv_theta;
+  const T dv = s * (inv_theta * (T)*ilmax);
   d[k] = dv;
   x[k] = mode == 1 ? x[k] + dv : dv;
 }
 
-// Later Chebyshev steps: r -= t (t = S d); d = c1 d + c2 D^-1 r; x += d.
+// Later Chebyshev steps: r -= t (t = S d); d = c1 d + c2 D^-1 r; x += d (c2 for
+// lambda_max = 1, scaled by *ilmax).
 template <int BS, class T>
 __global__ __launch_bounds__(256) void k_cheb_next(int n, const T* __restrict__ Dinv, const T* __restrict__ t,
                                                    T* __restrict__ r, T* __restrict__ d, T* __restrict__ x,
-                                                   T c1, T c2, const int* done) {
+                                                   T c1, T c2, const double* __restrict__ ilmax,
+                                                   const int* done) {
   if (done && *done) return;
   __shared__ T rs[256];
   const int nodes_per_block = 256 / BS;
@@ -182,7 +227,7 @@ __global__ __launch_bounds__(256) void k_cheb_next(int n, const T* __restrict__ 
 #pragma unroll
   for (int k2 = 0; k2 < BS; ++k2) s += m[k2] * rs[ln * BS + k2];
   const size_t k = (size_t)i * BS + a;
-  const T dv = c1 * d[k] + c2 * s;
+  const T dv = c1 * d[k] + (c2 * (T)*ilmax) * s;
   d[k] = dv;
   x[k] += dv;
 }
@@ -286,8 +331,10 @@ __global__ void k_lanczos_start(int n, int level, double* __restrict__ v) {
 
 // ---- generalized Lanczos on S x = lambda D x with device-resident scalars
 // Scalar slots: alpha[j] = s[j], beta[j] = s[32 + j], s[64] = norm^2,
-// s[65] = b2, s[66] = completed steps, s[67] = stop flag.
-constexpr int LZ_ALPHA = 0, LZ_BETA = 32, LZ_NRM = 64, LZ_B2 = 65, LZ_COUNT = 66, LZ_STOP = 67;
+// s[65] = b2, s[66] = completed steps, s[67] = stop flag, s[68] = lambda_max,
+// s[69] = 1 / lambda_max.
+constexpr int LZ_ALPHA = 0, LZ_BETA = 32, LZ_NRM = 64, LZ_B2 = 65, LZ_COUNT = 66, LZ_STOP = 67, LZ_LMAX = 68,
+              LZ_ILMAX = 69, LZ_SIZE = 72;
 
 // v <- v / sqrt(s[64]), u <- u / sqrt(s[64])
 __global__ void k_lanczos_normalize(int n, double* __restrict__ v, double* __restrict__ u,
@@ -324,6 +371,47 @@ __global__ void k_lanczos_advance(int n, int j, double* __restrict__ v, double* 
   up[i] = u[i];
   v[i] = w[i] * ib;
   u[i] = dw[i] * ib;
+}
+
+// lambda_max of the Lanczos tridiagonal matrix (alpha on the diagonal, beta
+// beside it; the steps completed before a breakdown, else `steps`): its
+// largest eigenvalue by bisection on the Sturm sequence count, one thread.
+// A start vector of non-positive D-norm (a smoother block that is not
+// positive definite) sets ERRF_NOT_SPD.
+__global__ void k_lanczos_finish(int steps, double* __restrict__ lz, uint32_t* err) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double nrm = lz[LZ_NRM];
+  if (!(nrm > 0.0) || !isfinite(nrm)) {
+    atomicOr(err, ERRF_NOT_SPD);
+    lz[LZ_LMAX] = 1.0;
+    lz[LZ_ILMAX] = 1.0;
+    return;
+  }
+  const int n = lz[LZ_STOP] != 0.0 ? (int)lz[LZ_COUNT] : steps;
+  const double* a = lz + LZ_ALPHA;
+  const double* b = lz + LZ_BETA;
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < n ? fabs(b[i]) : 0.0);
+    lo = fmin(lo, a[i] - r);
+    hi = fmax(hi, a[i] + r);
+  }
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    int below = 0;   // eigenvalues < mid
+    double d = 1.0;
+    for (int i = 0; i < n; ++i) {
+      d = a[i] - mid - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300;
+      if (d < 0.0) ++below;
+    }
+    if (below < n) lo = mid; else hi = mid;
+  }
+  const double lmax = 0.5 * (lo + hi);
+  lz[LZ_LMAX] = lmax;
+  lz[LZ_ILMAX] = 1.0 / lmax;
+  if (!(lmax > 0.0) || !isfinite(lmax)) atomicOr(err, ERRF_NOT_SPD);
 }
 
 // Bookkeeping after step j (one thread): record alpha_j as done, and beta_j or the stop.

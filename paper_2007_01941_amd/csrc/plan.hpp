@@ -67,7 +67,7 @@ struct Level {
   DBuf<float> P32;
   DBuf<double> Dinv;         // n * bs * bs inverse diagonal blocks
   DBuf<float> Dinv32;
-  double lmax = 0.0;         // lambda_max estimate of D^-1 S (generalized Lanczos)
+  double lmax = 0.0;         // host copy of lambda_max of D^-1 S (smoothed-prolongator setup only)
   bool explicit_op = true;   // level 0: use explicit S for smoothing (else implicit)
   // coarsest level: dense inverse of the operator (FP64), padded to nd x nd
   int nd = 0;
@@ -75,7 +75,7 @@ struct Level {
   DBuf<double> inv;          // inverse nd x nd
   // V-cycle work vectors, FP64 and FP32 (n * bs each)
   DBuf<double> lz_u, lz_v, lz_up, lz_vp, lz_av, lz_dav, lz_w, lz_dw;   // Lanczos vectors
-  DBuf<double> lz_s;         // Lanczos scalars: alpha[32], beta[32], norm, b2, count, stop
+  DBuf<double> lz_s;         // Lanczos scalars: alpha[32], beta[32], norm, b2, count, stop, lambda_max, 1/lambda_max
   DBuf<double> gj_scale;     // coarsest level: equilibration scales
   DBuf<double> gj_piv;       // coarsest level: inverse of the current 64 x 64 pivot block
   DBuf<double> vb, vx, vr, vd, vt, vpart;
@@ -183,6 +183,8 @@ struct ba_plan {
   const void* ws_base = nullptr;  // workspace the views point into
   uint32_t ws_key = 0;            // its layout
   size_t ws_span = 0;             // bytes that layout spans
+  hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};   // step phases: start, blocks done, setup done
+  uint32_t* h_err = nullptr;      // pinned copy of the error flags
   bamg::Scratch* scratch = nullptr;
   // side stream of the multigrid setup (default priority), forked from and
   // joined back into the caller's stream with these events

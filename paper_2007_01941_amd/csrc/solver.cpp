@@ -130,7 +130,7 @@ static size_t layout_ws(ba_plan* P, uint32_t key, char* base) {
       c.take(L.vx2, nv);
       for (DBuf<double>* v : {&L.lz_u, &L.lz_v, &L.lz_up, &L.lz_vp, &L.lz_av, &L.lz_dav, &L.lz_w, &L.lz_dw})
         c.take(*v, nv);
-      c.take(L.lz_s, 68);
+      c.take(L.lz_s, LZ_SIZE);
       if (P->sa) {
         c.take(L.Ps, (size_t)L.nnz_ps * L.bs * NS);
         c.take(L.Tsp, (size_t)L.nnz_t * L.bs * NS);
@@ -235,6 +235,8 @@ static void create_runtime(ba_plan* P) {
   P->lm = new LmWork();
   BA_HIP(hipHostMalloc((void**)&P->lm->h_scal, sizeof(LmScal), hipHostMallocDefault));
   BA_HIP(hipHostMalloc((void**)&P->lm->h_dots, 4 * sizeof(double), hipHostMallocDefault));
+  BA_HIP(hipHostMalloc((void**)&P->h_err, sizeof(uint32_t), hipHostMallocDefault));
+  for (hipEvent_t& e : P->ev_t) BA_HIP(hipEventCreate(&e));
   BA_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
   BA_HIP(hipStreamCreateWithFlags(&P->side2, hipStreamNonBlocking));
   BA_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
@@ -337,24 +339,25 @@ static void op_apply(ba_plan* P, int l, const T* x, T* y, const int* done, hipSt
   if (L.bs == 9)
     hipLaunchKernelGGL((k_bsr_row<9, T, EP_STORE>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p, lvS<T>(L),
                        x, y, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr, (T*)nullptr,
-                       (const T*)nullptr, (T*)nullptr, T(0), T(0), (const T*)nullptr, (const int32_t*)nullptr,
-                       (T*)nullptr, done);
+                       (const T*)nullptr, (T*)nullptr, T(0), T(0), (const double*)nullptr, (const T*)nullptr,
+                       (const int32_t*)nullptr, (T*)nullptr, done);
   else
     hipLaunchKernelGGL((k_bsr_row<16, T, EP_STORE>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p,
                        lvS<T>(L), x, y, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr,
-                       (T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), (const T*)nullptr,
-                       (const int32_t*)nullptr, (T*)nullptr, done);
+                       (T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), (const double*)nullptr,
+                       (const T*)nullptr, (const int32_t*)nullptr, (T*)nullptr, done);
 }
 
 // Block-row product with the explicit operator of level l and a fused epilogue
-// (see k_bsr_row): v is the product's input.
+// (see k_bsr_row): v is the product's input; c2 is for lambda_max = 1 (the
+// kernel scales it by the level's 1 / lambda_max on the device).
 template <int BS, class T, int EP>
 static void row_op(ba_plan* P, int l, const T* v, const T* b, T* r, const T* d_in, T* d_out, const T* x_in,
                    T* x_out, double c1, double c2, T* part, const int* done, hipStream_t s) {
   Level& L = P->levels[l];
   hipLaunchKernelGGL((k_bsr_row<BS, T, EP>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p, lvS<T>(L), v,
                      (T*)nullptr, lvDinv<T>(P, l), b, r, d_in, d_out, x_in, x_out, (T)c1, (T)c2,
-                     part ? lvP<T>(L) : (const T*)nullptr, part ? L.slot_of.p : (const int32_t*)nullptr, part,
+                     (const double*)(L.lz_s.p + LZ_ILMAX), part ? lvP<T>(L) : (const T*)nullptr, part ? L.slot_of.p : (const int32_t*)nullptr, part,
                      done);
 }
 
@@ -468,16 +471,18 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, 
   T* dB = LvVec<T>::d2(L);
   T* x2 = LvVec<T>::x2(L);
   const T* Dinv = lvDinv<T>(P, l);
-  const double lmax = L.lmax;
-  const double theta = 0.5 * (o->cheb_hi + o->cheb_lo) * lmax;
-  const double delta = 0.5 * (o->cheb_hi - o->cheb_lo) * lmax;
+  // Chebyshev coefficients for lambda_max = 1: the kernels scale the ones
+  // that depend on it by the level's 1 / lambda_max, read on the device
+  const double* il = L.lz_s.p + LZ_ILMAX;
+  const double theta = 0.5 * (o->cheb_hi + o->cheb_lo);
+  const double delta = 0.5 * (o->cheb_hi - o->cheb_lo);
   const double sigma1 = theta / delta;
   const int m = o->cheb_degree;
   const int nb = std::max(1, ceil_div(L.n, 256 / BS));
   // pre-smoothing from x = 0: r = b, d = D^-1 b / theta, x = d
   double rho = 1.0 / sigma1;
   hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, pend.part ? 2 : 0, Dinv, b,
-                     (const T*)nullptr, r, dA, x, (T)(1.0 / theta), pend.agg_ptr, pend.part, done);
+                     (const T*)nullptr, r, dA, x, (T)(1.0 / theta), il, pend.agg_ptr, pend.part, done);
   T* part = P->sa ? nullptr : LvVec<T>::part(L);
   for (int k = 0; k < m; ++k) {
     if (k == m - 1) {
@@ -536,22 +541,24 @@ static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pendin
   T* d = LvVec<T>::d(L);
   T* t = LvVec<T>::t(L);
   const T* Dinv = lvDinv<T>(P, l);
-  const double lmax = L.lmax;
-  const double theta = 0.5 * (o->cheb_hi + o->cheb_lo) * lmax;
-  const double delta = 0.5 * (o->cheb_hi - o->cheb_lo) * lmax;
+  // Chebyshev coefficients for lambda_max = 1: the kernels scale the ones
+  // that depend on it by the level's 1 / lambda_max, read on the device
+  const double* il = L.lz_s.p + LZ_ILMAX;
+  const double theta = 0.5 * (o->cheb_hi + o->cheb_lo);
+  const double delta = 0.5 * (o->cheb_hi - o->cheb_lo);
   const double sigma1 = theta / delta;
   const int m = o->cheb_degree;
   const int nb = std::max(1, ceil_div(L.n, 256 / BS));
   // pre-smoothing from x = 0
   double rho = 1.0 / sigma1;
   hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, 0, Dinv, b, (const T*)nullptr, r, d, x,
-                     (T)(1.0 / theta), (const int32_t*)nullptr, (const T*)nullptr, done);
+                     (T)(1.0 / theta), il, (const int32_t*)nullptr, (const T*)nullptr, done);
   for (int k = 0; k < m; ++k) {
     op_apply<T>(P, l, d, t, done, s);
     if (k == m - 1) break;
     const double rn = 1.0 / (2.0 * sigma1 - rho);
     hipLaunchKernelGGL((k_cheb_next<BS, T>), dim3(nb), dim3(256), 0, s, L.n, Dinv, (const T*)t, r, d, x,
-                       (T)(rn * rho), (T)(2.0 * rn / delta), done);
+                       (T)(rn * rho), (T)(2.0 * rn / delta), il, done);
     rho = rn;
   }
   // restriction of the pre-smoother's residual r - t
@@ -575,12 +582,12 @@ static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pendin
   op_apply<T>(P, l, x, t, done, s);
   rho = 1.0 / sigma1;
   hipLaunchKernelGGL((k_cheb_first<BS, T>), dim3(nb), dim3(256), 0, s, L.n, 1, Dinv, b, (const T*)t, r, d, x,
-                     (T)(1.0 / theta), (const int32_t*)nullptr, (const T*)nullptr, done);
+                     (T)(1.0 / theta), il, (const int32_t*)nullptr, (const T*)nullptr, done);
   for (int k = 0; k < m - 1; ++k) {
     op_apply<T>(P, l, d, t, done, s);
     const double rn = 1.0 / (2.0 * sigma1 - rho);
     hipLaunchKernelGGL((k_cheb_next<BS, T>), dim3(nb), dim3(256), 0, s, L.n, Dinv, (const T*)t, r, d, x,
-                       (T)(rn * rho), (T)(2.0 * rn / delta), done);
+                       (T)(rn * rho), (T)(2.0 * rn / delta), il, done);
     rho = rn;
   }
 }
@@ -648,44 +655,16 @@ static double plain_dot(ba_plan* P, int n, const double* a, const double* b, hip
   return v;
 }
 
-// Largest eigenvalue of a symmetric tridiagonal matrix by bisection on the
-// Sturm sequence count.
-static double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
-  const int n = (int)a.size();
-  double lo = 1e300, hi = -1e300;
-  for (int i = 0; i < n; ++i) {
-    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
-    lo = std::min(lo, a[i] - r);
-    hi = std::max(hi, a[i] + r);
-  }
-  auto count_below = [&](double x) {  // eigenvalues < x
-    int c = 0;
-    double d = 1.0;
-    for (int i = 0; i < n; ++i) {
-      d = a[i] - x - (i > 0 ? b[i - 1] * b[i - 1] / d : 0.0);
-      if (d == 0.0) d = -1e-300;
-      if (d < 0.0) ++c;
-    }
-    return c;
-  };
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (mid <= lo || mid >= hi) break;
-    if (count_below(mid) < n) lo = mid; else hi = mid;
-  }
-  return 0.5 * (lo + hi);
-}
-
 // lambda_max of D^-1 S on one level: `lanczos_steps` steps of generalized
-// Lanczos in the D inner product. The scalars stay on the device (L.lz_s);
-// lanczos_launch enqueues the process, lanczos_finish turns the scalars read
-// back to the host into the estimate.
+// Lanczos in the D inner product, then the largest eigenvalue of the
+// tridiagonal matrix (k_lanczos_finish). Everything stays on the device
+// (L.lz_s): the V-cycle's kernels read 1 / lambda_max from there.
 static void lanczos_launch(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
   Level& L = P->levels[l];
   const int n = L.n * L.bs;
   Scratch& W = *P->scratch;
   double* lz = L.lz_s.p;
-  BA_HIP(hipMemsetAsync(lz, 0, 68 * sizeof(double), s));
+  BA_HIP(hipMemsetAsync(lz, 0, LZ_SIZE * sizeof(double), s));
   BA_HIP(hipMemsetAsync(L.lz_up.p, 0, n * sizeof(double), s));
   BA_HIP(hipMemsetAsync(L.lz_vp.p, 0, n * sizeof(double), s));
   const int g = grid_of<double>(n);
@@ -715,15 +694,8 @@ static void lanczos_launch(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
     hipLaunchKernelGGL(k_lanczos_advance, dim3(g), dim3(256), 0, s, n, j, L.lz_v.p, L.lz_vp.p, L.lz_u.p, L.lz_up.p,
                        (const double*)L.lz_w.p, (const double*)L.lz_dw.p, (const double*)lz);
   }
+  hipLaunchKernelGGL(k_lanczos_finish, dim3(1), dim3(64), 0, s, steps, lz, P->errflag.p);
   BA_LAUNCH_CHECK();
-}
-
-static double lanczos_finish(const double* h, int steps) {
-  BA_CHECK(h[LZ_NRM] > 0.0 && std::isfinite(h[LZ_NRM]), BA_ERR_NOT_SPD, "smoother blocks are not positive definite");
-  // steps whose alpha is valid: all of them unless a breakdown stopped the process
-  const int na = h[LZ_STOP] != 0.0 ? (int)h[LZ_COUNT] : steps;
-  std::vector<double> alphas(h + LZ_ALPHA, h + LZ_ALPHA + na), betas(h + LZ_BETA, h + LZ_BETA + std::max(0, na - 1));
-  return tridiag_max_eig(alphas, betas);
 }
 
 // ---------------------------------------------------------------- multigrid setup
@@ -815,7 +787,7 @@ static void mg_setup_sa(ba_plan* P, const ba_opts* o, const double* cams, hipStr
                      L0.K.p);
   assemble_s0(P, s);
   L0.explicit_op = level0_explicit(P, o, 8);
-  std::vector<double> h(68);
+  std::vector<double> h(1);
   for (int l = 0; l + 1 < nl; ++l) {
     Level& F = P->levels[l];
     Level& C = P->levels[l + 1];
@@ -824,9 +796,9 @@ static void mg_setup_sa(ba_plan* P, const ba_opts* o, const double* cams, hipStr
     hipLaunchKernelGGL(k_qr_aggregates, dim3(F.n_agg), dim3(64), lds, s, F.bs, F.agg_ptr.p, F.agg_mem.p, F.K.p,
                        F.P.p, C.K.p);
     lanczos_launch(P, o, l, s);
-    BA_HIP(hipMemcpyAsync(h.data(), F.lz_s.p, 68 * sizeof(double), hipMemcpyDeviceToHost, s));
-    check_errflag(P, s, "multigrid setup (QR, smoother blocks)");
-    F.lmax = lanczos_finish(h.data(), o->lanczos_steps);
+    BA_HIP(hipMemcpyAsync(h.data(), F.lz_s.p + LZ_LMAX, sizeof(double), hipMemcpyDeviceToHost, s));
+    check_errflag(P, s, "multigrid setup (QR, smoother blocks, lambda_max)");
+    F.lmax = h[0];
     const double c = o->smooth_omega / F.lmax;
     const double* Dinv = lvDinv<double>(P, l);
     if (F.bs == 9) {
@@ -925,13 +897,8 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   BA_LAUNCH_CHECK();
   P->inspectable_mg = true;
   BA_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
-  // one readback: Lanczos scalars of every level and the error flags
-  std::vector<double> h((size_t)std::max(1, nl - 1) * 68);
-  for (int l = 0; l + 1 < nl; ++l)
-    BA_HIP(hipMemcpyAsync(h.data() + (size_t)l * 68, P->levels[l].lz_s.p, 68 * sizeof(double),
-                          hipMemcpyDeviceToHost, s));
-  check_errflag(P, s, "multigrid setup (QR, Galerkin, smoother blocks, coarse inverse)");
-  for (int l = 0; l + 1 < nl; ++l) P->levels[l].lmax = lanczos_finish(h.data() + (size_t)l * 68, o->lanczos_steps);
+  // no readback: lambda_max stays on the device, and the error flags are
+  // checked once the solve reads its scalars back
   if (mixed) {
     // FP32 copies of level 0 (the coarse levels of the FP32 V-cycle run in FP64)
     convert((size_t)L0.nnz * L0.bs * L0.bs, L0.S.p, L0.S32.p, s);
@@ -954,7 +921,7 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
   P->det = o->deterministic != 0;
   P->robust = o->loss != BA_LOSS_SQUARED;
   double* wsq = P->robust ? P->wsq.p : nullptr;
-  Timer tj(s);
+  BA_HIP(hipEventRecord(P->ev_t[0], s));
   hipLaunchKernelGGL(k_campre, dim3(grid_of<double>(P->n_cam)), dim3(256), 0, s, P->n_cam, cams, P->campre.p,
                      P->errflag.p);
   hipLaunchKernelGGL(k_jacobian_tiles, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
@@ -967,20 +934,19 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
                      mixed ? P->A32.p : nullptr, P->Dc.p, P->b.p, P->Scc.p, P->Sinv.p,
                      mixed ? P->Sinv32.p : nullptr, P->n_cam, wsq, P->errflag.p);
   BA_LAUNCH_CHECK();
-  check_errflag(P, s, "normal blocks");
-  const double tjac = tj.ms();
+  BA_HIP(hipEventRecord(P->ev_t[1], s));
+  // The error flags of the blocks and the setup are read back with the
+  // solve's first scalars (pcg_run), so that nothing here waits for the GPU
+  // (the smoothed-prolongator and cluster setups read back on their own).
   P->have_mixed = mixed;
   P->prepared = true;
-  Timer ts(s);
   if (o->precond == BA_PC_MULTIGRID) {
     if (P->sa) mg_setup_sa(P, o, cams, s);
     else mg_setup(P, o, cams, mixed, s);
   }
   if (o->precond == BA_PC_CLUSTER_JACOBI) cluster_setup(P, s);
-  const double tset = ts.ms();
+  BA_HIP(hipEventRecord(P->ev_t[2], s));
   if (st) {
-    st->t_jacobian_ms = tjac;
-    st->t_setup_ms = tset;
     st->levels = (int)P->levels.size();
     for (size_t l = 0; l < P->levels.size() && l < 16; ++l) {
       const Level& L = P->levels[l];
@@ -991,6 +957,17 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
       st->agg_mean[l] = has ? L.mean_agg : 0.0;
     }
   }
+}
+
+// Phase times of the prepared step into st (waits for the setup to finish).
+static void prepare_times(ba_plan* P, ba_stats* st) {
+  if (!st) return;
+  BA_HIP(hipEventSynchronize(P->ev_t[2]));
+  float a = 0.f, b = 0.f;
+  BA_HIP(hipEventElapsedTime(&a, P->ev_t[0], P->ev_t[1]));
+  BA_HIP(hipEventElapsedTime(&b, P->ev_t[1], P->ev_t[2]));
+  st->t_jacobian_ms = a;
+  st->t_setup_ms = b;
 }
 
 // ---------------------------------------------------------------- PCG
@@ -1038,7 +1015,11 @@ static PcgOut pcg_run(ba_plan* P, const ba_opts* o, const T* b, PcgVecs<T> v, do
   }
   BA_LAUNCH_CHECK();
   BA_HIP(hipMemcpyAsync(W.h_scal, sc, sizeof(PcgScal), hipMemcpyDeviceToHost, s));
+  BA_HIP(hipMemcpyAsync(P->h_err, P->errflag.p, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   BA_HIP(hipStreamSynchronize(s));
+  // an error of the step's blocks or preconditioner setup takes precedence
+  // over what the iteration made of it
+  if (*P->h_err) check_errflag(P, s, "normal blocks or preconditioner setup");
   out.iters = W.h_scal->iters;
   out.rr = W.h_scal->rr;
   out.bb = W.h_scal->bb;
@@ -1171,7 +1152,8 @@ static void level_data(const ba_plan* Pc, int l, int what, double* out, hipStrea
                             hipMemcpyDeviceToDevice, s));
       break;
     case 4:
-      BA_HIP(hipMemcpyAsync(out, &L.lmax, sizeof(double), hipMemcpyHostToDevice, s));
+      BA_CHECK(l + 1 < nl, BA_ERR_ARG, "the coarsest level has no smoother");
+      BA_HIP(hipMemcpyAsync(out, L.lz_s.p + LZ_LMAX, sizeof(double), hipMemcpyDeviceToDevice, s));
       break;
     case 5:
       BA_CHECK(l + 1 == nl, BA_ERR_ARG, "only the coarsest level has an inverse");
