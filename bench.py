@@ -358,7 +358,8 @@ def main():
                            ("mg_mixed", bamg.Options(precond="mg", precision="mixed", **base)),
                            ("bj_mixed", bamg.Options(precond="bj", precision="mixed", **base)),
                            ("mg_fp64_deterministic", bamg.Options(precond="mg", precision="fp64",
-                                                                  deterministic=True, **base))):
+                                                                  deterministic=True, **base)),
+                           ("mg_fp64_graph", bamg.Options(precond="mg", precision="fp64", graph=True, **base))):
             vms, _, s2, vdc, _ = time_steps(plan, cams, pts, uv, opts, max(2, args.steps // 2), 1)
             var[name] = step_entry(vms, s2, vdc, dc)
             log(f"[bench] {name}: {vms:.2f} ms/step, iters {s2.iters}, rel_res {s2.rel_res:.2e}")

@@ -131,7 +131,11 @@ typedef struct {
                                are multiplied by sqrt(rho'(s_o)) (iteratively reweighted least
                                squares, rho's own curvature left out). Not supported by
                                ba_lm_step_backward (BA_ERR_ARG). */
-  int32_t reserved1;
+  int32_t graph;            /* 1: every PCG iteration is replayed from a HIP graph (the iteration's
+                               ~30 launches recorded once per plan, workspace and options, then
+                               reused across steps); 0 (default): launched kernel by kernel. Same
+                               results either way; on MI355X the replay saves no time, because the
+                               GPU, not the host's launch rate, bounds the iteration. */
   double loss_scale;        /* a of BA_LOSS_HUBER, > 0, default 1 (pixels) */
   double smooth_omega;      /* w * lambda_max of BA_PROLONG_SMOOTHED, in (0, 2), default 4/3 */
 } ba_opts;

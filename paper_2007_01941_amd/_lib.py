@@ -52,7 +52,7 @@ class _Opts(ctypes.Structure):
                 ("level0_op", ctypes.c_int32), ("freeze_damping_in_grad", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("deterministic", ctypes.c_int32),
                 ("stop_rule", ctypes.c_int32), ("prolongator", ctypes.c_int32),
-                ("forcing", ctypes.c_double), ("loss", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("forcing", ctypes.c_double), ("loss", ctypes.c_int32), ("graph", ctypes.c_int32),
                 ("loss_scale", ctypes.c_double), ("smooth_omega", ctypes.c_double)]
 
 
@@ -132,6 +132,7 @@ class Options:
     forcing: float = 0.1
     loss: str = "squared"            # "squared" | "huber"
     loss_scale: float = 1.0
+    graph: bool = False              # replay PCG iterations from a captured HIP graph
     prolongator: str = "tentative"   # "tentative" | "smoothed" (fixed when the plan is built)
     smooth_omega: float = 4.0 / 3.0
 
@@ -152,6 +153,7 @@ class Options:
         o.forcing = self.forcing
         o.loss = {"squared": LOSS_SQUARED, "huber": LOSS_HUBER}[self.loss]
         o.loss_scale = self.loss_scale
+        o.graph = int(self.graph)
         o.prolongator = {"tentative": PROLONG_TENTATIVE, "smoothed": PROLONG_SMOOTHED}[self.prolongator]
         o.smooth_omega = self.smooth_omega
         return o

@@ -46,8 +46,13 @@ struct Scratch {
   DBuf<double> dots;     // plain dot results
   DBuf<double> pt_a, pt_b;
   PcgScal* h_scal = nullptr;
+  // one PCG iteration captured as a graph, per precision (0: FP64, 1: FP32),
+  // with the bytes of everything its launches depend on
+  hipGraphExec_t it_exec[2] = {nullptr, nullptr};
+  std::string it_key[2];
   ~Scratch() {
     if (h_scal) (void)hipHostFree(h_scal);
+    for (hipGraphExec_t e : it_exec) if (e) (void)hipGraphExecDestroy(e);
   }
 };
 
@@ -210,6 +215,7 @@ ba_status ba_opts_default(ba_opts* o) {
   o->loss = BA_LOSS_SQUARED;
   o->loss_scale = 1.0;
   o->prolongator = BA_PROLONG_TENTATIVE;
+  o->graph = 0;
   o->smooth_omega = 4.0 / 3.0;
   return BA_OK;
 }
@@ -237,6 +243,7 @@ static void validate_opts(const ba_opts* o) {
            "the Nash-Sofer rule needs forcing >= 0 and BA_FP64");
   BA_CHECK(o->loss == BA_LOSS_SQUARED || o->loss == BA_LOSS_HUBER, BA_ERR_ARG, "bad loss");
   BA_CHECK(o->loss == BA_LOSS_SQUARED || o->loss_scale > 0.0, BA_ERR_ARG, "loss_scale must be > 0");
+  BA_CHECK(o->graph == 0 || o->graph == 1, BA_ERR_ARG, "graph must be 0 or 1");
   BA_CHECK(o->prolongator == BA_PROLONG_TENTATIVE || o->prolongator == BA_PROLONG_SMOOTHED, BA_ERR_ARG,
            "bad prolongator");
   BA_CHECK(o->prolongator == BA_PROLONG_TENTATIVE || (o->smooth_omega > 0.0 && o->smooth_omega < 2.0), BA_ERR_ARG,
@@ -302,7 +309,7 @@ size_t ba_workspace_bytes(const ba_plan* P, const ba_opts* o, int32_t uses) {
 void ba_plan_destroy(ba_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();   // no work of the plan may still use its memory
-  for (hipStream_t st : {p->side, p->side2}) {
+  for (hipStream_t st : {p->side, p->side2, p->cap}) {
     if (!st) continue;
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);

@@ -17,6 +17,8 @@ struct PcgScal {
   double rr;      // r . r after the latest update
   double pq;
   double q;       // quadratic model 1/2 x^T S x - x^T b of the current iterate
+  double rtol2;   // stop when r . r <= rtol2 b . b
+  double forcing; // Nash-Sofer tolerance (< 0: rule off)
   int done;       // converged or broke down
   int iters;      // completed iterations
   int flag;       // ERRF_BREAKDOWN on breakdown
@@ -92,11 +94,13 @@ __global__ __launch_bounds__(256) void k_dot(int n, const T* __restrict__ a, con
   }
 }
 
-// b . b (and zero the iteration state)
+// b . b (and zero the iteration state; the stop tolerances go to the device
+// scalars, so that an iteration's launches do not depend on them)
 template <class T>
 __global__ __launch_bounds__(256) void k_pcg_start(int n, const T* __restrict__ b, T* __restrict__ x,
                                                    T* __restrict__ r, T* __restrict__ p,
-                                                   double* __restrict__ partial, PcgScal* s) {
+                                                   double* __restrict__ partial, PcgScal* s, double rtol2,
+                                                   double forcing) {
   double v = 0.0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
     const T bi = b[i];
@@ -110,6 +114,8 @@ __global__ __launch_bounds__(256) void k_pcg_start(int n, const T* __restrict__ 
   s->bb = tot;
   s->rr = tot;
   s->q = 0.0;
+  s->rtol2 = rtol2;
+  s->forcing = forcing;
   s->done = 0;
   s->iters = 0;
   s->flag = 0;
@@ -148,8 +154,7 @@ __global__ __launch_bounds__(256) void k_pcg_p_Ap(int n_cam, const T* __restrict
 template <class T>
 __global__ __launch_bounds__(256) void k_pcg_xr(int n, const T* __restrict__ p, const T* __restrict__ q,
                                                 T* __restrict__ x, T* __restrict__ r,
-                                                double* __restrict__ partial, PcgScal* s,
-                                                double rtol2, double forcing) {
+                                                double* __restrict__ partial, PcgScal* s) {
   if (s->done) return;
   const T alpha = (T)s->alpha;
   double v = 0.0;
@@ -163,11 +168,11 @@ __global__ __launch_bounds__(256) void k_pcg_xr(int n, const T* __restrict__ p, 
   if (!last_block_sum(v, partial, &s->count[2], &tot)) return;
   s->rr = tot;
   s->iters += 1;
-  if (tot <= rtol2 * s->bb) {
+  if (tot <= s->rtol2 * s->bb) {
     s->done = 1;
-  } else if (forcing >= 0.0) {
+  } else if (s->forcing >= 0.0) {
     const double qn = s->q - 0.5 * s->alpha * s->rz;
-    if ((double)s->iters * (qn - s->q) / qn <= forcing) s->done = 1;
+    if ((double)s->iters * (qn - s->q) / qn <= s->forcing) s->done = 1;
     s->q = qn;
   }
 }

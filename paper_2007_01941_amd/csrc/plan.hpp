@@ -185,6 +185,7 @@ struct ba_plan {
   size_t ws_span = 0;             // bytes that layout spans
   hipEvent_t ev_t[3] = {nullptr, nullptr, nullptr};   // step phases: start, blocks done, setup done
   uint32_t* h_err = nullptr;      // pinned copy of the error flags
+  hipStream_t cap = nullptr;      // stream the PCG iteration graph is captured on (runs nothing)
   bamg::Scratch* scratch = nullptr;
   // side stream of the multigrid setup (default priority), forked from and
   // joined back into the caller's stream with these events

@@ -236,6 +236,7 @@ static void create_runtime(ba_plan* P) {
   BA_HIP(hipHostMalloc((void**)&P->lm->h_scal, sizeof(LmScal), hipHostMallocDefault));
   BA_HIP(hipHostMalloc((void**)&P->lm->h_dots, 4 * sizeof(double), hipHostMallocDefault));
   BA_HIP(hipHostMalloc((void**)&P->h_err, sizeof(uint32_t), hipHostMallocDefault));
+  BA_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
   for (hipEvent_t& e : P->ev_t) BA_HIP(hipEventCreate(&e));
   BA_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
   BA_HIP(hipStreamCreateWithFlags(&P->side2, hipStreamNonBlocking));
@@ -705,25 +706,29 @@ static void lanczos_launch(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
 // scaled back: inv = s (s S s)^-1 s.
 static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
   Level& Lc = P->levels.back();
-  BA_HIP(hipMemsetAsync(Lc.dense.p, 0, (size_t)Lc.nd * Lc.nd * sizeof(double), s));
+  // The steps alternate between the two matrices; start in the one that makes
+  // the last step write Lc.inv, so that the inverse always lands in the same
+  // buffer (a captured V-cycle reads it by address).
+  const int nbk = Lc.nd / GJB;
+  double* src = nbk % 2 == 0 ? Lc.inv.p : Lc.dense.p;
+  double* dst = nbk % 2 == 0 ? Lc.dense.p : Lc.inv.p;
+  BA_HIP(hipMemsetAsync(src, 0, (size_t)Lc.nd * Lc.nd * sizeof(double), s));
   const int64_t tot = Lc.nnz * Lc.bs * Lc.bs + Lc.nd;
   hipLaunchKernelGGL(k_bsr_to_dense, dim3(grid_of<double>(tot)), dim3(256), 0, s, Lc.n, Lc.bs, Lc.nd, Lc.row_of.p,
-                     Lc.col.p, Lc.nnz, Lc.S.p, Lc.dense.p);
+                     Lc.col.p, Lc.nnz, Lc.S.p, src);
   DBuf<double>& scl = Lc.gj_scale;
   const int64_t nd2 = (int64_t)Lc.nd * Lc.nd;
-  hipLaunchKernelGGL(k_dense_diag, dim3(grid_of<double>(Lc.nd)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p,
+  hipLaunchKernelGGL(k_dense_diag, dim3(grid_of<double>(Lc.nd)), dim3(256), 0, s, Lc.nd, src, scl.p,
                      P->errflag.p);
-  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.dense.p, scl.p, 0.0);
+  hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, src, scl.p, 0.0);
   // Pivot step k: P_k = A_kk^-1 (one workgroup), then the update of every block.
-  const int nbk = Lc.nd / GJB;
   for (int k = 0; k < nbk; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)Lc.dense.p, k, Lc.gj_piv.p,
+    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)src, k, Lc.gj_piv.p,
                        P->errflag.p);
-    hipLaunchKernelGGL(k_gj_update, dim3(nbk * (nbk + 1) / 2), dim3(1024), 0, s, Lc.nd, (const double*)Lc.dense.p,
-                       Lc.inv.p, k, (const double*)Lc.gj_piv.p);
-    std::swap(Lc.dense, Lc.inv);
+    hipLaunchKernelGGL(k_gj_update, dim3(nbk * (nbk + 1) / 2), dim3(1024), 0, s, Lc.nd, (const double*)src, dst, k,
+                       (const double*)Lc.gj_piv.p);
+    std::swap(src, dst);
   }
-  std::swap(Lc.dense, Lc.inv);
   hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.inv.p, scl.p, 0.0);
   BA_LAUNCH_CHECK();
 }
@@ -982,31 +987,95 @@ struct PcgOut {
   bool breakdown = false;
 };
 
+// One PCG iteration (Saad, Algorithm 9.1): p = z + beta p with q = A p, then
+// q -= W C^-1 W^T p, alpha = r.z / p.q, x += alpha p, r -= alpha q (and the
+// stop tests), z = M r, beta. Every launch returns at once after `done`.
 template <class T>
-static PcgOut pcg_run(ba_plan* P, const ba_opts* o, const T* b, PcgVecs<T> v, double rtol, int max_iter,
-                      hipStream_t s, double forcing = -1.0) {
+static void pcg_iteration(ba_plan* P, const ba_opts* o, PcgVecs<T> v, hipStream_t s) {
   Scratch& W = *P->scratch;
   PcgScal* sc = W.scal.p;
   const int* done = &sc->done;
   const int n = W.n;
   const int g = red_grid(n);
-  hipLaunchKernelGGL((k_pcg_start<T>), dim3(g), dim3(256), 0, s, n, b, v.x, v.r, v.p, W.partial.p, sc);
+  hipLaunchKernelGGL((k_pcg_p_Ap<T>), dim3(grid_of<T>(9 * P->n_cam, 252 / 9 * 9)), dim3(256), 0, s, P->n_cam,
+                     (const T*)v.z, v.p, A_of<T>(P), v.q, (const PcgScal*)sc);
+  schur_tiles_dev<T>(P, v.p, v.q, done, s);
+  hipLaunchKernelGGL((k_dot<DOT_ALPHA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, W.partial.p,
+                     sc, (double*)nullptr);
+  hipLaunchKernelGGL((k_pcg_xr<T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, v.x, v.r,
+                     W.partial.p, sc);
+  precond_apply<T>(P, o, v.r, v.z, done, s);
+  hipLaunchKernelGGL((k_dot<DOT_BETA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.r, (const T*)v.z, W.partial.p,
+                     sc, (double*)nullptr);
+}
+
+// The bytes of everything an iteration's launches depend on beyond the plan's
+// fixed arrays: the workspace binding, the options that choose kernels or
+// their arguments, level 0's operator form, and the iteration's vectors.
+template <class T>
+static std::string iteration_key(const ba_plan* P, const ba_opts* o, const PcgVecs<T>& v) {
+  std::string k;
+  auto put = [&](const void* p, size_t n) { k.append(static_cast<const char*>(p), n); };
+  put(&P->ws_base, sizeof(P->ws_base));
+  put(&P->ws_key, sizeof(P->ws_key));
+  put(&o->precond, sizeof(o->precond));
+  put(&o->cheb_degree, sizeof(o->cheb_degree));
+  put(&o->cheb_lo, sizeof(o->cheb_lo));
+  put(&o->cheb_hi, sizeof(o->cheb_hi));
+  const char flags[3] = {(char)P->det, (char)P->sa, (char)(!P->levels.empty() && P->levels[0].explicit_op)};
+  put(flags, sizeof(flags));
+  put(&v, sizeof(v));
+  return k;
+}
+
+// The iteration as an executable graph, captured (on the plan's capture
+// stream, which records and runs nothing) when nothing cached matches.
+template <class T>
+static hipGraphExec_t iteration_graph(ba_plan* P, const ba_opts* o, const PcgVecs<T>& v) {
+  Scratch& W = *P->scratch;
+  const int ti = sizeof(T) == 4 ? 1 : 0;
+  std::string key = iteration_key<T>(P, o, v);
+  if (W.it_exec[ti] && W.it_key[ti] == key) return W.it_exec[ti];
+  if (W.it_exec[ti]) {
+    BA_HIP(hipGraphExecDestroy(W.it_exec[ti]));
+    W.it_exec[ti] = nullptr;
+  }
+  BA_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  hipGraph_t graph = nullptr;
+  try {
+    pcg_iteration<T>(P, o, v, P->cap);
+  } catch (...) {
+    (void)hipStreamEndCapture(P->cap, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  BA_HIP(hipStreamEndCapture(P->cap, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  BA_HIP(e);
+  W.it_exec[ti] = exec;
+  W.it_key[ti] = std::move(key);
+  return exec;
+}
+
+template <class T>
+static PcgOut pcg_run(ba_plan* P, const ba_opts* o, const T* b, PcgVecs<T> v, double rtol, int max_iter,
+                      hipStream_t s, double forcing = -1.0) {
+  Scratch& W = *P->scratch;
+  PcgScal* sc = W.scal.p;
+  const int n = W.n;
+  const int g = red_grid(n);
+  hipLaunchKernelGGL((k_pcg_start<T>), dim3(g), dim3(256), 0, s, n, b, v.x, v.r, v.p, W.partial.p, sc, rtol * rtol,
+                     forcing);
   precond_apply<T>(P, o, v.r, v.z, nullptr, s);
   hipLaunchKernelGGL((k_dot<DOT_INIT, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.r, (const T*)v.z, W.partial.p,
                      sc, (double*)nullptr);
-  const double rtol2 = rtol * rtol;
+  const hipGraphExec_t exec = o->graph ? iteration_graph<T>(P, o, v) : nullptr;
   PcgOut out;
   for (int it = 0; it < max_iter; ++it) {
-    hipLaunchKernelGGL((k_pcg_p_Ap<T>), dim3(grid_of<T>(9 * P->n_cam, 252 / 9 * 9)), dim3(256), 0, s, P->n_cam,
-                       (const T*)v.z, v.p, A_of<T>(P), v.q, (const PcgScal*)sc);
-    schur_tiles_dev<T>(P, v.p, v.q, done, s);
-    hipLaunchKernelGGL((k_dot<DOT_ALPHA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, W.partial.p,
-                       sc, (double*)nullptr);
-    hipLaunchKernelGGL((k_pcg_xr<T>), dim3(g), dim3(256), 0, s, n, (const T*)v.p, (const T*)v.q, v.x, v.r,
-                       W.partial.p, sc, rtol2, forcing);
-    precond_apply<T>(P, o, v.r, v.z, done, s);
-    hipLaunchKernelGGL((k_dot<DOT_BETA, T>), dim3(g), dim3(256), 0, s, n, (const T*)v.r, (const T*)v.z, W.partial.p,
-                       sc, (double*)nullptr);
+    if (exec) BA_HIP(hipGraphLaunch(exec, s));
+    else pcg_iteration<T>(P, o, v, s);
     if ((it + 1) % o->check_every == 0 || it + 1 == max_iter) {
       BA_HIP(hipMemcpyAsync(W.h_scal, sc, sizeof(PcgScal), hipMemcpyDeviceToHost, s));
       BA_HIP(hipStreamSynchronize(s));
