@@ -7,6 +7,37 @@
 
 namespace bamg {
 
+// Prolongation into the finer level fused into the kernel that finishes a
+// coarse node's iterate: x_f,i += P_i x_a for the members i of aggregate a
+// (each fine node has one aggregate, so no two workgroups write one x_f,i).
+template <class T>
+struct ProlongTo {
+  const int32_t* ptr = nullptr;   // finer level's members of every aggregate: mem[ptr[a] .. ptr[a+1])
+  const int32_t* mem = nullptr;
+  const T* P = nullptr;           // its tentative blocks [n_f][bs][16]
+  T* x = nullptr;                 // its iterate (null: no prolongation)
+  int bs = 0;                     // its block size
+};
+
+// x_f,i += P_i xa over the members of aggregate a, on one wave whose lane m
+// (m < 16) holds component m of x_a in xv; lanes step over (member, row) pairs.
+template <class T>
+__device__ __forceinline__ void prolong_members(const ProlongTo<T>& pro, int a, T xv) {
+  const int lane = threadIdx.x & 63;
+  T xa[NS];
+#pragma unroll
+  for (int m = 0; m < NS; ++m) xa[m] = __shfl(xv, m, 64);
+  const int i0 = pro.ptr[a], cnt = (pro.ptr[a + 1] - i0) * pro.bs;
+  for (int q = lane; q < cnt; q += 64) {
+    const int i = pro.mem[i0 + q / pro.bs], k = q % pro.bs;
+    const T* Pi = pro.P + ((size_t)i * pro.bs + k) * NS;
+    T s = 0;
+#pragma unroll
+    for (int m = 0; m < NS; ++m) s += Pi[m] * xa[m];
+    pro.x[(size_t)i * pro.bs + k] += s;
+  }
+}
+
 // Epilogues of the block-row product t = (S v)_i (one node i per workgroup).
 // The Chebyshev coefficient c2 is given for lambda_max = 1 and scaled by
 // *ilmax = 1 / lambda_max, which stays on the device:
@@ -38,7 +69,7 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
                                                  T* __restrict__ x_out, T c1, T c2,
                                                  const double* __restrict__ ilmax,
                                                  const T* __restrict__ P, const int32_t* __restrict__ slot_of,
-                                                 T* __restrict__ rpart, const int* done) {
+                                                 T* __restrict__ rpart, ProlongTo<T> pro, const int* done) {
   if (done && *done) return;
   constexpr int BB = BS * BS;
   constexpr int NB = 256 / BB;
@@ -129,14 +160,21 @@ __global__ __launch_bounds__(256) void k_bsr_row(int n, const int32_t* __restric
     }
     return;
   }
-  if (!own) return;
-  T z = 0;
+  if (threadIdx.x >= 64) return;   // the node's components are on lanes 0 .. BS-1 of wave 0
+  T xv = 0;
+  if (own) {
+    T z = 0;
 #pragma unroll
-  for (int k2 = 0; k2 < BS; ++k2) z += mrow[k2] * rs[k2];
-  const T c2s = c2 * (T)*ilmax;
-  const T dv = EP == EP_CHEB ? c1 * d0 + c2s * z : c2s * z;
-  d_out[k] = dv;
-  x_out[k] = x0 + dv;
+    for (int k2 = 0; k2 < BS; ++k2) z += mrow[k2] * rs[k2];
+    const T c2s = c2 * (T)*ilmax;
+    const T dv = EP == EP_CHEB ? c1 * d0 + c2s * z : c2s * z;
+    d_out[k] = dv;
+    xv = x0 + dv;
+    x_out[k] = xv;
+  }
+  if constexpr (EP == EP_CHEB && BS == NS) {
+    if (pro.x) prolong_members(pro, row, xv);
+  }
 }
 
 // z = D^-1 r block by block (BS x BS inverse blocks), one thread per dof.
@@ -311,6 +349,54 @@ __global__ __launch_bounds__(256) void k_dense_solve(int nv, int nd, const doubl
   }
   double s = wave_sum(s0 + s1);
   if (lane == 0) x[row] = (T)s;
+}
+
+// The coarsest solve with its neighbours fused, one workgroup of 16 waves per
+// coarsest node (wave w computes row w of the node): b is first summed from
+// the finer level's restriction partials (each workgroup forms all of it in
+// LDS; workgroup 0 also stores it), x = inv b, then x is prolonged into the
+// finer level (pro.x set). nv <= 4096.
+__global__ __launch_bounds__(1024) void k_coarse_solve_fused(int n, int nd, const double* __restrict__ inv,
+                                                             double* __restrict__ b,
+                                                             const int32_t* __restrict__ agg_ptr,
+                                                             const double* __restrict__ part, double* __restrict__ x,
+                                                             ProlongTo<double> pro, const int* done) {
+  if (done && *done) return;
+  __shared__ double bs[4096];
+  __shared__ double xs[NS];
+  const int nv = n * NS;
+  const int a = blockIdx.x;
+  for (int g = threadIdx.x; g < nv; g += 1024) {
+    double v;
+    if (part) {
+      const int c = g / NS, m = g % NS;
+      v = 0.0;
+      for (int q = agg_ptr[c]; q < agg_ptr[c + 1]; ++q) v += part[(size_t)q * NS + m];
+      if (a == 0) b[g] = v;
+    } else {
+      v = b[g];
+    }
+    bs[g] = v;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int row = a * NS + w;
+  const double* m = inv + (size_t)row * nd;
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+  for (int k = 2 * lane; k < nv; k += 128) {
+    const double2 mv = *reinterpret_cast<const double2*>(m + k);
+    s0 += mv.x * bs[k];
+    if (k + 1 < nv) s1 += mv.y * bs[k + 1];
+  }
+  const double sum = wave_sum(s0 + s1);
+  if (lane == 0) {
+    x[row] = sum;
+    xs[w] = sum;
+  }
+  if (!pro.x) return;
+  __syncthreads();
+  if (w == 0) prolong_members(pro, a, lane < NS ? xs[lane] : 0.0);
 }
 
 // Lanczos start vector on dof i of a level: (splitmix64(seed ^ i) >> 11) 2^-53 - 1/2,

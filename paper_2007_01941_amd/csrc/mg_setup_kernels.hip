@@ -467,11 +467,12 @@ __global__ __launch_bounds__(64) void k_mfma_probe(const double* X, const double
 // Gauss-Jordan elimination with 64 x 64 pivot blocks. With P = A_kk^-1, one
 // pivot step maps
 //   A_kk <- P,  A_kj <- P A_kj,  A_ik <- -A_ik P,  A_ij <- A_ij - A_ik P A_kj,
-// and after every block has served as pivot A holds A^-1. Each step is two
-// launches: the pivot inverse (one workgroup) and the update of every block
-// (one workgroup per block, reading one copy of A and writing the other). nd is a
-// multiple of 64; pivots are the diagonal blocks of successive Schur
-// complements, positive definite for SPD A.
+// and after every block has served as pivot A holds A^-1. The first pivot
+// inverse is a launch of its own (one workgroup); every step is then one
+// launch that updates every block (one workgroup per block, reading one copy
+// of A and writing the other) and inverts the next pivot. nd is a multiple of
+// 64; pivots are the diagonal blocks of successive Schur complements,
+// positive definite for SPD A.
 constexpr int GJB = 64;
 
 // In-place inverse of a 4 x 4 SPD matrix (row-major) by Gauss-Jordan without
@@ -556,22 +557,6 @@ __device__ __forceinline__ bool pivot_inverse64(double (&v)[16], double (*rowK)[
   return ok;
 }
 
-// One 64 x 64 block product on 16 waves: wave w owns output tile (w/4, w%4);
-// acc += sx * X Y (X, Y 64 x 64 row-major, leading dims ldx, ldy).
-__device__ __forceinline__ d4 block_mma(d4 acc, const double* X, int ldx, const double* Y, int ldy, double sx) {
-  const int w = threadIdx.x >> 6;
-  const int tr = w >> 2, tc = w & 3;
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-    acc = tile_mma_nn(acc, X + (size_t)(tr * 16) * ldx + t * 16, ldx, Y + (size_t)(t * 16) * ldy + tc * 16, ldy, sx);
-  return acc;
-}
-
-__device__ __forceinline__ double* block_tile(double* B, int ld) {
-  const int w = threadIdx.x >> 6;
-  return B + (size_t)((w >> 2) * 16) * ld + (w & 3) * 16;
-}
-
 // P = A_kk^-1 for pivot step k (one workgroup of 256 threads).
 __global__ __launch_bounds__(256) void k_gj_pivot(int nd, const double* __restrict__ A, int k,
                                                   double* __restrict__ Pbuf, uint32_t* err) {
@@ -589,71 +574,118 @@ __global__ __launch_bounds__(256) void k_gj_pivot(int nd, const double* __restri
   for (int m = 0; m < 16; ++m) Pbuf[(ii + 4 * m) * GJB + jj] = v[m];
 }
 
-// 64 x 64 block (row stride ld) into LDS (row stride GJB + 1), coalesced.
-__device__ __forceinline__ void stage_block(double* __restrict__ dst, const double* __restrict__ src, size_t ld) {
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int idx = threadIdx.x + 1024 * r;
-    dst[(idx / GJB) * (GJB + 1) + idx % GJB] = src[(size_t)(idx / GJB) * ld + idx % GJB];
-  }
-}
-
 // Pivot step k of blocked Gauss-Jordan from Ain to Aout, given P = A_kk^-1:
-// one workgroup (16 waves) per 64 x 64 block (i, j), i <= j, writes
+// one workgroup of four waves per 64 x 64 block (i, j), i <= j (wave w
+// computes tile row w of the output, four 16 x 16 tiles), writes
 //   (k, k): P;   (k, j): P A_kj;   (i, k): -A_ik P;   else A_ij - A_ik (P A_kj),
 // operands staged in LDS, products on the FP64 matrix cores. The iterate
 // keeps a fixed symmetry: A_ji = s A_ij^T with s = -1 when exactly one of
 // i, j has already served as pivot (i, j <= k) and +1 otherwise, so each
 // workgroup also writes block (j, i) and only the upper blocks are computed.
-__global__ __launch_bounds__(1024) void k_gj_update(int nd, const double* __restrict__ Ain, double* __restrict__ Aout,
-                                                    int k, const double* __restrict__ Pbuf) {
+// Look-ahead: the workgroup of block (k+1, k+1), the next step's pivot block,
+// is dispatched first and also inverts its result into Pnext
+// (pivot_inverse64 on its 256 threads), so every step after the first is one
+// launch and the inverse overlaps the other blocks' updates.
+__device__ __forceinline__ void stage_block256(double* __restrict__ dst, const double* __restrict__ src, size_t ld) {
+#pragma unroll 4
+  for (int r = 0; r < 16; ++r) {
+    const int idx = threadIdx.x + 256 * r;
+    dst[(idx / GJB) * (GJB + 1) + idx % GJB] = src[(size_t)(idx / GJB) * ld + idx % GJB];
+  }
+}
+
+// acc[u] += sx * (X Y) tile (w, u), X and Y 64 x 64 in LDS (leading dim ld)
+__device__ __forceinline__ void row_mma4(d4 (&acc)[4], const double* X, const double* Y, int ld, double sx) {
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      acc[u] = tile_mma_nn(acc[u], X + (size_t)(w * 16) * ld + t * 16, ld, Y + (size_t)(t * 16) * ld + u * 16, ld, sx);
+}
+
+__global__ __launch_bounds__(256) void k_gj_step(int nd, const double* __restrict__ Ain, double* __restrict__ Aout,
+                                                 int k, const double* __restrict__ Pbuf, double* __restrict__ Pnext,
+                                                 uint32_t* err) {
   constexpr int LD = GJB + 1;
   __shared__ double X[GJB * LD];
   __shared__ double Y[GJB * LD];
+  __shared__ double rowK[2][4][GJB];
+  __shared__ double colK[2][GJB][4];
   const int nb = nd / GJB;
-  // upper block number -> (bi, bj), bi <= bj, row by row
-  int bi = 0, rem = blockIdx.x;
+  // upper block number -> (bi, bj), bi <= bj, row by row; the next pivot
+  // block (k+1, k+1) goes to workgroup 0
+  int e = blockIdx.x;
+  if (k + 1 < nb) {
+    const int di = (k + 1) * nb - (k + 1) * k / 2;
+    e = e == 0 ? di : e <= di ? e - 1 : e;
+  }
+  int bi = 0, rem = e;
   while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
   const int bj = bi + rem;
   const size_t k0 = (size_t)k * GJB, i0 = (size_t)bi * GJB, j0 = (size_t)bj * GJB;
-  d4 acc = {0, 0, 0, 0};
-  if (bi == k && bj == k) {
-    stage_block(X, Pbuf, GJB);
-    __syncthreads();
-    acc = tile_load(block_tile(X, LD), LD);
-  } else if (bi == k) {
-    stage_block(X, Pbuf, GJB);
-    stage_block(Y, Ain + k0 * nd + j0, nd);
-    __syncthreads();
-    acc = block_mma(acc, X, LD, Y, LD, 1.0);
-  } else if (bj == k) {
-    stage_block(X, Ain + i0 * nd + k0, nd);
-    stage_block(Y, Pbuf, GJB);
-    __syncthreads();
-    acc = block_mma(acc, X, LD, Y, LD, -1.0);
-  } else {
-    stage_block(X, Pbuf, GJB);
-    stage_block(Y, Ain + k0 * nd + j0, nd);
-    __syncthreads();
-    d4 tk = {0, 0, 0, 0};
-    tk = block_mma(tk, X, LD, Y, LD, 1.0);   // T = P A_kj
-    __syncthreads();                          // every wave is done with X and Y
-    tile_store(block_tile(Y, LD), LD, tk);
-    stage_block(X, Ain + i0 * nd + k0, nd);
-    __syncthreads();
-    acc = tile_load(block_tile(const_cast<double*>(Ain) + i0 * nd + j0, nd), nd);
-    acc = block_mma(acc, X, LD, Y, LD, -1.0);
-  }
-  tile_store(block_tile(Aout + i0 * nd + j0, nd), nd, acc);
-  if (bi != bj) {
-    // block (j, i) = s (block (i, j))^T: this wave's tile (tr, tc) goes to
-    // tile (tc, tr) of block (j, i), transposed
-    const double sgn = ((bi <= k) != (bj <= k)) ? -1.0 : 1.0;
-    const int w = threadIdx.x >> 6, tr = w >> 2, tc = w & 3;
-    const int l = threadIdx.x & 63;
-    double* T = Aout + (j0 + tc * 16) * nd + i0 + tr * 16;
+  const int w = threadIdx.x >> 6;
+  d4 acc[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) T[(size_t)(l & 15) * nd + 4 * t + (l >> 4)] = sgn * acc[t];
+  for (int u = 0; u < 4; ++u) acc[u] = d4{0, 0, 0, 0};
+  if (bi == k && bj == k) {
+    stage_block256(X, Pbuf, GJB);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = tile_load(X + (size_t)(w * 16) * LD + u * 16, LD);
+  } else if (bi == k) {
+    stage_block256(X, Pbuf, GJB);
+    stage_block256(Y, Ain + k0 * nd + j0, nd);
+    __syncthreads();
+    row_mma4(acc, X, Y, LD, 1.0);
+  } else if (bj == k) {
+    stage_block256(X, Ain + i0 * nd + k0, nd);
+    stage_block256(Y, Pbuf, GJB);
+    __syncthreads();
+    row_mma4(acc, X, Y, LD, -1.0);
+  } else {
+    stage_block256(X, Pbuf, GJB);
+    stage_block256(Y, Ain + k0 * nd + j0, nd);
+    __syncthreads();
+    d4 tk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tk[u] = d4{0, 0, 0, 0};
+    row_mma4(tk, X, Y, LD, 1.0);   // T = P A_kj
+    __syncthreads();                // every wave is done with X and Y
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tile_store(Y + (size_t)(w * 16) * LD + u * 16, LD, tk[u]);
+    stage_block256(X, Ain + i0 * nd + k0, nd);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = tile_load(Ain + (i0 + w * 16) * nd + j0 + u * 16, nd);
+    row_mma4(acc, X, Y, LD, -1.0);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) tile_store(Aout + (i0 + w * 16) * nd + j0 + u * 16, nd, acc[u]);
+  if (bi != bj) {
+    // block (j, i) = s (block (i, j))^T: tile (w, u) goes to tile (u, w) of
+    // block (j, i), transposed
+    const double sgn = ((bi <= k) != (bj <= k)) ? -1.0 : 1.0;
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double* T = Aout + (j0 + u * 16) * nd + i0 + w * 16;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) T[(size_t)(l & 15) * nd + 4 * t + (l >> 4)] = sgn * acc[u][t];
+    }
+  } else if (bi == k + 1) {
+    // the next pivot block, inverted here from the values Aout receives
+    __syncthreads();   // every wave is done reading X
+#pragma unroll
+    for (int u = 0; u < 4; ++u) tile_store(X + (size_t)(w * 16) * LD + u * 16, LD, acc[u]);
+    __syncthreads();
+    const int t = threadIdx.x, jj = t % GJB, ii = t / GJB;
+    double v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = X[(ii + 4 * m) * LD + jj];
+    if (!pivot_inverse64(v, rowK, colK) && t == 0) atomicOr(err, ERRF_NOT_SPD);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) Pnext[(ii + 4 * m) * GJB + jj] = v[m];
   }
 }
 

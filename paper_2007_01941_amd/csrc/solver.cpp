@@ -140,7 +140,7 @@ static size_t layout_ws(ba_plan* P, uint32_t key, char* base) {
       c.take(L.dense, (size_t)L.nd * L.nd);
       c.take(L.inv, (size_t)L.nd * L.nd);
       c.take(L.gj_scale, L.nd);
-      c.take(L.gj_piv, GJB * GJB);
+      c.take(L.gj_piv, 2 * GJB * GJB);
     }
     for (DBuf<double>* v : {&L.vb, &L.vx, &L.vr, &L.vd, &L.vt}) c.take(*v, nv);
     if (mixed && l == 0) {
@@ -341,12 +341,12 @@ static void op_apply(ba_plan* P, int l, const T* x, T* y, const int* done, hipSt
     hipLaunchKernelGGL((k_bsr_row<9, T, EP_STORE>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p, lvS<T>(L),
                        x, y, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr, (T*)nullptr,
                        (const T*)nullptr, (T*)nullptr, T(0), T(0), (const double*)nullptr, (const T*)nullptr,
-                       (const int32_t*)nullptr, (T*)nullptr, done);
+                       (const int32_t*)nullptr, (T*)nullptr, ProlongTo<T>(), done);
   else
     hipLaunchKernelGGL((k_bsr_row<16, T, EP_STORE>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p,
                        lvS<T>(L), x, y, (const T*)nullptr, (const T*)nullptr, (T*)nullptr, (const T*)nullptr,
                        (T*)nullptr, (const T*)nullptr, (T*)nullptr, T(0), T(0), (const double*)nullptr,
-                       (const T*)nullptr, (const int32_t*)nullptr, (T*)nullptr, done);
+                       (const T*)nullptr, (const int32_t*)nullptr, (T*)nullptr, ProlongTo<T>(), done);
 }
 
 // Block-row product with the explicit operator of level l and a fused epilogue
@@ -354,12 +354,13 @@ static void op_apply(ba_plan* P, int l, const T* x, T* y, const int* done, hipSt
 // kernel scales it by the level's 1 / lambda_max on the device).
 template <int BS, class T, int EP>
 static void row_op(ba_plan* P, int l, const T* v, const T* b, T* r, const T* d_in, T* d_out, const T* x_in,
-                   T* x_out, double c1, double c2, T* part, const int* done, hipStream_t s) {
+                   T* x_out, double c1, double c2, T* part, const int* done, hipStream_t s,
+                   ProlongTo<T> pro = ProlongTo<T>()) {
   Level& L = P->levels[l];
   hipLaunchKernelGGL((k_bsr_row<BS, T, EP>), dim3(L.n), dim3(256), 0, s, L.n, L.rowptr32.p, L.col.p, lvS<T>(L), v,
                      (T*)nullptr, lvDinv<T>(P, l), b, r, d_in, d_out, x_in, x_out, (T)c1, (T)c2,
-                     (const double*)(L.lz_s.p + LZ_ILMAX), part ? lvP<T>(L) : (const T*)nullptr, part ? L.slot_of.p : (const int32_t*)nullptr, part,
-                     done);
+                     (const double*)(L.lz_s.p + LZ_ILMAX), part ? lvP<T>(L) : (const T*)nullptr,
+                     part ? L.slot_of.p : (const int32_t*)nullptr, part, pro, done);
 }
 
 template <int BS, class T>
@@ -380,25 +381,35 @@ struct Pending {
 
 template <int BS, class T>
 static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> pend, const int* done,
-                         hipStream_t s);
+                         hipStream_t s, ProlongTo<T> pro);
 
 // x = M_l b: the V-cycle from level l (Algorithm 1), x overwritten. With
-// pend.part set, b is first formed from the finer level's partials.
+// pend.part set, b is first formed from the finer level's partials; with
+// pro.x set, x is finally prolonged into the finer level (x_f += P x), inside
+// the kernel that finishes x.
 template <class T>
 static void vcycle(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> pend, const int* done,
-                   hipStream_t s) {
+                   hipStream_t s, ProlongTo<T> pro = ProlongTo<T>()) {
   Level& L = P->levels[l];
   if (l + 1 == (int)P->levels.size()) {
+    const int nv = L.n * L.bs;
+    if constexpr (std::is_same<T, double>::value) {
+      if (l > 0 && nv <= 4096) {
+        hipLaunchKernelGGL(k_coarse_solve_fused, dim3(L.n), dim3(1024), 0, s, L.n, L.nd, (const double*)L.inv.p, b,
+                           pend.agg_ptr, pend.part, x, pro, done);
+        return;
+      }
+    }
     if (pend.part)
       hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)L.n * NS)), dim3(256), 0, s, L.n,
                          pend.agg_ptr, pend.part, b, done);
-    const int nv = L.n * L.bs;
     hipLaunchKernelGGL((k_dense_solve<T>), dim3(grid_of<T>(nv, 4)), dim3(256), 0, s, nv, L.nd, L.inv.p,
                        (const T*)b, x, done);
+    BA_CHECK(!pro.x, BA_ERR_ARG, "internal: a prolongation pending at an unfused coarsest solve");
     return;
   }
-  if (L.bs == 9) vcycle_level<9, T>(P, o, l, b, x, pend, done, s);
-  else vcycle_level<16, T>(P, o, l, b, x, pend, done, s);
+  if (L.bs == 9) vcycle_level<9, T>(P, o, l, b, x, pend, done, s, pro);
+  else vcycle_level<16, T>(P, o, l, b, x, pend, done, s, pro);
 }
 
 // Coarse-grid correction of level l: xc = V-cycle of level l+1 on the restricted
@@ -415,6 +426,17 @@ template <>
 void coarse_correction<double>(ba_plan* P, const ba_opts* o, int l, double* bc, double* xc, Pending<double> pend,
                                const int* done, hipStream_t s) {
   vcycle<double>(P, o, l + 1, bc, xc, pend, done, s);
+}
+
+// The FP64 coarse-grid correction with level l's prolongation fused into the
+// coarse level's last kernel (x += P xc without a launch of its own). Whether
+// level l+1 can take it: its V-cycle must end in a Chebyshev row update
+// (degree >= 2) or be the fused coarsest solve.
+static bool can_fuse_prolong(const ba_plan* P, const ba_opts* o, int l) {
+  if (P->sa) return false;
+  const int c = l + 1;
+  if (c + 1 == (int)P->levels.size()) return c > 0 && P->levels[c].n * NS <= 4096;
+  return o->cheb_degree >= 2;
 }
 
 template <>
@@ -464,7 +486,7 @@ static void sa_prolong(ba_plan* P, int l, const T* xc, T* x, const int* done, hi
 // ping-ponged between two buffers so that no launch writes its product's input.
 template <int BS, class T>
 static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> pend, const int* done,
-                               hipStream_t s) {
+                               hipStream_t s, ProlongTo<T> pro) {
   Level& L = P->levels[l];
   Level& C = P->levels[l + 1];
   T* r = LvVec<T>::r(L);
@@ -508,14 +530,31 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, 
     Pending<T> next;
     next.agg_ptr = L.agg_ptr.p;
     next.part = part;
-    coarse_correction<T>(P, o, l, bc, xc, next, done, s);
-    hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
-                       lvP<T>(L), (const T*)xc, x, done);
+    bool fused = false;
+    if constexpr (std::is_same<T, double>::value) {
+      if (can_fuse_prolong(P, o, l)) {
+        // x += P xc happens in the coarse level's last kernel
+        ProlongTo<double> mine;
+        mine.ptr = L.agg_ptr.p;
+        mine.mem = L.agg_mem.p;
+        mine.P = L.P.p;
+        mine.x = x;
+        mine.bs = BS;
+        vcycle<double>(P, o, l + 1, bc, xc, next, done, s, mine);
+        fused = true;
+      }
+    }
+    if (!fused) {
+      coarse_correction<T>(P, o, l, bc, xc, next, done, s);
+      hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
+                         lvP<T>(L), (const T*)xc, x, done);
+    }
   }
   // post-smoothing from x: r = b - S x, d = D^-1 r / theta, iterate -> x2
   rho = 1.0 / sigma1;
   row_op<BS, T, EP_CHEB_POST>(P, l, x, b, r, nullptr, dA, x, x2, 0.0, 1.0 / theta, nullptr, done, s);
   if (m == 1) {
+    BA_CHECK(!pro.x, BA_ERR_ARG, "internal: a fused prolongation needs two smoothing steps");
     hipLaunchKernelGGL((k_convert<T, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n * BS,
                        (const T*)x2, x);
     return;
@@ -523,7 +562,9 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, 
   for (int k = 0; k < m - 1; ++k) {
     const double rn = 1.0 / (2.0 * sigma1 - rho);
     T* xo = k == m - 2 ? x : x2;
-    row_op<BS, T, EP_CHEB>(P, l, dA, nullptr, r, dA, dB, x2, xo, rn * rho, 2.0 * rn / delta, nullptr, done, s);
+    // the last step finishes x: the finer level's prolongation goes with it
+    row_op<BS, T, EP_CHEB>(P, l, dA, nullptr, r, dA, dB, x2, xo, rn * rho, 2.0 * rn / delta, nullptr, done, s,
+                           k == m - 2 ? pro : ProlongTo<T>());
     std::swap(dA, dB);
     rho = rn;
   }
@@ -531,12 +572,13 @@ static void vcycle_level_fused(ba_plan* P, const ba_opts* o, int l, T* b, T* x, 
 
 template <int BS, class T>
 static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pending<T> pend, const int* done,
-                         hipStream_t s) {
+                         hipStream_t s, ProlongTo<T> pro) {
   Level& L = P->levels[l];
   if (l > 0 || L.explicit_op) {
-    vcycle_level_fused<BS, T>(P, o, l, b, x, pend, done, s);
+    vcycle_level_fused<BS, T>(P, o, l, b, x, pend, done, s, pro);
     return;
   }
+  BA_CHECK(!pro.x, BA_ERR_ARG, "internal: level 0 has no finer level");
   Level& C = P->levels[l + 1];
   T* r = LvVec<T>::r(L);
   T* d = LvVec<T>::d(L);
@@ -575,9 +617,24 @@ static void vcycle_level(ba_plan* P, const ba_opts* o, int l, T* b, T* x, Pendin
                        L.slot_of.p, lvP<T>(L), (const T*)r, (const T*)t, part, done);
     hipLaunchKernelGGL((k_restrict_sum<T>), dim3(grid_of<T>((int64_t)C.n * NS)), dim3(256), 0, s, C.n,
                        L.agg_ptr.p, (const T*)part, bc, done);
-    coarse_correction<T>(P, o, l, bc, xc, Pending<T>(), done, s);
-    hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
-                       lvP<T>(L), (const T*)xc, x, done);
+    bool fused = false;
+    if constexpr (std::is_same<T, double>::value) {
+      if (can_fuse_prolong(P, o, l)) {
+        ProlongTo<double> mine;
+        mine.ptr = L.agg_ptr.p;
+        mine.mem = L.agg_mem.p;
+        mine.P = L.P.p;
+        mine.x = x;
+        mine.bs = BS;
+        vcycle<double>(P, o, l + 1, bc, xc, Pending<double>(), done, s, mine);
+        fused = true;
+      }
+    }
+    if (!fused) {
+      coarse_correction<T>(P, o, l, bc, xc, Pending<T>(), done, s);
+      hipLaunchKernelGGL((k_prolong<BS, T>), dim3(grid_of<T>((int64_t)L.n * BS)), dim3(256), 0, s, L.n, L.agg.p,
+                         lvP<T>(L), (const T*)xc, x, done);
+    }
   }
   // post-smoothing from x
   op_apply<T>(P, l, x, t, done, s);
@@ -721,12 +778,15 @@ static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_diag, dim3(grid_of<double>(Lc.nd)), dim3(256), 0, s, Lc.nd, src, scl.p,
                      P->errflag.p);
   hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, src, scl.p, 0.0);
-  // Pivot step k: P_k = A_kk^-1 (one workgroup), then the update of every block.
+  // P_0 = A_00^-1 (one workgroup); then step k updates every block with P_k
+  // and inverts the next pivot block into P_{k+1} (two alternating buffers).
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)src, 0, Lc.gj_piv.p,
+                     P->errflag.p);
   for (int k = 0; k < nbk; ++k) {
-    hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)src, k, Lc.gj_piv.p,
-                       P->errflag.p);
-    hipLaunchKernelGGL(k_gj_update, dim3(nbk * (nbk + 1) / 2), dim3(1024), 0, s, Lc.nd, (const double*)src, dst, k,
-                       (const double*)Lc.gj_piv.p);
+    const double* pk = Lc.gj_piv.p + (size_t)(k & 1) * GJB * GJB;
+    double* pn = Lc.gj_piv.p + (size_t)((k + 1) & 1) * GJB * GJB;
+    hipLaunchKernelGGL(k_gj_step, dim3(nbk * (nbk + 1) / 2), dim3(256), 0, s, Lc.nd, (const double*)src, dst, k, pk,
+                       pn, P->errflag.p);
     std::swap(src, dst);
   }
   hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, Lc.inv.p, scl.p, 0.0);
