@@ -60,7 +60,7 @@ def kernel_bytes(n_obs, n_pt, n_cam, s):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("schur_kernels.hip", "common.hpp"):
+    for f in ("schur_kernels.hip", "common.hpp", "layout.cpp"):   # layout.cpp groups the tiles
         h.update(open(os.path.join(ROOT, "paper_2007_01941_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
