@@ -43,6 +43,10 @@ struct Scratch {
   DBuf<float> fx, fr, fz, fp, fq, fb;
   DBuf<double> partial;
   DBuf<PcgScal> scal;
+  // reduction scratch of the Lanczos estimates, one slice per setup stream
+  // (levels on different streams run concurrently)
+  DBuf<double> lz_partial;   // [3][RED_BLOCKS]
+  DBuf<PcgScal> lz_scal;     // [3] (only the reduction counters are used)
   DBuf<double> dots;     // plain dot results
   DBuf<double> pt_a, pt_b;
   PcgScal* h_scal = nullptr;
@@ -309,7 +313,7 @@ size_t ba_workspace_bytes(const ba_plan* P, const ba_opts* o, int32_t uses) {
 void ba_plan_destroy(ba_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();   // no work of the plan may still use its memory
-  for (hipStream_t st : {p->side, p->side2, p->cap}) {
+  for (hipStream_t st : {p->side, p->side2, p->side3, p->cap}) {
     if (!st) continue;
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
@@ -317,7 +321,7 @@ void ba_plan_destroy(ba_plan* p) {
   for (hipEvent_t e : p->ev_qr) if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->ev_lvl) if (e) (void)hipEventDestroy(e);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
-  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  for (hipEvent_t e : p->ev_lz) if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : p->ev_t) if (e) (void)hipEventDestroy(e);
   if (p->h_err) (void)hipHostFree(p->h_err);
   delete p->scratch;

@@ -77,6 +77,7 @@ static ba_status lm_solve(ba_plan* P, const ba_opts* o_in, const ba_lm_opts* lo,
       // Drain the plan's streams before the next attempt reuses its buffers.
       BA_HIP(hipStreamSynchronize(P->side));
       BA_HIP(hipStreamSynchronize(P->side2));
+      BA_HIP(hipStreamSynchronize(P->side3));
       BA_HIP(hipMemsetAsync(P->errflag.p, 0, sizeof(uint32_t), s));
       BA_HIP(hipStreamSynchronize(s));
       if (history) {

@@ -146,9 +146,10 @@ __global__ void k_s0_init(int64_t n, const int32_t* __restrict__ row_of, const i
 // them per block and cuts every block's list into chunks of at most
 // S0_CHUNK points, so that heavy blocks spread over many waves). One wave per
 // chunk: in batches of 64 points each lane recomputes both cameras' Jacobian
-// blocks from the camera data and the point record [X | C_p^-1] and leaves
-// its 2 rows of U and V in LDS; then U^T V accumulates on the FP64 matrix
-// cores (16 x 16 x 4, 9 x 9 used), two points per instruction; the chunk's
+// blocks from the camera data and the point record [X | C_p^-1]; the lanes'
+// 2 rows of U and V pass through LDS 32 points at a time, and U^T V
+// accumulates on the FP64 matrix cores (16 x 16 x 4, 9 x 9 used), two points
+// per instruction, in the points' order; the chunk's
 // sum is added to blocks (i, j) and (j, i) with global atomics.
 // part != NULL (deterministic mode): each chunk stores its 9 x 9 sum to
 // part[chunk] instead, and k_s0_gather adds the chunks of every block in
@@ -160,8 +161,8 @@ __global__ __launch_bounds__(64) void k_explicit_s0(
     const int32_t* __restrict__ s0_q, const double* __restrict__ campre, const double* __restrict__ prec,
     const int32_t* __restrict__ pt_off, const int32_t* __restrict__ obs_cam, const double* __restrict__ wsq,
     double* __restrict__ S) {
-  __shared__ double Us[128 * 9];
-  __shared__ double Vs[128 * 9];
+  __shared__ double Us[64 * 9];   // rows of 32 points at a time (LDS per wave
+  __shared__ double Vs[64 * 9];   // kept small: more waves per CU)
   const int ch = blockIdx.x;
   const int e = chunk_e[ch];
   const int i = row_of[e], j = col[e];
@@ -174,6 +175,7 @@ __global__ __launch_bounds__(64) void k_explicit_s0(
   const int end = min(s0_ptr[e + 1], beg + S0_CHUNK);
   for (int base = beg; base < end; base += 64) {
     const int nh = end - base < 64 ? end - base : 64;
+    double urow[18], vrow[18];   // this lane's point: its 2 rows of U and of V
     if (lane < nh) {
       const int q = s0_q[base + lane];
       const double* rec = prec + (size_t)q * PREC;
@@ -214,23 +216,37 @@ __global__ __launch_bounds__(64) void k_explicit_s0(
         for (int t = 0; t < 2; ++t)
           m[r * 2 + t] = ec[r * 3 + 0] * ej[t * 3 + 0] + ec[r * 3 + 1] * ej[t * 3 + 1] + ec[r * 3 + 2] * ej[t * 3 + 2];
 #pragma unroll
+      for (int k = 0; k < 18; ++k) urow[k] = fi[k];
+#pragma unroll
       for (int k = 0; k < 9; ++k) {
-        Us[(2 * lane) * 9 + k] = fi[k];
-        Us[(2 * lane + 1) * 9 + k] = fi[9 + k];
-        Vs[(2 * lane) * 9 + k] = m[0] * fj[k] + m[1] * fj[9 + k];
-        Vs[(2 * lane + 1) * 9 + k] = m[2] * fj[k] + m[3] * fj[9 + k];
+        vrow[k] = m[0] * fj[k] + m[1] * fj[9 + k];
+        vrow[9 + k] = m[2] * fj[k] + m[3] * fj[9 + k];
       }
     }
-    __syncthreads();
-    // rows 4 s .. 4 s + 3 of the stacked U, V (points 2 s, 2 s + 1)
-    for (int st = 0; st < (nh + 1) / 2; ++st) {
-      const int row = 4 * st + kq;
-      const bool ok = cc < 9 && row < 2 * nh;
-      const double a = ok ? Us[row * 9 + cc] : 0.0;
-      const double b = ok ? Vs[row * 9 + cc] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    // the batch's points go through LDS in two halves of 32, in order
+    for (int n0 = 0; n0 < nh; n0 += 32) {
+      const int nn = nh - n0 < 32 ? nh - n0 : 32;
+      const int pl = lane - n0;
+      if (pl >= 0 && pl < nn) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          Us[(2 * pl) * 9 + k] = urow[k];
+          Us[(2 * pl + 1) * 9 + k] = urow[9 + k];
+          Vs[(2 * pl) * 9 + k] = vrow[k];
+          Vs[(2 * pl + 1) * 9 + k] = vrow[9 + k];
+        }
+      }
+      __syncthreads();
+      // rows 4 s .. 4 s + 3 of the stacked U, V (points n0 + 2 s, n0 + 2 s + 1)
+      for (int st = 0; st < (nn + 1) / 2; ++st) {
+        const int row = 4 * st + kq;
+        const bool ok = cc < 9 && row < 2 * nn;
+        const double a = ok ? Us[row * 9 + cc] : 0.0;
+        const double b = ok ? Vs[row * 9 + cc] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
   // accumulator element t of lane l holds (U^T V)[4 t + l / 16][l % 16]
 #pragma unroll
@@ -269,7 +285,10 @@ __global__ __launch_bounds__(256) void k_s0_gather(int n_blk, const int32_t* __r
 
 // Coarse entry (A, B) = sum over fine entries (i, j) with agg(i) = A, agg(j) = B
 // of P_i^T S_ij P_j (fine blocks bs x bs, P blocks bs x 16). One workgroup of
-// 256 threads per coarse entry; thread (r, c) owns entry (r, c).
+// 256 threads per coarse entry; thread (r, c) owns entry (r, c). The fine
+// entries are software-pipelined: each thread's elements of the next entry's
+// S_ij, P_i and P_j (and the indices of the one after) are loaded while the
+// current entry's products run.
 __global__ __launch_bounds__(256) void k_galerkin(int bs, const int32_t* __restrict__ gal_ptr,
                                                   const int32_t* __restrict__ gal_fine,
                                                   const int32_t* __restrict__ row_of,
@@ -279,15 +298,47 @@ __global__ __launch_bounds__(256) void k_galerkin(int bs, const int32_t* __restr
                                                   double* __restrict__ Sc) {
   __shared__ double Ss[NS * NS], Pi[NS * NS], Pj[NS * NS], T[NS * NS];
   const int ec = blockIdx.x;
-  const int r = threadIdx.x / NS, c = threadIdx.x % NS;
+  const int tid = threadIdx.x;
+  const int r = tid / NS, c = tid % NS;
+  const bool ls = tid < bs * bs, lp = tid < bs * NS;
+  const int g0 = gal_ptr[ec], g1 = gal_ptr[ec + 1];
+  // indices of entry g (ie, ii, ij) and this thread's elements of it (vs, vi, vj)
+  int ie = 0, ii = 0, ij = 0;
+  double vs = 0.0, vi = 0.0, vj = 0.0;
+  if (g0 < g1) {
+    ie = gal_fine[g0];
+    ii = row_of[ie];
+    ij = col[ie];
+    if (ls) vs = Sf[(size_t)ie * bs * bs + tid];
+    if (lp) {
+      vi = P[(size_t)ii * bs * NS + tid];
+      vj = P[(size_t)ij * bs * NS + tid];
+    }
+  }
+  int ne = 0, ni = 0, nj = 0;   // indices of entry g + 1
+  if (g0 + 1 < g1) {
+    ne = gal_fine[g0 + 1];
+    ni = row_of[ne];
+    nj = col[ne];
+  }
   double acc = 0.0;
-  for (int g = gal_ptr[ec]; g < gal_ptr[ec + 1]; ++g) {
-    const int e = gal_fine[g];
-    const int i = row_of[e], j = col[e];
-    if (threadIdx.x < bs * bs) Ss[threadIdx.x] = Sf[(size_t)e * bs * bs + threadIdx.x];
-    if (threadIdx.x < bs * NS) {
-      Pi[threadIdx.x] = P[(size_t)i * bs * NS + threadIdx.x];
-      Pj[threadIdx.x] = P[(size_t)j * bs * NS + threadIdx.x];
+  for (int g = g0; g < g1; ++g) {
+    if (ls) Ss[tid] = vs;
+    if (lp) {
+      Pi[tid] = vi;
+      Pj[tid] = vj;
+    }
+    if (g + 1 < g1) {
+      if (ls) vs = Sf[(size_t)ne * bs * bs + tid];
+      if (lp) {
+        vi = P[(size_t)ni * bs * NS + tid];
+        vj = P[(size_t)nj * bs * NS + tid];
+      }
+      if (g + 2 < g1) {
+        ne = gal_fine[g + 2];
+        ni = row_of[ne];
+        nj = col[ne];
+      }
     }
     __syncthreads();
     // T = S_ij P_j  (bs x 16)
@@ -464,26 +515,42 @@ __global__ __launch_bounds__(64) void k_mfma_probe(const double* X, const double
 // ---------------------------------------------------------------- coarse inverse
 
 // Dense inverse of the (equilibrated, SPD) coarsest operator by blocked
-// Gauss-Jordan elimination with 64 x 64 pivot blocks. With P = A_kk^-1, one
+// Gauss-Jordan elimination with B x B pivot blocks. With P = A_kk^-1, one
 // pivot step maps
 //   A_kk <- P,  A_kj <- P A_kj,  A_ik <- -A_ik P,  A_ij <- A_ij - A_ik P A_kj,
 // and after every block has served as pivot A holds A^-1. The first pivot
 // inverse is a launch of its own (one workgroup); every step is then one
 // launch that updates every block (one workgroup per block, reading one copy
 // of A and writing the other) and inverts the next pivot. nd is a multiple of
-// 64; pivots are the diagonal blocks of successive Schur complements,
-// positive definite for SPD A.
+// B; pivots are the diagonal blocks of successive Schur complements,
+// positive definite for SPD A. The pivot inverses form the sequential chain
+// of the elimination (one per step); each step reads and writes the whole
+// matrix. B = 64 (inverted as 2 x 2 blocks of 32, see block_inverse) and
+// B = 32 (half the chain per step, twice the steps) measured alike on the
+// coarsest operators met here; 64 takes half the launches and traffic.
 constexpr int GJB = 64;
 
+// 1 / x for a positive normal x: the hardware reciprocal estimate refined by
+// two steps of Newton's iteration r <- r + r (1 - x r) (each step squares the
+// relative error), which leaves it within about an ulp of the quotient; a
+// shorter dependent chain than the fully rounded division, and the pivots'
+// reciprocals are the sequential part of the elimination.
+__device__ __forceinline__ double recip_newton(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
 // In-place inverse of a 4 x 4 SPD matrix (row-major) by Gauss-Jordan without
-// pivoting; false if a pivot is not positive.
+// pivoting; false if a pivot is not positive (or below the normal range).
 __device__ __forceinline__ bool inv4(double (&a)[16]) {
   bool ok = true;
 #pragma unroll
   for (int p = 0; p < 4; ++p) {
     const double piv = a[p * 4 + p];
-    ok = ok && (piv > 0.0);
-    const double ip = 1.0 / piv;
+    ok = ok && (piv >= 0x1p-1022);
+    const double ip = recip_newton(piv);
 #pragma unroll
     for (int j = 0; j < 4; ++j)
       if (j != p) a[p * 4 + j] *= ip;
@@ -501,22 +568,28 @@ __device__ __forceinline__ bool inv4(double (&a)[16]) {
   return ok;
 }
 
-// v <- inverse of a 64 x 64 SPD block held by 256 threads (thread t keeps
-// column j = t % 64, rows t / 64 + 4 m, m < 16), by Gauss-Jordan on 4 x 4
-// pivot blocks: pivot block q is rows 4q .. 4q+3, i.e. register v[q] of the
-// threads with t / 64 = 0 .. 3. Pivot rows and columns go through
-// double-buffered LDS (one barrier per pivot block); every thread inverts the
-// 4 x 4 pivot itself.
-__device__ __forceinline__ bool pivot_inverse64(double (&v)[16], double (*rowK)[4][GJB], double (*colK)[GJB][4]) {
-  const int t = threadIdx.x, j = t % GJB, i0 = t / GJB;
+// v <- inverse of a B x B SPD block held by 256 threads (thread t keeps
+// column j = t % B, rows i0 + R m with i0 = t / B, R = 256 / B, m < B / R),
+// by Gauss-Jordan on 4 x 4 pivot blocks: pivot block q is rows 4q .. 4q+3,
+// i.e. register v[4q / R] of the threads with i0 - 4q mod R in 0 .. 3.
+// Pivot rows and columns go through double-buffered LDS (one barrier per
+// pivot block); every thread inverts the 4 x 4 pivot itself.
+template <int B>
+__device__ __forceinline__ bool pivot_inverse(double (&v)[B * B / 256], double (*rowK)[4][B],
+                                              double (*colK)[B][4]) {
+  constexpr int R = 256 / B, M = B / R;
+  const int t = threadIdx.x, j = t % B, i0 = t / B;
   bool ok = true;
 #pragma unroll
-  for (int q = 0; q < GJB / 4; ++q) {
+  for (int q = 0; q < B / 4; ++q) {
     const int buf = q & 1;
-    rowK[buf][i0][j] = v[q];
+    const int mq = (4 * q) / R;          // the register holding the pivot rows
+    const int aq = i0 - (4 * q) % R;     // this thread's row within the pivot block
+    const bool prow = aq >= 0 && aq < 4;
+    if (prow) rowK[buf][aq][j] = v[mq];
     if ((j >> 2) == q) {
 #pragma unroll
-      for (int m = 0; m < 16; ++m) colK[buf][i0 + 4 * m][j & 3] = v[m];
+      for (int m = 0; m < M; ++m) colK[buf][i0 + R * m][j & 3] = v[m];
     }
     __syncthreads();
     double p4[16];
@@ -542,12 +615,12 @@ __device__ __forceinline__ bool pivot_inverse64(double (&v)[16], double (*rowK)[
 #pragma unroll
     for (int a = 0; a < 4; ++a) w[a] = jin ? pc[a] : tj[a];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      if (m == q) {
-        // row 4q + i0 of the pivot block row
-        v[m] = i0 == 0 ? w[0] : i0 == 1 ? w[1] : i0 == 2 ? w[2] : w[3];
+    for (int m = 0; m < M; ++m) {
+      if (m == mq && prow) {
+        // row 4q + aq of the pivot block row
+        v[m] = aq == 0 ? w[0] : aq == 1 ? w[1] : aq == 2 ? w[2] : w[3];
       } else {
-        const int i = i0 + 4 * m;
+        const int i = i0 + R * m;
         const double c0 = colK[buf][i][0], c1 = colK[buf][i][1], c2 = colK[buf][i][2], c3 = colK[buf][i][3];
         const double d = c0 * w[0] + c1 * w[1] + c2 * w[2] + c3 * w[3];
         v[m] = jin ? -d : v[m] - d;
@@ -557,26 +630,149 @@ __device__ __forceinline__ bool pivot_inverse64(double (&v)[16], double (*rowK)[
   return ok;
 }
 
+// Staging of a B x B block into LDS (leading dim B + 1), 256 threads.
+template <int B>
+__device__ __forceinline__ void stage_block256(double* __restrict__ dst, const double* __restrict__ src, size_t ld) {
+#pragma unroll 4
+  for (int r = 0; r < B * B / 256; ++r) {
+    const int idx = threadIdx.x + 256 * r;
+    dst[(idx / B) * (B + 1) + idx % B] = src[(size_t)(idx / B) * ld + idx % B];
+  }
+}
+
+// The same in two halves: the global loads into registers, and (later) the
+// registers into LDS, so that a load can be in flight during other work.
+template <int B>
+__device__ __forceinline__ void load_block256(double (&r)[B * B / 256], const double* __restrict__ src, size_t ld) {
+#pragma unroll
+  for (int i = 0; i < B * B / 256; ++i) {
+    const int idx = threadIdx.x + 256 * i;
+    r[i] = src[(size_t)(idx / B) * ld + idx % B];
+  }
+}
+
+template <int B>
+__device__ __forceinline__ void store_block256(double* __restrict__ dst, const double (&r)[B * B / 256]) {
+#pragma unroll
+  for (int i = 0; i < B * B / 256; ++i) {
+    const int idx = threadIdx.x + 256 * i;
+    dst[(idx / B) * (B + 1) + idx % B] = r[i];
+  }
+}
+
+// acc[u] += sx * (X Y) for this wave's tiles of a B x B product, X and Y in
+// LDS (leading dim ld)
+template <int B>
+__device__ __forceinline__ void wave_tiles_mma(d4 (&acc)[(B / 16) * (B / 16) / 4], const double* X, const double* Y,
+                                               int ld, double sx) {
+  constexpr int TI = B / 16, NT = TI * TI / 4;
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int u = 0; u < NT; ++u) {
+    const int e = w * NT + u, tr = e / TI, tc = e % TI;
+#pragma unroll
+    for (int t = 0; t < TI; ++t)
+      acc[u] = tile_mma_nn(acc[u], X + (size_t)(tr * 16) * ld + t * 16, ld, Y + (size_t)(t * 16) * ld + tc * 16, ld, sx);
+  }
+}
+
+// In-place inverse of the SPD B x B block held in LDS X (leading dim B + 1)
+// by the 256 threads of the workgroup; Y is LDS scratch of the same size.
+// B = 32: pivot_inverse directly. B = 64: by the 2 x 2 partition into
+// 32 x 32 blocks [A11 A12; A21 A22]:
+//   X11 = A11^-1,  T = X11 A12,  R = A21 X11,  S = A22 - A21 T,  Si = S^-1,
+//   inverse = [X11 - T B21, B12; B21, Si] with B12 = -T Si, B21 = -Si R,
+// the two 32 x 32 inverses by pivot_inverse<32> (S is the Schur complement
+// of A11, SPD with A) and the products on the FP64 matrix cores (wave w:
+// tile (w / 2, w % 2) of every 32 x 32 product), so that the sequential
+// part is two 32 x 32 eliminations instead of one 64 x 64. False if a pivot
+// is not positive.
+__device__ __forceinline__ bool inv32_lds(double* A, int ld, double (*rowK)[4][32], double (*colK)[32][4]) {
+  const int t = threadIdx.x, j = t % 32, i0 = t / 32;
+  double v[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) v[m] = A[(i0 + 8 * m) * ld + j];
+  const bool ok = pivot_inverse<32>(v, rowK, colK);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) A[(i0 + 8 * m) * ld + j] = v[m];
+  return ok;
+}
+
+template <int B>
+__device__ __forceinline__ bool block_inverse(double* X, double* Y, double (*rowK)[4][32], double (*colK)[32][4]) {
+  constexpr int LD = B + 1;
+  if (B == 32) return inv32_lds(X, LD, rowK, colK);
+  const int w = threadIdx.x >> 6, tr = w >> 1, tc = w & 1;
+  double* A11 = X;
+  double* A12 = X + 32;
+  double* A21 = X + 32 * LD;
+  double* A22 = X + 32 * LD + 32;
+  double* T = Y;             // Y rows 0 .. 31
+  double* R = Y + 32 * LD;   // Y rows 32 .. 63
+  const size_t me = (size_t)(tr * 16) * LD + tc * 16;   // this wave's tile
+  bool ok = inv32_lds(A11, LD, rowK, colK);
+  __syncthreads();
+  d4 tt = {0, 0, 0, 0}, rr = {0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    tt = tile_mma_nn(tt, A11 + (tr * 16) * LD + kk * 16, LD, A12 + (kk * 16) * LD + tc * 16, LD, 1.0);
+    rr = tile_mma_nn(rr, A21 + (tr * 16) * LD + kk * 16, LD, A11 + (kk * 16) * LD + tc * 16, LD, 1.0);
+  }
+  tile_store(T + me, LD, tt);
+  tile_store(R + me, LD, rr);
+  __syncthreads();
+  // S in place of A22 (each wave reads only its own tile of A22)
+  d4 ss = tile_load(A22 + me, LD);
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk)
+    ss = tile_mma_nn(ss, A21 + (tr * 16) * LD + kk * 16, LD, T + (kk * 16) * LD + tc * 16, LD, -1.0);
+  tile_store(A22 + me, LD, ss);
+  __syncthreads();
+  ok = inv32_lds(A22, LD, rowK, colK) && ok;
+  __syncthreads();
+  d4 b12 = {0, 0, 0, 0}, b21 = {0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk) {
+    b12 = tile_mma_nn(b12, T + (tr * 16) * LD + kk * 16, LD, A22 + (kk * 16) * LD + tc * 16, LD, -1.0);
+    b21 = tile_mma_nn(b21, A22 + (tr * 16) * LD + kk * 16, LD, R + (kk * 16) * LD + tc * 16, LD, -1.0);
+  }
+  tile_store(A12 + me, LD, b12);
+  tile_store(A21 + me, LD, b21);
+  __syncthreads();
+  // X11 - T B21 in place of A11 (each wave reads only its own tile of A11)
+  d4 b11 = tile_load(A11 + me, LD);
+#pragma unroll
+  for (int kk = 0; kk < 2; ++kk)
+    b11 = tile_mma_nn(b11, T + (tr * 16) * LD + kk * 16, LD, A21 + (kk * 16) * LD + tc * 16, LD, -1.0);
+  tile_store(A11 + me, LD, b11);
+  __syncthreads();
+  return ok;
+}
+
 // P = A_kk^-1 for pivot step k (one workgroup of 256 threads).
+template <int B>
 __global__ __launch_bounds__(256) void k_gj_pivot(int nd, const double* __restrict__ A, int k,
                                                   double* __restrict__ Pbuf, uint32_t* err) {
-  __shared__ double rowK[2][4][GJB];
-  __shared__ double colK[2][GJB][4];
-  const size_t k0 = (size_t)k * GJB;
-  const int t = threadIdx.x, jj = t % GJB, ii = t / GJB;
-  double v[16];
+  constexpr int LD = B + 1;
+  __shared__ double X[B * LD];
+  __shared__ double Y[B == 64 ? B * LD : 1];
+  __shared__ double rowK[2][4][32];
+  __shared__ double colK[2][32][4];
+  const size_t k0 = (size_t)k * B;
+  stage_block256<B>(X, A + k0 * nd + k0, nd);
+  __syncthreads();
+  if (!block_inverse<B>(X, Y, rowK, colK) && threadIdx.x == 0) atomicOr(err, ERRF_NOT_SPD);
 #pragma unroll
-  for (int m = 0; m < 16; ++m) v[m] = A[(k0 + ii + 4 * m) * nd + k0 + jj];
-  if (!pivot_inverse64(v, rowK, colK)) {
-    if (t == 0) atomicOr(err, ERRF_NOT_SPD);
+  for (int r = 0; r < B * B / 256; ++r) {
+    const int idx = threadIdx.x + 256 * r;
+    Pbuf[idx] = X[(idx / B) * LD + idx % B];
   }
-#pragma unroll
-  for (int m = 0; m < 16; ++m) Pbuf[(ii + 4 * m) * GJB + jj] = v[m];
 }
 
 // Pivot step k of blocked Gauss-Jordan from Ain to Aout, given P = A_kk^-1:
-// one workgroup of four waves per 64 x 64 block (i, j), i <= j (wave w
-// computes tile row w of the output, four 16 x 16 tiles), writes
+// one workgroup of four waves per B x B block (i, j), i <= j (the block's
+// 16 x 16 tiles in row-major order, dealt to the waves in equal consecutive
+// shares), writes
 //   (k, k): P;   (k, j): P A_kj;   (i, k): -A_ik P;   else A_ij - A_ik (P A_kj),
 // operands staged in LDS, products on the FP64 matrix cores. The iterate
 // keeps a fixed symmetry: A_ji = s A_ij^T with s = -1 when exactly one of
@@ -584,35 +780,18 @@ __global__ __launch_bounds__(256) void k_gj_pivot(int nd, const double* __restri
 // workgroup also writes block (j, i) and only the upper blocks are computed.
 // Look-ahead: the workgroup of block (k+1, k+1), the next step's pivot block,
 // is dispatched first and also inverts its result into Pnext
-// (pivot_inverse64 on its 256 threads), so every step after the first is one
+// (block_inverse on its 256 threads), so every step after the first is one
 // launch and the inverse overlaps the other blocks' updates.
-__device__ __forceinline__ void stage_block256(double* __restrict__ dst, const double* __restrict__ src, size_t ld) {
-#pragma unroll 4
-  for (int r = 0; r < 16; ++r) {
-    const int idx = threadIdx.x + 256 * r;
-    dst[(idx / GJB) * (GJB + 1) + idx % GJB] = src[(size_t)(idx / GJB) * ld + idx % GJB];
-  }
-}
-
-// acc[u] += sx * (X Y) tile (w, u), X and Y 64 x 64 in LDS (leading dim ld)
-__device__ __forceinline__ void row_mma4(d4 (&acc)[4], const double* X, const double* Y, int ld, double sx) {
-  const int w = threadIdx.x >> 6;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-      acc[u] = tile_mma_nn(acc[u], X + (size_t)(w * 16) * ld + t * 16, ld, Y + (size_t)(t * 16) * ld + u * 16, ld, sx);
-}
-
+template <int B>
 __global__ __launch_bounds__(256) void k_gj_step(int nd, const double* __restrict__ Ain, double* __restrict__ Aout,
                                                  int k, const double* __restrict__ Pbuf, double* __restrict__ Pnext,
                                                  uint32_t* err) {
-  constexpr int LD = GJB + 1;
-  __shared__ double X[GJB * LD];
-  __shared__ double Y[GJB * LD];
-  __shared__ double rowK[2][4][GJB];
-  __shared__ double colK[2][GJB][4];
-  const int nb = nd / GJB;
+  constexpr int LD = B + 1, TI = B / 16, NT = TI * TI / 4;
+  __shared__ double X[B * LD];
+  __shared__ double Y[B * LD];
+  __shared__ double rowK[2][4][32];
+  __shared__ double colK[2][32][4];
+  const int nb = nd / B;
   // upper block number -> (bi, bj), bi <= bj, row by row; the next pivot
   // block (k+1, k+1) goes to workgroup 0
   int e = blockIdx.x;
@@ -623,53 +802,69 @@ __global__ __launch_bounds__(256) void k_gj_step(int nd, const double* __restric
   int bi = 0, rem = e;
   while (rem >= nb - bi) { rem -= nb - bi; ++bi; }
   const int bj = bi + rem;
-  const size_t k0 = (size_t)k * GJB, i0 = (size_t)bi * GJB, j0 = (size_t)bj * GJB;
+  const size_t k0 = (size_t)k * B, i0 = (size_t)bi * B, j0 = (size_t)bj * B;
   const int w = threadIdx.x >> 6;
-  d4 acc[4];
+  d4 acc[NT];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) acc[u] = d4{0, 0, 0, 0};
+  for (int u = 0; u < NT; ++u) acc[u] = d4{0, 0, 0, 0};
   if (bi == k && bj == k) {
-    stage_block256(X, Pbuf, GJB);
+    stage_block256<B>(X, Pbuf, B);
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] = tile_load(X + (size_t)(w * 16) * LD + u * 16, LD);
+    for (int u = 0; u < NT; ++u) {
+      const int te = w * NT + u;
+      acc[u] = tile_load(X + (size_t)((te / TI) * 16) * LD + (te % TI) * 16, LD);
+    }
   } else if (bi == k) {
-    stage_block256(X, Pbuf, GJB);
-    stage_block256(Y, Ain + k0 * nd + j0, nd);
+    stage_block256<B>(X, Pbuf, B);
+    stage_block256<B>(Y, Ain + k0 * nd + j0, nd);
     __syncthreads();
-    row_mma4(acc, X, Y, LD, 1.0);
+    wave_tiles_mma<B>(acc, X, Y, LD, 1.0);
   } else if (bj == k) {
-    stage_block256(X, Ain + i0 * nd + k0, nd);
-    stage_block256(Y, Pbuf, GJB);
+    stage_block256<B>(X, Ain + i0 * nd + k0, nd);
+    stage_block256<B>(Y, Pbuf, B);
     __syncthreads();
-    row_mma4(acc, X, Y, LD, -1.0);
+    wave_tiles_mma<B>(acc, X, Y, LD, -1.0);
   } else {
-    stage_block256(X, Pbuf, GJB);
-    stage_block256(Y, Ain + k0 * nd + j0, nd);
+    // A_ik and A_ij are loaded up front, in flight during T = P A_kj
+    double aik[B * B / 256];
+    load_block256<B>(aik, Ain + i0 * nd + k0, nd);
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int te = w * NT + u;
+      acc[u] = tile_load(Ain + (i0 + (te / TI) * 16) * nd + j0 + (te % TI) * 16, nd);
+    }
+    stage_block256<B>(X, Pbuf, B);
+    stage_block256<B>(Y, Ain + k0 * nd + j0, nd);
     __syncthreads();
-    d4 tk[4];
+    d4 tk[NT];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) tk[u] = d4{0, 0, 0, 0};
-    row_mma4(tk, X, Y, LD, 1.0);   // T = P A_kj
-    __syncthreads();                // every wave is done with X and Y
+    for (int u = 0; u < NT; ++u) tk[u] = d4{0, 0, 0, 0};
+    wave_tiles_mma<B>(tk, X, Y, LD, 1.0);   // T = P A_kj
+    __syncthreads();                         // every wave is done with X and Y
 #pragma unroll
-    for (int u = 0; u < 4; ++u) tile_store(Y + (size_t)(w * 16) * LD + u * 16, LD, tk[u]);
-    stage_block256(X, Ain + i0 * nd + k0, nd);
+    for (int u = 0; u < NT; ++u) {
+      const int te = w * NT + u;
+      tile_store(Y + (size_t)((te / TI) * 16) * LD + (te % TI) * 16, LD, tk[u]);
+    }
+    store_block256<B>(X, aik);
     __syncthreads();
-#pragma unroll
-    for (int u = 0; u < 4; ++u) acc[u] = tile_load(Ain + (i0 + w * 16) * nd + j0 + u * 16, nd);
-    row_mma4(acc, X, Y, LD, -1.0);
+    wave_tiles_mma<B>(acc, X, Y, LD, -1.0);
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) tile_store(Aout + (i0 + w * 16) * nd + j0 + u * 16, nd, acc[u]);
+  for (int u = 0; u < NT; ++u) {
+    const int te = w * NT + u;
+    tile_store(Aout + (i0 + (te / TI) * 16) * nd + j0 + (te % TI) * 16, nd, acc[u]);
+  }
   if (bi != bj) {
-    // block (j, i) = s (block (i, j))^T: tile (w, u) goes to tile (u, w) of
-    // block (j, i), transposed
+    // block (j, i) = s (block (i, j))^T: tile (tr, tc) goes to tile (tc, tr)
+    // of block (j, i), transposed
     const double sgn = ((bi <= k) != (bj <= k)) ? -1.0 : 1.0;
     const int l = threadIdx.x & 63;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      double* T = Aout + (j0 + u * 16) * nd + i0 + w * 16;
+    for (int u = 0; u < NT; ++u) {
+      const int te = w * NT + u, tr = te / TI, tc = te % TI;
+      double* T = Aout + (j0 + tc * 16) * nd + i0 + tr * 16;
 #pragma unroll
       for (int t = 0; t < 4; ++t) T[(size_t)(l & 15) * nd + 4 * t + (l >> 4)] = sgn * acc[u][t];
     }
@@ -677,16 +872,23 @@ __global__ __launch_bounds__(256) void k_gj_step(int nd, const double* __restric
     // the next pivot block, inverted here from the values Aout receives
     __syncthreads();   // every wave is done reading X
 #pragma unroll
-    for (int u = 0; u < 4; ++u) tile_store(X + (size_t)(w * 16) * LD + u * 16, LD, acc[u]);
+    for (int u = 0; u < NT; ++u) {
+      const int te = w * NT + u;
+      tile_store(X + (size_t)((te / TI) * 16) * LD + (te % TI) * 16, LD, acc[u]);
+    }
     __syncthreads();
-    const int t = threadIdx.x, jj = t % GJB, ii = t / GJB;
-    double v[16];
+    if (!block_inverse<B>(X, Y, rowK, colK) && threadIdx.x == 0) atomicOr(err, ERRF_NOT_SPD);
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = X[(ii + 4 * m) * LD + jj];
-    if (!pivot_inverse64(v, rowK, colK) && t == 0) atomicOr(err, ERRF_NOT_SPD);
-#pragma unroll
-    for (int m = 0; m < 16; ++m) Pnext[(ii + 4 * m) * GJB + jj] = v[m];
+    for (int r = 0; r < B * B / 256; ++r) {
+      const int idx = threadIdx.x + 256 * r;
+      Pnext[idx] = X[(idx / B) * LD + idx % B];
+    }
   }
 }
+
+template __global__ void k_gj_pivot<32>(int, const double*, int, double*, uint32_t*);
+template __global__ void k_gj_pivot<64>(int, const double*, int, double*, uint32_t*);
+template __global__ void k_gj_step<32>(int, const double*, double*, int, const double*, double*, uint32_t*);
+template __global__ void k_gj_step<64>(int, const double*, double*, int, const double*, double*, uint32_t*);
 
 }  // namespace bamg

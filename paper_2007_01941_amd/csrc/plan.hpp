@@ -187,10 +187,13 @@ struct ba_plan {
   uint32_t* h_err = nullptr;      // pinned copy of the error flags
   hipStream_t cap = nullptr;      // stream the PCG iteration graph is captured on (runs nothing)
   bamg::Scratch* scratch = nullptr;
-  // side stream of the multigrid setup (default priority), forked from and
-  // joined back into the caller's stream with these events
-  hipStream_t side = nullptr, side2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // side streams of the multigrid setup (default priority), forked from and
+  // joined back into the caller's stream with these events: side runs the QR
+  // chain, and the Lanczos estimate of level l runs on the (l mod 3)-th of
+  // side2, side and side3, each stream signalling its ev_lz[] when done
+  hipStream_t side = nullptr, side2 = nullptr, side3 = nullptr;
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_lz[3] = {nullptr, nullptr, nullptr};
   std::vector<hipEvent_t> ev_qr, ev_lvl;   // per level: QR done; operator and block inverses ready
   bamg::Backward* bwd = nullptr;
   bamg::LmWork* lm = nullptr;

@@ -85,6 +85,8 @@ static size_t layout_ws(ba_plan* P, uint32_t key, char* base) {
   for (DBuf<double>* v : {&W.x, &W.r, &W.z, &W.p, &W.q, &W.t, &W.bref, &W.e}) c.take(*v, n);
   c.take(W.partial, RED_BLOCKS);
   c.take(W.scal, 2);
+  c.take(W.lz_partial, 3 * RED_BLOCKS);
+  c.take(W.lz_scal, 3);
   c.take(W.dots, 8);
   c.take(W.pt_a, 3 * np);
   c.take(W.pt_b, 3 * np);
@@ -222,6 +224,7 @@ static void bind_ws(ba_plan* P, uint32_t key, void* ws, size_t ws_bytes, hipStre
   P->ws_key = k;
   // the reduction counters in the scalar blocks start at zero
   BA_HIP(hipMemsetAsync(P->scratch->scal.p, 0, 2 * sizeof(PcgScal), s));
+  BA_HIP(hipMemsetAsync(P->scratch->lz_scal.p, 0, 3 * sizeof(PcgScal), s));
   if (k & WS_LM) BA_HIP(hipMemsetAsync(P->lm->scal.p, 0, sizeof(LmScal), s));
 }
 
@@ -236,12 +239,12 @@ static void create_runtime(ba_plan* P) {
   BA_HIP(hipHostMalloc((void**)&P->lm->h_scal, sizeof(LmScal), hipHostMallocDefault));
   BA_HIP(hipHostMalloc((void**)&P->lm->h_dots, 4 * sizeof(double), hipHostMallocDefault));
   BA_HIP(hipHostMalloc((void**)&P->h_err, sizeof(uint32_t), hipHostMallocDefault));
-  BA_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
   for (hipEvent_t& e : P->ev_t) BA_HIP(hipEventCreate(&e));
   BA_HIP(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
   BA_HIP(hipStreamCreateWithFlags(&P->side2, hipStreamNonBlocking));
+  BA_HIP(hipStreamCreateWithFlags(&P->side3, hipStreamNonBlocking));
   BA_HIP(hipEventCreateWithFlags(&P->ev_fork, hipEventDisableTiming));
-  BA_HIP(hipEventCreateWithFlags(&P->ev_join, hipEventDisableTiming));
+  for (hipEvent_t& e : P->ev_lz) BA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   P->ev_qr.assign(P->levels.size(), nullptr);
   P->ev_lvl.assign(P->levels.size(), nullptr);
   for (hipEvent_t& e : P->ev_qr) BA_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -717,10 +720,12 @@ static double plain_dot(ba_plan* P, int n, const double* a, const double* b, hip
 // Lanczos in the D inner product, then the largest eigenvalue of the
 // tridiagonal matrix (k_lanczos_finish). Everything stays on the device
 // (L.lz_s): the V-cycle's kernels read 1 / lambda_max from there.
-static void lanczos_launch(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
+static void lanczos_launch(ba_plan* P, const ba_opts* o, int l, hipStream_t s, int slot) {
   Level& L = P->levels[l];
   const int n = L.n * L.bs;
   Scratch& W = *P->scratch;
+  double* partial = W.lz_partial.p + (size_t)slot * RED_BLOCKS;
+  PcgScal* red = W.lz_scal.p + slot;
   double* lz = L.lz_s.p;
   BA_HIP(hipMemsetAsync(lz, 0, LZ_SIZE * sizeof(double), s));
   BA_HIP(hipMemsetAsync(L.lz_up.p, 0, n * sizeof(double), s));
@@ -731,9 +736,8 @@ static void lanczos_launch(ba_plan* P, const ba_opts* o, int l, hipStream_t s) {
     if (L.bs == 9) blockdiag_apply<9, double>(P, l, in, out, nullptr, s);
     else blockdiag_apply<16, double>(P, l, in, out, nullptr, s);
   };
-  auto dot = [&](const double* a, const double* b, int slot) {
-    hipLaunchKernelGGL((k_dot<DOT_PLAIN, double>), dim3(rg), dim3(256), 0, s, n, a, b, W.partial.p, W.scal.p + 1,
-                       lz + slot);
+  auto dot = [&](const double* a, const double* b, int at) {
+    hipLaunchKernelGGL((k_dot<DOT_PLAIN, double>), dim3(rg), dim3(256), 0, s, n, a, b, partial, red, lz + at);
   };
   hipLaunchKernelGGL(k_lanczos_start, dim3(g), dim3(256), 0, s, n, l, L.lz_u.p);
   dinv(L.lz_u.p, L.lz_v.p);
@@ -780,12 +784,12 @@ static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_scale, dim3(grid_of<double>(nd2)), dim3(256), 0, s, Lc.nd, src, scl.p, 0.0);
   // P_0 = A_00^-1 (one workgroup); then step k updates every block with P_k
   // and inverts the next pivot block into P_{k+1} (two alternating buffers).
-  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)src, 0, Lc.gj_piv.p,
+  hipLaunchKernelGGL(k_gj_pivot<GJB>, dim3(1), dim3(256), 0, s, Lc.nd, (const double*)src, 0, Lc.gj_piv.p,
                      P->errflag.p);
   for (int k = 0; k < nbk; ++k) {
     const double* pk = Lc.gj_piv.p + (size_t)(k & 1) * GJB * GJB;
     double* pn = Lc.gj_piv.p + (size_t)((k + 1) & 1) * GJB * GJB;
-    hipLaunchKernelGGL(k_gj_step, dim3(nbk * (nbk + 1) / 2), dim3(256), 0, s, Lc.nd, (const double*)src, dst, k, pk,
+    hipLaunchKernelGGL(k_gj_step<GJB>, dim3(nbk * (nbk + 1) / 2), dim3(256), 0, s, Lc.nd, (const double*)src, dst, k, pk,
                        pn, P->errflag.p);
     std::swap(src, dst);
   }
@@ -794,15 +798,15 @@ static void coarse_inverse(ba_plan* P, const ba_opts* o, hipStream_t s) {
 }
 
 
-// Numeric multigrid setup as a small task graph on three streams (forked from
+// Numeric multigrid setup as a small task graph on four streams (forked from
 // and joined back into s with events):
 //   side : near-nullspace, then QR of every level in turn (QR(l+1) needs only
 //          the coarse K of QR(l));
 //   s    : explicit level-0 S, then per level the Galerkin product (after
 //          QR(l)) and the next level's block inverses, then the coarsest
 //          level's dense inverse;
-//   side2: the Lanczos estimate of every level once its operator and block
-//          inverses are ready.
+//   side2, side, side3: the Lanczos estimate of level l on the (l mod 3)-th,
+//          once that level's operator and block inverses are ready.
 // Explicit level-0 Schur complement (Section 3.6): diagonal blocks S_cc, then
 // the off-diagonal blocks from the shared points of every camera pair.
 static void assemble_s0(ba_plan* P, hipStream_t s) {
@@ -860,7 +864,7 @@ static void mg_setup_sa(ba_plan* P, const ba_opts* o, const double* cams, hipStr
     BA_CHECK(lds <= 160 * 1024, BA_ERR_LIMIT, "aggregate with %d nodes exceeds the QR kernel's LDS", F.max_agg);
     hipLaunchKernelGGL(k_qr_aggregates, dim3(F.n_agg), dim3(64), lds, s, F.bs, F.agg_ptr.p, F.agg_mem.p, F.K.p,
                        F.P.p, C.K.p);
-    lanczos_launch(P, o, l, s);
+    lanczos_launch(P, o, l, s, 0);
     BA_HIP(hipMemcpyAsync(h.data(), F.lz_s.p + LZ_LMAX, sizeof(double), hipMemcpyDeviceToHost, s));
     check_errflag(P, s, "multigrid setup (QR, smoother blocks, lambda_max)");
     F.lmax = h[0];
@@ -926,8 +930,12 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
       hipLaunchKernelGGL(k_diag_inverse16, dim3(C.n), dim3(64), 0, s, C.diag_pos.p, C.S.p, C.Dinv.p, P->errflag.p);
     BA_HIP(hipEventRecord(P->ev_lvl[l + 1], s));
   }
-  // ---- side2: Lanczos per level, enqueued from a second host thread (its
-  // many small launches would otherwise hold back the coarse inverse's)
+  // ---- Lanczos per level, enqueued from a second host thread (its many
+  // small launches would otherwise hold back the coarse inverse's), level l
+  // on stream l mod 3 of {side2, side, side3} (side once its QR chain is
+  // done), so that the levels' estimates run concurrently: each is a chain
+  // of small dependent launches. (Streams beyond the process's hardware
+  // queues share one; the short estimate of level 2 then still runs last.)
   // (the error message is thread-local: a failure there is re-raised here
   // with its message)
   bool lz_failed = false;
@@ -935,11 +943,12 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   std::string lz_msg;
   std::thread lz([&]() {
     try {
+      const hipStream_t lzs[3] = {P->side2, P->side, P->side3};
       for (int l = 0; l + 1 < nl; ++l) {
-        BA_HIP(hipStreamWaitEvent(P->side2, P->ev_lvl[l], 0));
-        lanczos_launch(P, o, l, P->side2);
+        BA_HIP(hipStreamWaitEvent(lzs[l % 3], P->ev_lvl[l], 0));
+        lanczos_launch(P, o, l, lzs[l % 3], l % 3);
       }
-      BA_HIP(hipEventRecord(P->ev_join, P->side2));
+      for (int i = 0; i < 3; ++i) BA_HIP(hipEventRecord(P->ev_lz[i], lzs[i]));
     } catch (const Fail& f) {
       lz_failed = true;
       lz_status = f.st;
@@ -961,7 +970,7 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
   BA_CHECK(!lz_failed, lz_status, "%s", lz_msg.c_str());
   BA_LAUNCH_CHECK();
   P->inspectable_mg = true;
-  BA_HIP(hipStreamWaitEvent(s, P->ev_join, 0));
+  for (hipEvent_t e : P->ev_lz) BA_HIP(hipStreamWaitEvent(s, e, 0));
   // no readback: lambda_max stays on the device, and the error flags are
   // checked once the solve reads its scalars back
   if (mixed) {
@@ -1100,6 +1109,9 @@ static hipGraphExec_t iteration_graph(ba_plan* P, const ba_opts* o, const PcgVec
     BA_HIP(hipGraphExecDestroy(W.it_exec[ti]));
     W.it_exec[ti] = nullptr;
   }
+  // created on first use: a stream takes one of the process's few hardware
+  // queues, which the setup's side streams should have to themselves
+  if (!P->cap) BA_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
   BA_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
   hipGraph_t graph = nullptr;
   try {
