@@ -58,15 +58,29 @@ def kernel_bytes(n_obs, n_pt, n_cam, s):
     return n_obs * (24 * s + 4) + n_pt * (6 * s + 4) + n_cam * 27 * s
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def kernel_flops_rc(n_obs, n_pt):
+    """FP64 operations of one launch of the FP64 tile kernel, which recomputes
+    F_o and E_o: per observation the projection and its Jacobian blocks (148:
+    camera transform 18, 1/z, projection and distortion 12, d pi / d x_cam 27,
+    E_o 30, F_o's rotation columns 48, its intrinsic columns 12) and the
+    product (94: F x 36, E^T s 9, the point sum 3, E u 10, F^T w 27, the camera
+    sum 9); per point C_p^-1 z (15)."""
+    return n_obs * (148 + 94) + n_pt * 15
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("schur_kernels.hip", "common.hpp", "layout.cpp"):   # layout.cpp groups the tiles
+    # layout.cpp groups the tiles; step_kernels.hip holds the projection the FP64 kernel recomputes
+    for f in ("schur_kernels.hip", "common.hpp", "layout.cpp", "step_kernels.hip"):
         h.update(open(os.path.join(ROOT, "paper_2007_01941_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
 def read_traffic(scene, prec):
-    """HBM bytes per launch of k_schur_groups<prec> on `scene` from the committed
+    """HBM bytes per launch of the tile kernel of `prec` on `scene` from the committed
     rocprofv3 counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a copy
     kernel), if it was taken on the current kernel source; else None."""
     path = os.path.join(PROFILE_DIR, f"k_schur_groups_{scene}_traffic.txt")
@@ -139,13 +153,26 @@ def measure_products(bamg, plan, sc, cams, pts, uv, base, reps=50):
         tk = time_launches(lambda: plan.schur_offdiag_apply(x, y, mode), reps)
         Bk = kernel_bytes(sc.n_obs, sc.n_pt, sc.n_cam, s)
         a = Bk / tk / 1e9
-        kname = "double" if prec == "fp64" else "float"
-        roof[prec] = {"kernel": f"k_schur_groups<{kname}>: y -= W C^-1 W^T x (implicit Schur product)",
-                      "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                      "frac": a / HBM_PEAK_GBPS, "traffic": read_traffic(sc.name, prec),
-                      "algorithmic_bytes": Bk, "s_per_launch": tk}
+        if prec == "fp64":
+            # F_o and E_o are recomputed, not read: the GB/s are the method's bytes B over the
+            # time (what a kernel streaming the stored blocks would have to reach), `traffic` the
+            # bytes the counters see move, and `alu` the FP64 arithmetic against the vector peak
+            fl = kernel_flops_rc(sc.n_obs, sc.n_pt)
+            roof[prec] = {"kernel": "k_schur_groups_rc<double>: y -= W C^-1 W^T x, F_o and E_o recomputed "
+                                    "(implicit Schur product)",
+                          "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                          "frac": a / HBM_PEAK_GBPS, "traffic": read_traffic(sc.name, prec),
+                          "algorithmic_bytes": Bk, "s_per_launch": tk,
+                          "alu": {"achieved": fl / tk / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                  "frac": fl / tk / 1e12 / FP64_VECTOR_PEAK_TFLOPS, "flops": fl}}
+        else:
+            roof[prec] = {"kernel": "k_schur_groups<float>: y -= W C^-1 W^T x (implicit Schur product)",
+                          "bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                          "frac": a / HBM_PEAK_GBPS, "traffic": read_traffic(sc.name, prec),
+                          "algorithmic_bytes": Bk, "s_per_launch": tk}
         log(f"[bench] {sc.name} Schur product {prec}: {t * 1e6:.1f} us/apply ({B / t / 1e9:.0f} GB/s); "
-            f"tile kernel {tk * 1e6:.1f} us/launch, {a:.0f} GB/s = {a / HBM_PEAK_GBPS:.3f} of peak")
+            f"tile kernel {tk * 1e6:.1f} us/launch, {a:.0f} GB/s = {a / HBM_PEAK_GBPS:.3f} of peak"
+            + (f", {roof[prec]['alu']['achieved']:.1f} TFLOP/s FP64" if prec == "fp64" else ""))
     return mat, roof
 
 
@@ -228,7 +255,7 @@ def run_leg(bamg, name, cache, steps, warmup):
 
 def kernel_only(bamg, name, cache, reps):
     """Only the tile kernel, for counter collection: reps launches of
-    k_schur_groups<double>, then of k_schur_groups<float>, on `name`."""
+    k_schur_groups_rc<double>, then of k_schur_groups<float>, on `name`."""
     import torch
     from scenes import cached_scene
     sc = cached_scene(name, cache)
@@ -237,7 +264,7 @@ def kernel_only(bamg, name, cache, reps):
     plan = bamg.Plan(sc.n_cam, sc.n_pt, oc, op, bamg.Options(precond="bj", **base))
     x = torch.randn(sc.n_cam, 9, dtype=torch.float64, device="cuda:0")
     y = torch.zeros_like(x)
-    out = {"scene": name, "reps": reps}
+    out = {"scene": name, "reps": reps, "n_obs": int(sc.n_obs), "n_pt": int(sc.n_pt), "n_cam": int(sc.n_cam)}
     for prec, mode, s in (("fp64", "fp64", 8), ("fp32", "mixed", 4)):
         plan.prepare(cams, pts, uv, opts=bamg.Options(precond="bj", precision=mode, **base))
         torch.cuda.synchronize()
