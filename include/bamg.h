@@ -272,7 +272,9 @@ ba_status ba_schur_apply(ba_plan* p, int32_t precision, const double* x, double*
 
 /* y <- y - W C^-1 W^T x with W = F^T E: the point-elimination term of the
  * Schur complement S = A - W C^-1 W^T (Section 2.1) alone, as one kernel
- * launch (the implicit product of Section 3.6 without its A x part).
+ * launch (the implicit product of Section 3.6 without its A x part; in
+ * FP64 it recomputes F and E from the prepared cameras and points rather
+ * than reading them, with the same arithmetic as the stored blocks).
  * x [n_cam][9] is read, y [n_cam][9] is read and updated. precision as for
  * ba_schur_apply. Enqueued on `stream`; returns without waiting. */
 ba_status ba_schur_offdiag_apply(ba_plan* p, int32_t precision, const double* x, double* y,
