@@ -72,10 +72,16 @@ def kernel_flops_rc(n_obs, n_pt):
 
 
 def kernel_source_hash():
+    """Hash of the sources the tile kernels are built from: their file, the
+    layout constants, the plan code that groups the tiles, and the projection
+    (in step_kernels.hip) that the FP64 kernel recomputes."""
     h = hashlib.sha256()
-    # layout.cpp groups the tiles; step_kernels.hip holds the projection the FP64 kernel recomputes
-    for f in ("schur_kernels.hip", "common.hpp", "layout.cpp", "step_kernels.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2007_01941_amd", "csrc", f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2007_01941_amd", "csrc")
+    for f in ("schur_kernels.hip", "common.hpp", "layout.cpp"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    step = open(os.path.join(csrc, "step_kernels.hip"), "rb").read()
+    i = step.index(b"__device__ __forceinline__ void project_jacobian(")
+    h.update(step[i:step.index(b"\n}\n", i) + 3])
     return h.hexdigest()[:16]
 
 

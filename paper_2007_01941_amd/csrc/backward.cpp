@@ -8,7 +8,7 @@ static ba_status backward(ba_plan* P, const ba_opts* o, const double* cams, cons
                           const double* gd_pt, double* g_cams, double* g_pts, double* g_uv, ba_stats* st,
                           hipStream_t s) {
   if (st) std::memset(st, 0, sizeof(*st));
-  prepare(P, o, cams, pts, uv, D, st, s);
+  prepare(P, o, cams, pts, uv, D, st, s, true);   // the adjoint kernels read the planes
   Scratch& W = *P->scratch;
   Backward& B = *P->bwd;
   Timer ts(s);
@@ -21,8 +21,9 @@ static ba_status backward(ba_plan* P, const ba_opts* o, const double* cams, cons
   const ba_status status = solve_camera_system(P, o, W.bref.p, st, s);
   // mu_p = C^-1 (gd_p - W^T mu_c), caller order
   hipLaunchKernelGGL(k_recover_tiles, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
-                     P->pt_orig.p, P->obs_cam.p, P->n_obs_pad, P->F.p, P->E.p, P->Cinv.p, W.pt_b.p, 1.0, W.x.p,
-                     B.mu_p.p, P->n_tiles);
+                     P->pt_orig.p, P->obs_cam.p, P->n_obs_pad, (const double*)P->F.p, (const double*)P->E.p,
+                     P->obs_pt.p, (const double*)nullptr, (const double*)nullptr, (const double*)nullptr, P->Cinv.p,
+                     W.pt_b.p, 1.0, W.x.p, B.mu_p.p, P->n_tiles);
   hipLaunchKernelGGL(k_adjoint_obs, dim3(grid_of<double>(P->n_obs)), dim3(256), 0, s, (int)P->n_obs, P->obs_cam.p,
                      P->obs_pt.p, P->obs_orig.p, P->pt_orig.p, P->n_obs_pad, P->F.p, P->E.p, P->fres.p, cams, pts,
                      W.x.p, B.mu_p.p, delta_cam, delta_pt, o->lambda, (D || o->freeze_damping_in_grad) ? 1 : 0, g_uv, B.tcam.p,

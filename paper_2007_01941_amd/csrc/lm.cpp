@@ -68,7 +68,7 @@ static ba_status lm_solve(ba_plan* P, const ba_opts* o_in, const ba_lm_opts* lo,
     ba_stats st{};
     ba_status ss = BA_OK;
     try {
-      prepare(P, &o, cams, pts, uv, nullptr, &st, s);
+      prepare(P, &o, cams, pts, uv, nullptr, &st, s, true);   // the model decrease reads the planes
       ss = solve(P, &o, L.dc.p, L.dp.p, &st, s);
     } catch (const Fail& f) {
       if (f.st != BA_ERR_NOT_SPD) throw;

@@ -983,8 +983,12 @@ static void mg_setup(ba_plan* P, const ba_opts* o, const double* cams, bool mixe
 
 // ---------------------------------------------------------------- prepare
 
+// planes: also write the FP64 observation planes F and E (the adjoint and the
+// LM loop's model read them); the step itself recomputes the blocks where it
+// needs them (Schur product, camera blocks, explicit level-0 S,
+// back-substitution), so a plain step skips those 192 bytes per observation.
 static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const double* pts, const double* uv,
-                    const double* D, ba_stats* st, hipStream_t s) {
+                    const double* D, ba_stats* st, hipStream_t s, bool planes = false) {
   const bool mixed = o->precision == BA_MIXED;
   const uint32_t need = ws_key(o, 0);
   BA_CHECK((P->ws_key & need) == need, BA_ERR_ARG, "internal: the bound workspace does not fit the options");
@@ -1000,7 +1004,8 @@ static void prepare(ba_plan* P, const ba_opts* o, const double* cams, const doub
                      P->errflag.p);
   hipLaunchKernelGGL(k_jacobian_tiles, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
                      P->obs_slot.p, P->obs_cam.p, P->obs_orig.p, P->pt_orig.p, P->campre.p, pts, uv, P->n_obs_pad,
-                     o->lambda, D, P->n_cam, P->F.p, P->E.p, P->fres.p, mixed ? P->F32.p : nullptr,
+                     o->lambda, D, P->n_cam, (planes || !SCHUR_RECOMPUTE) ? P->F.p : nullptr,
+                     (planes || !SCHUR_RECOMPUTE) ? P->E.p : nullptr, P->fres.p, mixed ? P->F32.p : nullptr,
                      mixed ? P->E32.p : nullptr, P->Cinv.p, mixed ? P->Cinv32.p : nullptr, P->vgp.p, P->gp.p,
                      P->Dp.p, P->prec.p, P->n_tiles, o->loss, o->loss_scale, wsq, P->errflag.p);
   hipLaunchKernelGGL(k_camera_blocks, dim3(xcd_grid(P->n_cam)), dim3(256), 0, s, P->cam_off.p, P->cam_obs.p, P->cam_q.p,
@@ -1256,9 +1261,12 @@ static ba_status solve(ba_plan* P, const ba_opts* o, double* delta_cam, double* 
       solve_camera_system(P, o, P->b.p, st, s, o->stop_rule == BA_STOP_NASH_SOFER ? o->forcing : -1.0);
   BA_HIP(hipMemcpyAsync(delta_cam, W.x.p, (size_t)W.n * sizeof(double), hipMemcpyDeviceToDevice, s));
   // back-substitution delta_p = C^-1 (-g_p - W^T delta_c)
+  // (F_o, E_o recomputed from the cameras and point records: the planes may not be written)
   hipLaunchKernelGGL(k_recover_tiles, dim3(xcd_grid(P->n_tiles)), dim3(256), 0, s, P->tile_obs.p, P->tile_pt.p, P->pt_off.p,
-                     P->pt_orig.p, P->obs_cam.p, P->n_obs_pad, P->F.p, P->E.p, P->Cinv.p, P->gp.p, -1.0, W.x.p,
-                     delta_pt, P->n_tiles);
+                     P->pt_orig.p, P->obs_cam.p, P->n_obs_pad, (const double*)nullptr, (const double*)nullptr,
+                     P->obs_pt.p, (const double*)P->campre.p, (const double*)P->prec.p,
+                     P->robust ? (const double*)P->wsq.p : nullptr, P->Cinv.p, P->gp.p, -1.0, W.x.p, delta_pt,
+                     P->n_tiles);
   BA_LAUNCH_CHECK();
   const double t = ts.ms();
   if (st) st->t_solve_ms = t;

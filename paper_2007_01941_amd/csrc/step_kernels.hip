@@ -166,6 +166,8 @@ __device__ __forceinline__ void finish_point(int q, int qo, const double C[6], c
 // and the point record [X | C_p^-1 | v_p] read by the camera-side kernels.
 // With a robust loss (wsq non-null) every observation's rows are scaled by
 // sqrt(rho'(|f_o|^2)), stored in wsq for the kernels that recompute F_o, E_o.
+// F, E may be NULL: the planes are then not written (the step recomputes the
+// blocks where it needs them).
 __global__ __launch_bounds__(256) void k_jacobian_tiles(
     const int32_t* __restrict__ tile_obs, const int32_t* __restrict__ tile_pt,
     const int32_t* __restrict__ pt_off, const uint32_t* __restrict__ obs_slot,
@@ -213,10 +215,12 @@ __global__ __launch_bounds__(256) void k_jacobian_tiles(
     }
     fres[o] = r0;
     fres[stride + o] = r1;
+    if (F) {
 #pragma unroll
-    for (int k = 0; k < 18; ++k) F[k * stride + o] = Fo[k];
+      for (int k = 0; k < 18; ++k) F[k * stride + o] = Fo[k];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) E[k * stride + o] = e[k];
+      for (int k = 0; k < 6; ++k) E[k * stride + o] = e[k];
+    }
     if (F32) {
 #pragma unroll
       for (int k = 0; k < 18; ++k) F32[k * stride + o] = (float)Fo[k];
@@ -454,12 +458,17 @@ __global__ __launch_bounds__(256) void k_cam_FtEv(const int32_t* __restrict__ ca
 // in caller order; r_p is in reordered point order (rp may be NULL for 0). One
 // workgroup per tile of whole points, one thread per observation (coalesced
 // plane reads); per-observation terms are summed per point in order.
+// F == NULL: F_o and E_o are recomputed from the camera (campre) and the
+// point record (prec) with the Jacobian kernel's projection, times the robust
+// weight wsq[o] when wsq is given, instead of read from the planes.
 __global__ __launch_bounds__(256) void k_recover_tiles(
     const int32_t* __restrict__ tile_obs, const int32_t* __restrict__ tile_pt,
     const int32_t* __restrict__ pt_off, const int32_t* __restrict__ pt_orig,
     const int32_t* __restrict__ obs_cam, int64_t stride, const double* __restrict__ F,
-    const double* __restrict__ E, const double* __restrict__ Cinv, const double* __restrict__ rp,
-    double rscale, const double* __restrict__ xc, double* __restrict__ out, int n_tiles) {
+    const double* __restrict__ E, const int32_t* __restrict__ obs_pt, const double* __restrict__ campre,
+    const double* __restrict__ prec, const double* __restrict__ wsq, const double* __restrict__ Cinv,
+    const double* __restrict__ rp, double rscale, const double* __restrict__ xc, double* __restrict__ out,
+    int n_tiles) {
   __shared__ double part[3][TILE_OBS];
   const int t = xcd_block(blockIdx.x, n_tiles);
   if (t >= n_tiles) return;
@@ -467,13 +476,33 @@ __global__ __launch_bounds__(256) void k_recover_tiles(
   const int q0 = tile_pt[t], np = tile_pt[t + 1] - q0;
   double z0 = 0, z1 = 0, z2 = 0;
   for (int o = o0 + threadIdx.x; o < o1; o += TILE_OBS) {
-    const double* xv = xc + (size_t)obs_cam[o] * 9;
+    const int c = obs_cam[o];
+    const double* xv = xc + (size_t)c * 9;
+    double f[18], e[6];
+    if (F) {
+#pragma unroll
+      for (int k = 0; k < 18; ++k) f[k] = F[k * stride + o];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) e[k] = E[k * stride + o];
+    } else {
+      const double* rec = prec + (size_t)obs_pt[o] * PREC;
+      const double X[3] = {rec[0], rec[1], rec[2]};
+      double pi[2], z;
+      project_jacobian(campre + (size_t)c * 24, X, pi, f, e, &z);
+      if (wsq) {
+        const double w = wsq[o];
+#pragma unroll
+        for (int k = 0; k < 18; ++k) f[k] *= w;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) e[k] *= w;
+      }
+    }
     double s0 = 0, s1 = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) { s0 += F[k * stride + o] * xv[k]; s1 += F[(9 + k) * stride + o] * xv[k]; }
-    z0 += E[0 * stride + o] * s0 + E[3 * stride + o] * s1;
-    z1 += E[1 * stride + o] * s0 + E[4 * stride + o] * s1;
-    z2 += E[2 * stride + o] * s0 + E[5 * stride + o] * s1;
+    for (int k = 0; k < 9; ++k) { s0 += f[k] * xv[k]; s1 += f[9 + k] * xv[k]; }
+    z0 += e[0] * s0 + e[3] * s1;
+    z1 += e[1] * s0 + e[4] * s1;
+    z2 += e[2] * s0 + e[5] * s1;
   }
   part[0][threadIdx.x] = z0;
   part[1][threadIdx.x] = z1;
