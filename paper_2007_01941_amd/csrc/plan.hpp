@@ -77,7 +77,7 @@ struct Level {
   DBuf<double> lz_u, lz_v, lz_up, lz_vp, lz_av, lz_dav, lz_w, lz_dw;   // Lanczos vectors
   DBuf<double> lz_s;         // Lanczos scalars: alpha[32], beta[32], norm, b2, count, stop, lambda_max, 1/lambda_max
   DBuf<double> gj_scale;     // coarsest level: equilibration scales
-  DBuf<double> gj_piv;       // coarsest level: inverse of the current 64 x 64 pivot block
+  DBuf<double> gj_piv;       // coarsest level: inverses of the current and next pivot blocks (2 x GJB x GJB)
   DBuf<double> vb, vx, vr, vd, vt, vpart;
   DBuf<float> fb, fx, fr, fd, ft, fpart;   // vpart/fpart: restriction partials (n * NS)
   DBuf<double> vd2, vx2;     // second Chebyshev direction and iterate (fused block-row products)

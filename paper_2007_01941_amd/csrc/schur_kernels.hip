@@ -189,7 +189,15 @@ __global__ __launch_bounds__(256) void k_schur_groups(
     const int slot = (int)(cur.w & 0xffffu), pl = (int)((cur.w >> 16) & 0xffu), rank = (int)(cur.w >> 24);
     T z0 = 0, z1 = 0, z2 = 0;
     if (act) {
-      const T* xv = slot < GROUP_SLOTS ? &xs[slot * 9] : &x[(size_t)grp_cams[gc0 + slot] * 9];
+      T xv[9];
+      if (slot < GROUP_SLOTS) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) xv[k] = xs[slot * 9 + k];
+      } else {
+        const T* xg = &x[(size_t)grp_cams[gc0 + slot] * 9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) xv[k] = xg[k];
+      }
       T s0 = 0, s1 = 0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) { s0 += cur.f[k] * xv[k]; s1 += cur.f[9 + k] * xv[k]; }
@@ -427,8 +435,18 @@ __global__ __launch_bounds__(256, 4) void k_schur_groups_rc(
         for (int k = 0; k < 24; ++k) cpr[k] = cg[k];
       }
       const double X[3] = {xp[pl * 3], xp[pl * 3 + 1], xp[pl * 3 + 2]};
+      // x_c from LDS (or, past the staged slots, global memory), by explicit
+      // branches so that each load uses its own address space
+      T xv[9];
+      if (slot < GROUP_SLOTS) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) xv[k] = xs[slot * 9 + k];
+      } else {
+        const T* xg = &x[(size_t)grp_cams[gc0 + slot] * 9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) xv[k] = xg[k];
+      }
       recompute_blocks<T>(cpr, X, wgt, f, e);
-      const T* xv = slot < GROUP_SLOTS ? &xs[slot * 9] : &x[(size_t)grp_cams[gc0 + slot] * 9];
       T s0 = 0, s1 = 0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) { s0 += f[k] * xv[k]; s1 += f[9 + k] * xv[k]; }
