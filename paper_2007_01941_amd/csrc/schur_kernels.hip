@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void k_schur_groups(
 // weight with a robust loss), per point its record [X | C_p^-1], and per
 // group its cameras' 24 parameters, staged in LDS with x: a few dozen bytes
 // per observation instead of 24 scalars, for the projection's arithmetic
-// (about 100 FP64 operations), which the chip has more of than bandwidth.
+// (about 150 FP64 operations), which the chip has more of than bandwidth.
 // The FP32 form rounds the recomputed blocks exactly as the stored FP32
 // copies are rounded. Otherwise as k_schur_groups.
 constexpr int CPS = 26;   // LDS stride of a camera's parameters (24 used; 16-byte rows)
